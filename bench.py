@@ -1,0 +1,166 @@
+"""Benchmark of the tone-mapping hot path on one MI355X.
+
+A step is one pass of the whole path over one synthetic 4000x3000 WDR image (inputs
+resident in HBM): prologue (Eq. 11 + image statistics), integral image and integral
+histogram (Eq. 5, 8), the fused per-pixel query/blend over all fields (Eq. 1-4), and the
+backward (adjoint of the same path) when it is enabled.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--prec c32x2|f32|f64] [--no-backward]
+                    [--no-cpu-baseline] [--kernel-only query|tables|backward]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "wdr_4000x3000"
+PEAK_HBM_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="c32x2", choices=["c32x2", "f32", "f64"])
+    ap.add_argument("--n-bins", type=int, default=5)
+    ap.add_argument("--n-scales", type=int, default=5)
+    ap.add_argument("--eps", type=float, default=0.1)
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-only", choices=["query", "tables", "backward"], default=None,
+                    help="launch only that stage in the timed loop (profiling runs)")
+    return ap.parse_args()
+
+
+def query_bytes_per_px(prec: str, n_bins: int) -> int:
+    """Algorithmic bytes of the fused query per pixel: luminance in, every table entry read
+    once (interleaved integral image + n-1 cumulative planes), tone value out."""
+    sat = {"f32": 8, "c32x2": 16, "f64": 16}[prec]
+    return 4 + sat + 4 * (n_bins - 1) + 4
+
+
+def cpu_baseline(rgb, params_np):
+    """The oracle, single-threaded, on the full image (about 10-20 s)."""
+    import numpy as np
+
+    import oracle
+    n, s, eps = params_np
+    t0 = time.perf_counter()
+    lum = oracle.luminance(rgb)
+    e = oracle.exact_edges(lum.min(), lum.max(), n)
+    rx, ry = oracle.paper_radii(lum.shape[0], lum.shape[1], s)
+    oracle.forward(lum, e, rx, ry, eps)
+    dt = time.perf_counter() - t0
+    H, W = lum.shape
+    return {"value": round(H * W / dt / 1e6, 4), "unit": "megapixels/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"full {W}x{H} forward (luminance, exact edges, FP64 double-double "
+                       f"tables, per-pixel pass), one thread, {dt:.1f} s")}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "see DESIGN.md for how the path would shard", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2102_01289_amd as tm
+    from synth import WORKLOADS, gen_wdr
+
+    cfg = WORKLOADS[WORKLOAD]
+    H, W = cfg["H"], cfg["W"]
+    img = gen_wdr(H, W, cfg["K"], cfg["lo"], cfg["hi"], cfg["seed"])
+    dev = torch.device("cuda:0")
+    rgb = torch.from_numpy(img.rgb).to(dev)
+    params = tm.make_params(args.n_bins, args.n_scales, eps=args.eps, H=H, W=W)
+    mapper = tm.ToneMapper(H, W, params, args.prec, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        ko = args.kernel_only
+        if ko is None or ko != "query":
+            mapper.prologue(rgb)
+            mapper.tables()
+        if ko is None or ko == "query":
+            if ev is not None:
+                ev[0].record(stream)
+            mapper.query()
+            if ev is not None:
+                ev[1].record(stream)
+
+    # warm-up (also produces the tables a query-only loop reads)
+    mapper.run(rgb)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    q_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+    # per-stage split (outside the timed loop)
+    stage = {}
+    for name, fn in (("prologue", lambda: mapper.prologue(rgb)), ("tables", mapper.tables),
+                     ("query", mapper.query)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(5):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        stage[name] = round(a.elapsed_time(b) / 5, 4)
+
+    mpx = H * W / 1e6
+    qbytes = query_bytes_per_px(args.prec, args.n_bins) * H * W
+    achieved = qbytes / (q_ms * 1e-3) / 1e9
+    line = {
+        "metric": "megapixels/s fwd and fwd+bwd at 12MP vs plain fwd; HBM GB/s fraction",
+        "value": round(mpx / (ms_step * 1e-3), 3),
+        "unit": "megapixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"c32x2": "f32x2", "f32": "f32", "f64": "f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "height": H, "width": W, "n_bins": args.n_bins,
+                   "n_scales": args.n_scales, "eps": args.eps, "sat_precision": args.prec,
+                   "radii_x": list(params.rx[:args.n_scales]),
+                   "radii_y": list(params.ry[:args.n_scales]),
+                   "step": "forward" if args.kernel_only is None else args.kernel_only},
+        "fwd_mp_s": round(mpx / (sum(stage.values()) * 1e-3), 3),
+        "stage_ms": stage,
+        "roofline": {"bound": "hbm", "kernel": "forward_kernel (fused query+blend)",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": qbytes,
+                     "avg_kernel_ms": round(q_ms, 4)},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(img.rgb, (args.n_bins, args.n_scales, args.eps))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * tm.h -- C ABI of the MI355X (gfx950) implementation of multi-receptive-field local tone
+ * mapping with integral images and integral histograms (Yang, Lin, Liu, Shahnovich,
+ * Yadid-Pecht, "Mobile-end Tone Mapping based on Integral Image and Integral Histogram",
+ * arXiv 2102.01289).
+ *
+ * The method (Section II): the luminance image i is compressed to l = log i and split into
+ * n equal-width bins (Eq. 7); an integral histogram (Eq. 8) and integral images of i and
+ * i^2 (Eq. 5) are built once; then every pixel, for each of s receptive fields w_j centred
+ * on it, reads O(1) box queries (Eq. 6, Eq. 9) to get the window histogram's CDF at its own
+ * bin (Eq. 1), a tone value (Eq. 2), the window variance (Eq. 10) and a weight (Eq. 4), and
+ * the per-field tone values are fused by the weights (Eq. 3).
+ *
+ * Conventions shared by every entry point
+ *   - All data pointers are DEVICE pointers owned by the caller (hipMalloc or framework
+ *     tensors).  The library never allocates, frees or keeps caller memory.  Scratch space
+ *     comes from the caller's workspace `ws` of `ws_bytes` bytes; the size an entry point
+ *     needs is returned by the matching tm_*_workspace_bytes function.  ws must be 256-byte
+ *     aligned and is clobbered.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every call only enqueues kernels
+ *     on it and returns without synchronising; no call uses hipMemset, so a sequence of
+ *     calls can be captured into a HIP graph.
+ *   - Images are row-major FP32 with a row pitch `ld_*` counted in elements (ld >= W).
+ *     Pixel (x, y) is column x of row y.
+ *   - Integral tables use one layout ("table layout"): a pointer T0 to the entry of pixel
+ *     (0, 0) and a row pitch ld >= W + 1.  The entry for (x, y) is T0[y*ld + x] for
+ *     -1 <= x < W and -1 <= y < H; the entries with x = -1 or y = -1 are the zero border of
+ *     Eq. 5 (the sums over an empty range).  x = -1 of row y aliases column ld-1 of row y-1,
+ *     which is padding.  The producing call writes every entry of this region, the zeros
+ *     included: row -1 (ld + 1 entries starting at T0 - ld - 1) and the padding columns
+ *     [W, ld) of every row.  tm_table_geometry() returns an ld, the offset of T0 from the
+ *     start of an allocation and the element count to allocate.
+ *   - Every argument is checked on the host before anything is launched; a failed check
+ *     returns a negative tm_status and launches nothing.  HIP launch errors map to
+ *     TM_ERR_HIP.  No C++ exception crosses this interface.
+ *   - Sizes: 1 <= H, W; H*W < 2^31; every table and plane holds < 2^31 entries.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TM_OK = 0,
+    TM_ERR_ARG = -1,          /* null pointer, bad enum, bad parameter value */
+    TM_ERR_SHAPE = -2,        /* H, W, ld or plane stride out of range */
+    TM_ERR_ALIGN = -3,        /* pointer not aligned as documented */
+    TM_ERR_WORKSPACE = -4,    /* ws NULL, misaligned or smaller than required */
+    TM_ERR_HIP = -5,          /* a HIP runtime call failed */
+    TM_ERR_UNSUPPORTED = -6   /* valid request this build does not implement */
+} tm_status;
+
+/* Storage and accumulation of the integral images of i and i^2 (Eq. 5).
+ *   TM_SAT_F32   plain FP32 sums, no offset; entry = float2 {I(i), I(i^2)} (8 bytes).
+ *   TM_SAT_C32X2 sums of (i - mu1) and (i^2 - mu2) accumulated with compensated FP32
+ *                (TwoSum) arithmetic and stored as unevaluated pairs hi + lo;
+ *                entry = float4 {I1.hi, I1.lo, I2.hi, I2.lo} (16 bytes).  mu1, mu2 are
+ *                the FP32 offsets from tm_image_stats (the image means of i and i^2).
+ *   TM_SAT_F64   plain FP64 sums, no offset; entry = double2 {I(i), I(i^2)} (16 bytes). */
+typedef enum { TM_SAT_F32 = 0, TM_SAT_C32X2 = 1, TM_SAT_F64 = 2 } tm_sat_prec;
+
+/* Integral-histogram planes (Eq. 8), uint32 each, in the table layout.
+ *   TM_HIST_PER_BIN     n planes H_k, k = 0..n-1: counts of pixels in bin k (Eq. 8).
+ *   TM_HIST_CUMULATIVE  n-1 planes G_k, k = 1..n-1: counts of pixels in bins below k,
+ *                       G_k = sum_{j<k} H_j.  The CDF of Eq. 1 at a pixel of bin b is then
+ *                       one box query on G_b (G_0 = 0 is not stored).
+ * Plane p (0-based) starts at hist + p * plane_stride. */
+typedef enum { TM_HIST_PER_BIN = 0, TM_HIST_CUMULATIVE = 1 } tm_hist_layout;
+
+#define TM_MAX_SCALES 8
+#define TM_MAX_BINS 256
+
+/* Method parameters (Section II-C).  Paper setting: n = 5, s = 5, eps = 0.1 (Section IV),
+ * radii halving from the image size (tm_paper_radii), display range [0, 1].
+ *   n_bins   n, 1..256 (number of equal-width log-luminance bins, Eq. 7)
+ *   n_scales s, 1..8   (number of receptive fields, Eq. 3)
+ *   rx, ry   per-field half-widths >= 0; field j covers x-(rx+1) < x' <= x+rx and the same
+ *            in y (Algorithm 1), clamped to the image
+ *   eps      the regulariser of Eq. 4, > 0, in units of luminance squared
+ *   ld_min, ld_max  display luminance range of Eq. 2, ld_max > ld_min */
+typedef struct {
+    int32_t n_bins;
+    int32_t n_scales;
+    int32_t rx[TM_MAX_SCALES];
+    int32_t ry[TM_MAX_SCALES];
+    float eps;
+    float ld_min;
+    float ld_max;
+} tm_params;
+
+/* Scan tiling (chosen by the autotuner; NULL anywhere means the built-in default).
+ *   tile_w_vec  columns per lane of one 64-lane tile: 1, 2, 4 or 8 (tile width 64*vec)
+ *   tile_h      rows per tile, 1..256
+ *   bin_chunk   histogram planes accumulated per pass over the image tile: 2, 4 or 8 */
+typedef struct {
+    int32_t tile_w_vec;
+    int32_t tile_h;
+    int32_t bin_chunk;
+} tm_tune;
+
+const char *tm_status_string(tm_status s);
+
+/* Radii of the receptive-field pyramid (Section II-C): the largest field is the image and
+ * each next one is half as wide, rx[j] = W >> (j+1), ry[j] = H >> (j+1) for j < n_scales.
+ * Host function; fills p->rx, p->ry only. */
+tm_status tm_paper_radii(int32_t H, int32_t W, tm_params *p);
+
+/* Table layout helper (host): for an H x W image returns the row pitch ld (elements, a
+ * multiple of 64, >= W + 1), the offset in elements of T0 from the start of an allocation
+ * (a multiple of 64, >= ld + 1) and the elements one table or plane needs (origin offset +
+ * H * ld, rounded up to 64).  Use the same element count as the plane stride. */
+tm_status tm_table_geometry(int32_t H, int32_t W, int64_t *ld, int64_t *origin_offset,
+                            int64_t *elems);
+
+/* ---------------------------------------------------------------- stage a1: prologue */
+
+/* Luminance (Section III, Eq. 11): i = 0.2126 R + 0.7152 G + 0.0722 B from planar FP32
+ * RGB (channel c of pixel (x, y) at rgb[c*ch_stride + y*ld_rgb + x]).  Evaluated in FP32
+ * left to right with fused multiply-adds, i = fma(0.0722, B, fma(0.7152, G, 0.2126*R)).
+ * lum: H x W, pitch ld_lum.  No workspace. */
+tm_status tm_luminance(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                       int32_t W, float *lum, int64_t ld_lum, void *stream);
+
+/* Image statistics the later stages need, in one reduction over lum:
+ *   edges[0..n_bins-2] (FP32, device): bin edges of n_bins equal-width bins of log i over
+ *       [log i_min, log i_max] (Section II-A, Eq. 7).  Edge k sits at the real number
+ *       e_k = i_min^(1-k/n) i_max^(k/n); the stored value is the smallest FP32 >= e_k, so
+ *       `i >= edges[k-1]` decides bin >= k exactly.  i_min is floored at the smallest
+ *       normal FP32.  If i_max <= i_min all edges are +inf.  n_bins = 1 writes nothing.
+ *   offsets[2] (FP32, device, nullable): {mu1, mu2} = FP32-rounded means of i and i^2
+ *       (FP64 sums), the offsets of TM_SAT_C32X2 tables.
+ *   minmax[2] (FP32, device, nullable): {min i, max i}.
+ * Deterministic (fixed reduction order).  Workspace: tm_image_stats_workspace_bytes. */
+size_t tm_image_stats_workspace_bytes(int32_t H, int32_t W);
+tm_status tm_image_stats(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                         int32_t n_bins, float *edges, float *offsets, float *minmax,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* Eq. 11 and the statistics above fused in one pass over the RGB image. */
+tm_status tm_prologue(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                      int32_t W, int32_t n_bins, float *lum, int64_t ld_lum, float *edges,
+                      float *offsets, float *minmax, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- stages a2, a3: tables */
+
+/* Integral images (Eq. 5) of v and v^2 in one interleaved table (entry type per
+ * tm_sat_prec), table layout, pitch ld_sat.  offsets: device float[2] for TM_SAT_C32X2
+ * (required), ignored otherwise.  Workspace: tm_tables_workspace_bytes. */
+tm_status tm_integral_image(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                            tm_sat_prec prec, const float *offsets, void *sat,
+                            int64_t ld_sat, const tm_tune *tune, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* Integral histogram (Eq. 7-8) of v's bins under `edges` (as from tm_image_stats), uint32
+ * planes in the table layout.  Counts are exact.  Workspace: tm_tables_workspace_bytes. */
+tm_status tm_integral_histogram(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                const float *edges, int32_t n_bins, tm_hist_layout layout,
+                                uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
+                                const tm_tune *tune, void *ws, size_t ws_bytes,
+                                void *stream);
+
+/* Both tables in one pass over v (sat or hist may be NULL to skip that table). */
+tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                             tm_sat_prec prec, const float *offsets, void *sat,
+                             int64_t ld_sat, const float *edges, int32_t n_bins,
+                             tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,
+                             int64_t plane_stride, const tm_tune *tune, void *ws,
+                             size_t ws_bytes, void *stream);
+
+size_t tm_tables_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_sat_prec prec,
+                                 const tm_tune *tune);
+
+/* ---------------------------------------------------------------- stage a4: forward */
+
+/* Tone-mapped luminance (Eq. 1-4, 6, 9, 10 and the fusion of Eq. 3) of v, from its
+ * integral images `sat` (precision prec, offsets as used to build it) and its cumulative
+ * integral histogram `hist_cum` (n_bins-1 planes, may be NULL when n_bins = 1).
+ * For each pixel p and field j: the clamped window (Algorithm 1's corners), its pixel
+ * count N, S1 = sum v and S2 = sum v^2 (Eq. 6), the count c of window pixels in bins below
+ * p's bin (Eq. 9 summed as in Eq. 1, one query on G_b), P = c/N (Eq. 1; the histogram
+ * total equals N), L_j = ld_min + (ld_max - ld_min) P (Eq. 2), var = max(0, S2/N -
+ * (S1/N)^2) (Eq. 10 as the population variance), W_j = var/(var + eps) (Eq. 4); then
+ * L = sum W_j L_j / sum W_j (Eq. 3), or the mean of the L_j where every W_j = 0.
+ * out: FP32 H x W, pitch ld_out.  No workspace.  One launch for all fields. */
+tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                             const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                             const float *offsets, const uint32_t *hist_cum, int64_t ld_hist,
+                             int64_t plane_stride, const float *edges, const tm_params *p,
+                             float *out, int64_t ld_out, void *stream);
+
+/* ---------------------------------------------------------------- stage a5: backward */
+
+/* Gradient of sum_p g(p) L(p) (g = grad_out) with respect to v and to (eps, ld_min,
+ * ld_max), from the same tables the forward read.  The histogram terms are piecewise
+ * constant in v and the bin edges are held fixed, so v enters only through the window
+ * variances: with D = sum_j W_j and a_j = g (L_j - L)/D eps/(var_j + eps)^2 (zero where
+ * var_j was clamped or D = 0),
+ *   dv(q) = sum_j sum_{p: q in w_j(p)} (-2 a_j S1_j/N_j^2 + 2 v(q) a_j/N_j),
+ * evaluated by depositing the per-pixel coefficients at the window corners and taking two
+ * reverse (suffix) 2-D scans.  grad_v: FP32 H x W, pitch ld_gv.  grad_params: device
+ * double[3] = {d/d eps, d/d ld_min, d/d ld_max}, deterministic.
+ * Workspace: tm_backward_workspace_bytes. */
+size_t tm_backward_workspace_bytes(int32_t H, int32_t W, const tm_params *p);
+tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                              const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                              const float *offsets, const uint32_t *hist_cum,
+                              int64_t ld_hist, int64_t plane_stride, const float *edges,
+                              const tm_params *p, const float *grad_out, int64_t ld_g,
+                              float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
+                              size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TM_H */

@@ -1,0 +1,339 @@
+"""MI355X (gfx950) multi-receptive-field local tone mapping with integral images and
+integral histograms (arXiv 2102.01289), behind a C ABI (include/tm.h).
+
+This module is the thin Python binding: it marshals torch device tensors into the C entry
+points of the same names and allocates outputs.  Every step of the method runs in the HIP
+kernels of libtm355.so; there is no host or PyTorch fallback, and a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _capi
+
+__all__ = [
+    "TmError", "Table", "table_geometry", "paper_radii", "make_params", "tune",
+    "tm_luminance", "tm_image_stats", "tm_prologue", "tm_integral_image",
+    "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
+    "tm_tonemap_backward", "ToneMapper", "tonemap",
+]
+
+
+class TmError(RuntimeError):
+    def __init__(self, name: str, status: int):
+        self.status = status
+        msg = _capi.load().tm_status_string(status).decode()
+        super().__init__(f"{name}: {_capi.STATUS.get(status, status)} ({msg})")
+
+
+def _ck(name: str, status: int) -> None:
+    if status != 0:
+        raise TmError(name, status)
+
+
+def _lib():
+    return _capi.load()
+
+
+def _vp(t) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(0)
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _img(t: torch.Tensor, name: str):
+    if t.dtype != torch.float32 or t.dim() != 2 or t.stride(1) != 1 or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA float32 [H, W] tensor with unit column stride")
+    return t.shape[0], t.shape[1], t.stride(0)
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------------ parameters
+def table_geometry(H: int, W: int):
+    ld, org, el = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _ck("tm_table_geometry", _lib().tm_table_geometry(H, W, ctypes.byref(ld), ctypes.byref(org),
+                                                       ctypes.byref(el)))
+    return ld.value, org.value, el.value
+
+
+def paper_radii(H: int, W: int, s: int):
+    p = _capi.TmParams()
+    p.n_scales = s
+    _ck("tm_paper_radii", _lib().tm_paper_radii(H, W, ctypes.byref(p)))
+    return list(p.rx[:s]), list(p.ry[:s])
+
+
+def make_params(n_bins: int = 5, n_scales: int = 5, rx=None, ry=None, eps: float = 0.1,
+                ld_min: float = 0.0, ld_max: float = 1.0, H: int | None = None,
+                W: int | None = None) -> _capi.TmParams:
+    """tm_params; radii default to the paper's pyramid for an H x W image."""
+    p = _capi.TmParams()
+    p.n_bins = n_bins
+    p.n_scales = n_scales
+    if rx is None or ry is None:
+        if H is None or W is None:
+            raise ValueError("give rx, ry or the image size H, W")
+        rx, ry = paper_radii(H, W, n_scales)
+    if len(rx) != n_scales or len(ry) != n_scales:
+        raise ValueError("rx, ry must have n_scales entries")
+    for j in range(n_scales):
+        p.rx[j] = int(rx[j])
+        p.ry[j] = int(ry[j])
+    p.eps = eps
+    p.ld_min = ld_min
+    p.ld_max = ld_max
+    return p
+
+
+def tune(tile_w_vec: int, tile_h: int, bin_chunk: int) -> _capi.TmTune:
+    return _capi.TmTune(tile_w_vec, tile_h, bin_chunk)
+
+
+# ------------------------------------------------------------------------ tables
+_KIND = {"f32": (2, torch.float32), "c32x2": (4, torch.float32), "f64": (2, torch.float64),
+         "u32": (1, torch.uint32)}
+
+
+class Table:
+    """One or more integral tables of an H x W image in the library's table layout
+    (origin pointer, row pitch ld >= W+1, zero row -1 and column -1), on a CUDA device."""
+
+    def __init__(self, H: int, W: int, kind: str, planes: int = 1, device="cuda"):
+        comps, dtype = _KIND[kind]
+        self.H, self.W, self.kind, self.planes, self.comps = H, W, kind, planes, comps
+        self.ld, self.origin, self.elems = table_geometry(H, W)
+        self.buf = torch.empty(max(planes, 1) * self.elems * comps, dtype=dtype, device=device)
+        self.itemsize = self.buf.element_size() * comps
+        self.plane_stride = self.elems
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr() + self.origin * self.itemsize
+
+    def padded(self) -> torch.Tensor:
+        """[planes, H+1, W+1, comps] with entry [p, y+1, x+1] = T_p(x, y) and the zero
+        border at index 0 -- the oracle's layout -- copied to the host."""
+        b = self.buf.view(max(self.planes, 1), self.elems, self.comps)
+        lo = self.origin - self.ld
+        rows = b[:, lo:lo + (self.H + 1) * self.ld].reshape(-1, self.H + 1, self.ld, self.comps)
+        out = torch.empty((rows.shape[0], self.H + 1, self.W + 1, self.comps), dtype=b.dtype)
+        r = rows.cpu()
+        out[:, :, 1:] = r[:, :, :self.W]
+        out[:, 1:, 0] = r[:, :-1, self.ld - 1]          # x = -1 of row y is column ld-1 of row y-1
+        out[:, 0, 0] = b[:, lo - 1].cpu()               # (x, y) = (-1, -1)
+        return out
+
+    def raw_region(self) -> torch.Tensor:
+        """Everything the producing call must write: [planes, (H+1)*ld + 1, comps]."""
+        b = self.buf.view(max(self.planes, 1), self.elems, self.comps)
+        lo = self.origin - self.ld - 1
+        return b[:, lo:self.origin + self.H * self.ld]
+
+
+# ------------------------------------------------------------------------ entry points
+def tm_luminance(rgb: torch.Tensor, lum: torch.Tensor | None = None, stream=None):
+    """Eq. 11 on planar float32 RGB [3, H, W] (CUDA) -> luminance [H, W]."""
+    if rgb.dtype != torch.float32 or rgb.dim() != 3 or rgb.shape[0] != 3 or rgb.stride(2) != 1:
+        raise ValueError("rgb must be float32 [3, H, W] with unit column stride")
+    _, H, W = rgb.shape
+    if lum is None:
+        lum = torch.empty((H, W), dtype=torch.float32, device=rgb.device)
+    _ck("tm_luminance", _lib().tm_luminance(_vp(rgb), rgb.stride(0), rgb.stride(1), H, W,
+                                            _vp(lum), lum.stride(0), _stream(stream)))
+    return lum
+
+
+def tm_image_stats(lum: torch.Tensor, n_bins: int, stream=None):
+    """(edges [n_bins-1], offsets [2], minmax [2]) of a luminance image."""
+    H, W, ld = _img(lum, "lum")
+    dev = lum.device
+    edges = torch.empty(max(n_bins - 1, 1), dtype=torch.float32, device=dev)
+    offsets = torch.empty(2, dtype=torch.float32, device=dev)
+    minmax = torch.empty(2, dtype=torch.float32, device=dev)
+    nb = _lib().tm_image_stats_workspace_bytes(H, W)
+    ws = _ws(nb, dev)
+    _ck("tm_image_stats", _lib().tm_image_stats(_vp(lum), ld, H, W, n_bins, _vp(edges),
+                                                _vp(offsets), _vp(minmax), _vp(ws), ws.numel(),
+                                                _stream(stream)))
+    return edges[:n_bins - 1], offsets, minmax
+
+
+def tm_prologue(rgb: torch.Tensor, n_bins: int, stream=None):
+    """Eq. 11 and the image statistics in one pass: (lum, edges, offsets, minmax)."""
+    _, H, W = rgb.shape
+    dev = rgb.device
+    lum = torch.empty((H, W), dtype=torch.float32, device=dev)
+    edges = torch.empty(max(n_bins - 1, 1), dtype=torch.float32, device=dev)
+    offsets = torch.empty(2, dtype=torch.float32, device=dev)
+    minmax = torch.empty(2, dtype=torch.float32, device=dev)
+    ws = _ws(_lib().tm_image_stats_workspace_bytes(H, W), dev)
+    _ck("tm_prologue", _lib().tm_prologue(_vp(rgb), rgb.stride(0), rgb.stride(1), H, W, n_bins,
+                                          _vp(lum), lum.stride(0), _vp(edges), _vp(offsets),
+                                          _vp(minmax), _vp(ws), ws.numel(), _stream(stream)))
+    return lum, edges[:n_bins - 1], offsets, minmax
+
+
+def _tune_ref(t):
+    return ctypes.byref(t) if t is not None else None
+
+
+def tm_integral_tables(v: torch.Tensor, prec: str | None = "c32x2", offsets=None, edges=None,
+                       n_bins: int = 5, layout: str | None = "cumulative", tune=None,
+                       stream=None, sat: Table | None = None, hist: Table | None = None):
+    """Integral image (prec, or None to skip) and integral histogram (layout, or None to
+    skip) of v in one pass.  Returns (sat Table | None, hist Table | None); preallocated
+    tables may be passed in."""
+    H, W, ld = _img(v, "v")
+    dev = v.device
+    if sat is None and prec is not None:
+        sat = Table(H, W, prec, 1, dev)
+    if hist is None and layout is not None:
+        planes = n_bins if layout == "per_bin" else n_bins - 1
+        hist = Table(H, W, "u32", planes, dev) if planes > 0 else None
+    if sat is None and hist is None:
+        return None, None
+    pcode = _capi.SAT_PREC[prec] if prec is not None else 0
+    nbytes = _lib().tm_tables_workspace_bytes(H, W, n_bins, pcode, _tune_ref(tune))
+    ws = _ws(nbytes, dev)
+    st = _lib().tm_integral_tables(
+        _vp(v), ld, H, W, pcode, _vp(offsets), _vp(sat.ptr if sat else None),
+        sat.ld if sat else 0, _vp(edges), n_bins, _capi.HIST_LAYOUT[layout or "cumulative"],
+        _vp(hist.ptr if hist else None), hist.ld if hist else 0,
+        hist.plane_stride if hist else 0, _tune_ref(tune), _vp(ws), ws.numel(), _stream(stream))
+    _ck("tm_integral_tables", st)
+    return sat, hist
+
+
+def tm_integral_image(v, prec="c32x2", offsets=None, tune=None, stream=None) -> Table:
+    H, W, ld = _img(v, "v")
+    sat = Table(H, W, prec, 1, v.device)
+    pcode = _capi.SAT_PREC[prec]
+    ws = _ws(_lib().tm_tables_workspace_bytes(H, W, 1, pcode, _tune_ref(tune)), v.device)
+    _ck("tm_integral_image", _lib().tm_integral_image(
+        _vp(v), ld, H, W, pcode, _vp(offsets), _vp(sat.ptr), sat.ld, _tune_ref(tune), _vp(ws),
+        ws.numel(), _stream(stream)))
+    return sat
+
+
+def tm_integral_histogram(v, edges, n_bins: int, layout="cumulative", tune=None,
+                          stream=None) -> Table:
+    H, W, ld = _img(v, "v")
+    planes = n_bins if layout == "per_bin" else n_bins - 1
+    hist = Table(H, W, "u32", planes, v.device)
+    ws = _ws(_lib().tm_tables_workspace_bytes(H, W, n_bins, 0, _tune_ref(tune)), v.device)
+    _ck("tm_integral_histogram", _lib().tm_integral_histogram(
+        _vp(v), ld, H, W, _vp(edges), n_bins, _capi.HIST_LAYOUT[layout], _vp(hist.ptr),
+        hist.ld, hist.plane_stride, _tune_ref(tune), _vp(ws), ws.numel(), _stream(stream)))
+    return hist
+
+
+def tm_tonemap_forward(v, sat: Table, hist: Table | None, edges, params, offsets=None,
+                       out=None, stream=None):
+    """Fused per-pixel query and blend (Eq. 1-4, 6, 9, 10, fusion Eq. 3) -> L [H, W]."""
+    H, W, ld = _img(v, "v")
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=v.device)
+    _ck("tm_tonemap_forward", _lib().tm_tonemap_forward(
+        _vp(v), ld, H, W, _vp(sat.ptr), sat.ld, _capi.SAT_PREC[sat.kind], _vp(offsets),
+        _vp(hist.ptr if hist else None), hist.ld if hist else 0,
+        hist.plane_stride if hist else 0, _vp(edges), ctypes.byref(params), _vp(out),
+        out.stride(0), _stream(stream)))
+    return out
+
+
+def tm_tonemap_backward(v, sat: Table, hist: Table | None, edges, params, grad_out,
+                        offsets=None, stream=None):
+    """(grad_v [H, W] float32, grad_params [3] float64 = d/d(eps, ld_min, ld_max))."""
+    H, W, ld = _img(v, "v")
+    _, _, ldg = _img(grad_out, "grad_out")
+    gv = torch.empty((H, W), dtype=torch.float32, device=v.device)
+    gp = torch.empty(3, dtype=torch.float64, device=v.device)
+    nb = _lib().tm_backward_workspace_bytes(H, W, ctypes.byref(params))
+    ws = _ws(nb, v.device)
+    _ck("tm_tonemap_backward", _lib().tm_tonemap_backward(
+        _vp(v), ld, H, W, _vp(sat.ptr), sat.ld, _capi.SAT_PREC[sat.kind], _vp(offsets),
+        _vp(hist.ptr if hist else None), hist.ld if hist else 0,
+        hist.plane_stride if hist else 0, _vp(edges), ctypes.byref(params), _vp(grad_out), ldg,
+        _vp(gv), gv.stride(0), _vp(gp), _vp(ws), ws.numel(), _stream(stream)))
+    return gv, gp
+
+
+# ------------------------------------------------------------------------ pipeline
+@dataclass
+class Stage:
+    lum: torch.Tensor
+    edges: torch.Tensor
+    offsets: torch.Tensor
+    minmax: torch.Tensor
+    sat: Table
+    hist: Table | None
+    out: torch.Tensor
+
+
+class ToneMapper:
+    """Preallocated forward path for one image shape: prologue (Eq. 11 + statistics),
+    integral tables (Eq. 5, 8), fused query (Eq. 1-4).  All buffers and workspaces are
+    allocated once so that run() only enqueues kernels (capturable in a HIP graph)."""
+
+    def __init__(self, H: int, W: int, params, prec: str = "c32x2", tune=None,
+                 device="cuda"):
+        self.H, self.W, self.params, self.prec, self.tune = H, W, params, prec, tune
+        n = params.n_bins
+        dev = torch.device(device)
+        self.lum = torch.empty((H, W), dtype=torch.float32, device=dev)
+        self.edges = torch.empty(max(n - 1, 1), dtype=torch.float32, device=dev)
+        self.offsets = torch.empty(2, dtype=torch.float32, device=dev)
+        self.minmax = torch.empty(2, dtype=torch.float32, device=dev)
+        self.sat = Table(H, W, prec, 1, dev)
+        self.hist = Table(H, W, "u32", n - 1, dev) if n > 1 else None
+        self.out = torch.empty((H, W), dtype=torch.float32, device=dev)
+        self.ws_stats = _ws(_lib().tm_image_stats_workspace_bytes(H, W), dev)
+        self.ws_tab = _ws(_lib().tm_tables_workspace_bytes(H, W, n, _capi.SAT_PREC[prec],
+                                                            _tune_ref(tune)), dev)
+        self.tune_ref = _tune_ref(tune)
+
+    def prologue(self, rgb, stream=None):
+        _ck("tm_prologue", _lib().tm_prologue(
+            _vp(rgb), rgb.stride(0), rgb.stride(1), self.H, self.W, self.params.n_bins,
+            _vp(self.lum), self.lum.stride(0), _vp(self.edges), _vp(self.offsets),
+            _vp(self.minmax), _vp(self.ws_stats), self.ws_stats.numel(), _stream(stream)))
+
+    def tables(self, stream=None):
+        h = self.hist
+        _ck("tm_integral_tables", _lib().tm_integral_tables(
+            _vp(self.lum), self.lum.stride(0), self.H, self.W, _capi.SAT_PREC[self.prec],
+            _vp(self.offsets), _vp(self.sat.ptr), self.sat.ld, _vp(self.edges),
+            self.params.n_bins, 1, _vp(h.ptr if h else None), h.ld if h else 0,
+            h.plane_stride if h else 0, self.tune_ref, _vp(self.ws_tab), self.ws_tab.numel(),
+            _stream(stream)))
+
+    def query(self, stream=None):
+        tm_tonemap_forward(self.lum, self.sat, self.hist, self.edges, self.params,
+                           self.offsets, self.out, stream)
+
+    def run(self, rgb, stream=None) -> torch.Tensor:
+        self.prologue(rgb, stream)
+        self.tables(stream)
+        self.query(stream)
+        return self.out
+
+
+def tonemap(rgb: torch.Tensor, n_bins: int = 5, n_scales: int = 5, eps: float = 0.1,
+            prec: str = "c32x2", ld_min: float = 0.0, ld_max: float = 1.0) -> torch.Tensor:
+    """Tone-mapped luminance of one planar RGB image with the paper's parameter set."""
+    _, H, W = rgb.shape
+    p = make_params(n_bins, n_scales, eps=eps, ld_min=ld_min, ld_max=ld_max, H=H, W=W)
+    return ToneMapper(H, W, p, prec, device=rgb.device).run(rgb).clone()

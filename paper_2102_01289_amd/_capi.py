@@ -1,0 +1,79 @@
+"""ctypes declarations of the C ABI in include/tm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtm355.so")
+
+TM_MAX_SCALES = 8
+TM_MAX_BINS = 256
+
+STATUS = {0: "TM_OK", -1: "TM_ERR_ARG", -2: "TM_ERR_SHAPE", -3: "TM_ERR_ALIGN",
+          -4: "TM_ERR_WORKSPACE", -5: "TM_ERR_HIP", -6: "TM_ERR_UNSUPPORTED"}
+
+SAT_PREC = {"f32": 0, "c32x2": 1, "f64": 2}
+HIST_LAYOUT = {"per_bin": 0, "cumulative": 1}
+
+
+class TmParams(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("n_scales", ctypes.c_int32),
+                ("rx", ctypes.c_int32 * TM_MAX_SCALES), ("ry", ctypes.c_int32 * TM_MAX_SCALES),
+                ("eps", ctypes.c_float), ("ld_min", ctypes.c_float), ("ld_max", ctypes.c_float)]
+
+
+class TmTune(ctypes.Structure):
+    _fields_ = [("tile_w_vec", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("bin_chunk", ctypes.c_int32)]
+
+
+# (name, restype, argtypes) for every entry point of include/tm.h
+P, I32, I64, SZ, F, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t,
+                         ctypes.c_float, ctypes.c_double)
+PP = ctypes.POINTER(TmParams)
+PT = ctypes.POINTER(TmTune)
+PI64 = ctypes.POINTER(ctypes.c_int64)
+
+SIGNATURES = {
+    "tm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "tm_paper_radii": (ctypes.c_int, [I32, I32, PP]),
+    "tm_table_geometry": (ctypes.c_int, [I32, I32, PI64, PI64, PI64]),
+    "tm_luminance": (ctypes.c_int, [P, I64, I64, I32, I32, P, I64, P]),
+    "tm_image_stats_workspace_bytes": (SZ, [I32, I32]),
+    "tm_image_stats": (ctypes.c_int, [P, I64, I32, I32, I32, P, P, P, P, SZ, P]),
+    "tm_prologue": (ctypes.c_int, [P, I64, I64, I32, I32, I32, P, I64, P, P, P, P, SZ, P]),
+    "tm_integral_image": (ctypes.c_int, [P, I64, I32, I32, ctypes.c_int, P, P, I64, PT, P, SZ,
+                                         P]),
+    "tm_integral_histogram": (ctypes.c_int, [P, I64, I32, I32, P, I32, ctypes.c_int, P, I64,
+                                             I64, PT, P, SZ, P]),
+    "tm_integral_tables": (ctypes.c_int, [P, I64, I32, I32, ctypes.c_int, P, P, I64, P, I32,
+                                          ctypes.c_int, P, I64, I64, PT, P, SZ, P]),
+    "tm_tables_workspace_bytes": (SZ, [I32, I32, I32, ctypes.c_int, PT]),
+    "tm_tonemap_forward": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
+                                          I64, P, PP, P, I64, P]),
+    "tm_backward_workspace_bytes": (SZ, [I32, I32, PP]),
+    "tm_tonemap_backward": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
+                                           I64, P, PP, P, I64, P, I64, P, P, SZ, P]),
+}
+
+_LIB = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree HIP library.  Raises if it has not been built: there is no
+    fallback path."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library {LIB_PATH} is missing; build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'` or "
+                "`python paper_2102_01289_amd/build.py`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB

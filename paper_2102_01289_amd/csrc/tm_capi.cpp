@@ -1,0 +1,313 @@
+// tm_capi.cpp -- the C ABI declared in include/tm.h: host-side argument checks, workspace
+// sizing and kernel dispatch.  Nothing here computes on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/tm.h"
+#include "tm_internal.h"
+
+using namespace tmo;
+
+namespace {
+
+constexpr int64_t kMaxEntries = (int64_t)1 << 31;
+
+bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+tm_status check_image(int32_t H, int32_t W) {
+    if (H < 1 || W < 1) return TM_ERR_SHAPE;
+    if ((int64_t)H * W >= kMaxEntries) return TM_ERR_SHAPE;
+    return TM_OK;
+}
+
+tm_status check_plane(int32_t H, int32_t W, int64_t ld) {
+    if (ld < W) return TM_ERR_SHAPE;
+    if ((int64_t)H * ld >= kMaxEntries) return TM_ERR_SHAPE;
+    return TM_OK;
+}
+
+// A table in the documented layout: ld >= W+1, ld % 4 == 0, < 2^31 entries incl. border.
+tm_status check_table(int32_t H, int32_t W, int64_t ld, const void *t0) {
+    if (ld < (int64_t)W + 1 || ld % 4 != 0) return TM_ERR_SHAPE;
+    if (((int64_t)H + 1) * ld + 1 >= kMaxEntries) return TM_ERR_SHAPE;
+    if (!t0) return TM_ERR_ARG;
+    if (!aligned(t0, 16)) return TM_ERR_ALIGN;
+    return TM_OK;
+}
+
+tm_status check_hist(int32_t H, int32_t W, int64_t ld, int64_t stride, const void *h,
+                     int planes) {
+    tm_status s = check_table(H, W, ld, h);
+    if (s != TM_OK) return s;
+    if (planes > 1) {
+        if (stride < ((int64_t)H + 1) * ld + 1 || stride % 4 != 0) return TM_ERR_SHAPE;
+        if (stride * (planes - 1) + (int64_t)H * ld >= ((int64_t)1 << 40)) return TM_ERR_SHAPE;
+    }
+    return TM_OK;
+}
+
+tm_status check_ws(void *ws, size_t have, size_t need) {
+    if (need == 0) return TM_OK;
+    if (!ws) return TM_ERR_WORKSPACE;
+    if (!aligned(ws, 256)) return TM_ERR_WORKSPACE;
+    if (have < need) return TM_ERR_WORKSPACE;
+    return TM_OK;
+}
+
+tm_status check_params(const tm_params *p) {
+    if (!p) return TM_ERR_ARG;
+    if (p->n_bins < 1 || p->n_bins > TM_MAX_BINS) return TM_ERR_ARG;
+    if (p->n_scales < 1 || p->n_scales > TM_MAX_SCALES) return TM_ERR_ARG;
+    for (int j = 0; j < p->n_scales; ++j)
+        if (p->rx[j] < 0 || p->ry[j] < 0) return TM_ERR_ARG;
+    if (!(p->eps > 0.f) || !std::isfinite(p->eps)) return TM_ERR_ARG;
+    if (!std::isfinite(p->ld_min) || !std::isfinite(p->ld_max) || !(p->ld_max > p->ld_min))
+        return TM_ERR_ARG;
+    return TM_OK;
+}
+
+bool valid_prec(int prec) { return prec == TM_SAT_F32 || prec == TM_SAT_C32X2 || prec == TM_SAT_F64; }
+
+tm_status from_hip(hipError_t e) { return e == hipSuccess ? TM_OK : TM_ERR_HIP; }
+
+ScanTune resolve_tune(const tm_tune *t, int H, int W, tm_status *st) {
+    *st = TM_OK;
+    if (!t) return scan_tune_default(H, W);
+    ScanTune r{t->tile_w_vec, t->tile_h, t->bin_chunk};
+    if (!scan_tune_valid(r)) *st = TM_ERR_ARG;
+    return r;
+}
+
+size_t round256(size_t a) { return (a + 255) / 256 * 256; }
+
+#define TM_TRY(expr)                      \
+    do {                                  \
+        tm_status _s = (expr);            \
+        if (_s != TM_OK) return _s;       \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char *tm_status_string(tm_status s) {
+    switch (s) {
+        case TM_OK: return "ok";
+        case TM_ERR_ARG: return "invalid argument";
+        case TM_ERR_SHAPE: return "invalid shape, pitch or stride";
+        case TM_ERR_ALIGN: return "misaligned pointer";
+        case TM_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        case TM_ERR_HIP: return "HIP runtime error";
+        case TM_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+tm_status tm_paper_radii(int32_t H, int32_t W, tm_params *p) {
+    if (!p) return TM_ERR_ARG;
+    TM_TRY(check_image(H, W));
+    if (p->n_scales < 1 || p->n_scales > TM_MAX_SCALES) return TM_ERR_ARG;
+    for (int j = 0; j < p->n_scales; ++j) {
+        p->rx[j] = W >> (j + 1);
+        p->ry[j] = H >> (j + 1);
+    }
+    return TM_OK;
+}
+
+tm_status tm_table_geometry(int32_t H, int32_t W, int64_t *ld, int64_t *origin_offset,
+                            int64_t *elems) {
+    TM_TRY(check_image(H, W));
+    const int64_t l = ((int64_t)W + 1 + 63) / 64 * 64;
+    const int64_t o = (l + 1 + 63) / 64 * 64;
+    const int64_t e = (o + (int64_t)H * l + 63) / 64 * 64;
+    if (e >= kMaxEntries) return TM_ERR_SHAPE;
+    if (ld) *ld = l;
+    if (origin_offset) *origin_offset = o;
+    if (elems) *elems = e;
+    return TM_OK;
+}
+
+// ------------------------------------------------------------------ a1
+tm_status tm_luminance(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                       int32_t W, float *lum, int64_t ld_lum, void *stream) {
+    TM_TRY(check_image(H, W));
+    if (!rgb || !lum) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_rgb));
+    TM_TRY(check_plane(H, W, ld_lum));
+    if (ch_stride < (int64_t)H * ld_rgb) return TM_ERR_SHAPE;
+    return from_hip(launch_luminance(rgb, ch_stride, ld_rgb, H, W, lum, ld_lum,
+                                     (hipStream_t)stream));
+}
+
+size_t tm_image_stats_workspace_bytes(int32_t H, int32_t W) {
+    if (check_image(H, W) != TM_OK) return 0;
+    return round256((size_t)stats_blocks(H, W) * sizeof(StatsPartial));
+}
+
+tm_status tm_image_stats(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                         int32_t n_bins, float *edges, float *offsets, float *minmax,
+                         void *ws, size_t ws_bytes, void *stream) {
+    TM_TRY(check_image(H, W));
+    if (!lum || n_bins < 1 || n_bins > TM_MAX_BINS) return TM_ERR_ARG;
+    if (n_bins > 1 && !edges) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_lum));
+    TM_TRY(check_ws(ws, ws_bytes, tm_image_stats_workspace_bytes(H, W)));
+    return from_hip(launch_stats(nullptr, 0, 0, lum, ld_lum, nullptr, 0, H, W, n_bins, edges,
+                                 offsets, minmax, static_cast<StatsPartial *>(ws),
+                                 (hipStream_t)stream));
+}
+
+tm_status tm_prologue(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                      int32_t W, int32_t n_bins, float *lum, int64_t ld_lum, float *edges,
+                      float *offsets, float *minmax, void *ws, size_t ws_bytes, void *stream) {
+    TM_TRY(check_image(H, W));
+    if (!rgb || !lum || n_bins < 1 || n_bins > TM_MAX_BINS) return TM_ERR_ARG;
+    if (n_bins > 1 && !edges) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_rgb));
+    TM_TRY(check_plane(H, W, ld_lum));
+    if (ch_stride < (int64_t)H * ld_rgb) return TM_ERR_SHAPE;
+    TM_TRY(check_ws(ws, ws_bytes, tm_image_stats_workspace_bytes(H, W)));
+    return from_hip(launch_stats(rgb, ch_stride, ld_rgb, nullptr, 0, lum, ld_lum, H, W, n_bins,
+                                 edges, offsets, minmax, static_cast<StatsPartial *>(ws),
+                                 (hipStream_t)stream));
+}
+
+// ------------------------------------------------------------------ a2, a3
+size_t tm_tables_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_sat_prec prec,
+                                 const tm_tune *tune) {
+    if (check_image(H, W) != TM_OK || !valid_prec(prec) || n_bins < 1 || n_bins > TM_MAX_BINS)
+        return 0;
+    tm_status st;
+    ScanTune t = resolve_tune(tune, H, W, &st);
+    if (st != TM_OK) return 0;
+    return make_scan_plan(H, W, (int)prec, n_bins, t).total;
+}
+
+tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                             tm_sat_prec prec, const float *offsets, void *sat,
+                             int64_t ld_sat, const float *edges, int32_t n_bins,
+                             tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,
+                             int64_t plane_stride, const tm_tune *tune, void *ws,
+                             size_t ws_bytes, void *stream) {
+    TM_TRY(check_image(H, W));
+    if (!v) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_v));
+    if (!sat && !hist) return TM_ERR_ARG;
+    int n_planes = 0;
+    if (sat) {
+        if (!valid_prec(prec)) return TM_ERR_ARG;
+        TM_TRY(check_table(H, W, ld_sat, sat));
+        if (prec == TM_SAT_C32X2 && !offsets) return TM_ERR_ARG;
+    }
+    if (hist) {
+        if (n_bins < 1 || n_bins > TM_MAX_BINS) return TM_ERR_ARG;
+        if (layout != TM_HIST_PER_BIN && layout != TM_HIST_CUMULATIVE) return TM_ERR_ARG;
+        n_planes = layout == TM_HIST_PER_BIN ? n_bins : n_bins - 1;
+        if (n_planes > 0) {
+            if (n_bins > 1 && !edges) return TM_ERR_ARG;
+            TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist, n_planes));
+        }
+    }
+    tm_status st;
+    ScanTune t = resolve_tune(tune, H, W, &st);
+    TM_TRY(st);
+    const int sp = sat ? (int)prec : -1;
+    ScanPlan plan = make_scan_plan(H, W, sp, n_planes, t);
+    // the workspace query assumes a full-precision integral image and n_bins planes
+    TM_TRY(check_ws(ws, ws_bytes, plan.total));
+    if (!sat && n_planes == 0) return TM_OK;
+    ScanArgs a{};
+    a.v = v;
+    a.ld_v = ld_v;
+    a.H = H;
+    a.W = W;
+    a.sat_prec = sp;
+    a.offsets = offsets;
+    a.sat = sat;
+    a.ld_sat = ld_sat;
+    a.edges = edges;
+    a.n_bins = n_bins;
+    a.layout = (int)layout;
+    a.n_planes = n_planes;
+    a.hist = n_planes > 0 ? hist : nullptr;
+    a.ld_hist = ld_hist;
+    a.plane_stride = plane_stride;
+    return from_hip(launch_tables(a, plan, ws, (hipStream_t)stream));
+}
+
+tm_status tm_integral_image(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                            tm_sat_prec prec, const float *offsets, void *sat,
+                            int64_t ld_sat, const tm_tune *tune, void *ws, size_t ws_bytes,
+                            void *stream) {
+    if (!sat) return TM_ERR_ARG;
+    return tm_integral_tables(v, ld_v, H, W, prec, offsets, sat, ld_sat, nullptr, 1,
+                              TM_HIST_CUMULATIVE, nullptr, 0, 0, tune, ws, ws_bytes, stream);
+}
+
+tm_status tm_integral_histogram(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                const float *edges, int32_t n_bins, tm_hist_layout layout,
+                                uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
+                                const tm_tune *tune, void *ws, size_t ws_bytes,
+                                void *stream) {
+    if (!hist) return TM_ERR_ARG;
+    return tm_integral_tables(v, ld_v, H, W, TM_SAT_F32, nullptr, nullptr, 0, edges, n_bins,
+                              layout, hist, ld_hist, plane_stride, tune, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------------------------ a4
+tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                             const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                             const float *offsets, const uint32_t *hist_cum, int64_t ld_hist,
+                             int64_t plane_stride, const float *edges, const tm_params *p,
+                             float *out, int64_t ld_out, void *stream) {
+    TM_TRY(check_image(H, W));
+    TM_TRY(check_params(p));
+    if (!v || !out || !valid_prec(prec)) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_v));
+    TM_TRY(check_plane(H, W, ld_out));
+    TM_TRY(check_table(H, W, ld_sat, sat));
+    if (prec == TM_SAT_C32X2 && !offsets) return TM_ERR_ARG;
+    if (p->n_bins > 1) {
+        if (!edges) return TM_ERR_ARG;
+        TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
+    }
+    QueryParams q{};
+    q.n_bins = p->n_bins;
+    q.n_scales = p->n_scales;
+    for (int j = 0; j < TM_MAX_SCALES; ++j) {
+        q.rx[j] = j < p->n_scales ? p->rx[j] : 0;
+        q.ry[j] = j < p->n_scales ? p->ry[j] : 0;
+    }
+    q.eps = p->eps;
+    q.ld_min = p->ld_min;
+    q.ld_max = p->ld_max;
+    return from_hip(launch_forward(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
+                                   ld_hist, plane_stride, edges, q, out, ld_out,
+                                   (hipStream_t)stream));
+}
+
+// ------------------------------------------------------------------ a5
+size_t tm_backward_workspace_bytes(int32_t H, int32_t W, const tm_params *p) {
+    (void)H;
+    (void)W;
+    (void)p;
+    return 0;
+}
+
+tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                              const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                              const float *offsets, const uint32_t *hist_cum,
+                              int64_t ld_hist, int64_t plane_stride, const float *edges,
+                              const tm_params *p, const float *grad_out, int64_t ld_g,
+                              float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
+                              size_t ws_bytes, void *stream) {
+    (void)v; (void)ld_v; (void)H; (void)W; (void)sat; (void)ld_sat; (void)prec;
+    (void)offsets; (void)hist_cum; (void)ld_hist; (void)plane_stride; (void)edges; (void)p;
+    (void)grad_out; (void)ld_g; (void)grad_v; (void)ld_gv; (void)grad_params; (void)ws;
+    (void)ws_bytes; (void)stream;
+    return TM_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

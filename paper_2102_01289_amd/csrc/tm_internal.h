@@ -1,0 +1,77 @@
+// tm_internal.h -- host-side launchers shared between the kernel files and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tmo {
+
+// ---------------------------------------------------------------- prologue (a1)
+struct StatsPartial {          // one per reduction block, 32 bytes
+    float mn, mx;
+    double s1, s2;
+    double pad;
+};
+constexpr int kStatsMaxBlocks = 1024;
+int stats_blocks(int H, int W);
+
+hipError_t launch_luminance(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int H, int W,
+                            float *lum, int64_t ld_lum, hipStream_t s);
+// rgb == nullptr: reduce lum only.  Otherwise compute lum from rgb and reduce it.
+hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, const float *lum_in,
+                        int64_t ld_lum_in, float *lum_out, int64_t ld_lum_out, int H, int W,
+                        int n_bins, float *edges, float *offsets, float *minmax,
+                        StatsPartial *partials, hipStream_t s);
+
+// ---------------------------------------------------------------- scans (a2, a3)
+struct ScanTune {
+    int vec;        // columns per lane: 1, 2, 4, 8
+    int th;         // rows per tile
+    int chunk;      // histogram planes per pass: 2, 4, 8
+};
+ScanTune scan_tune_default(int H, int W);
+bool scan_tune_valid(const ScanTune &t);
+
+// Workspace carve-up of the three-stage scan (a pure function of the shape and options).
+struct ScanPlan {
+    int H, W, tiles_x, tiles_y, vec, th, chunk;
+    int sat_prec;      // -1: no integral image
+    int n_planes;      // 0: no histogram
+    size_t acc_bytes;  // bytes of one accumulator element (4 or 8)
+    // byte offsets into ws
+    size_t rs_sat, cs_sat, tt_sat, xc_sat, cse_sat, tte_sat;  // each holds 2 quantities
+    size_t rs_h, cs_h, tt_h, xc_h, cse_h, tte_h;              // n_planes quantities
+    size_t total;
+};
+ScanPlan make_scan_plan(int H, int W, int sat_prec, int n_planes, const ScanTune &t);
+
+struct ScanArgs {
+    const float *v;
+    int64_t ld_v;
+    int H, W;
+    int sat_prec;            // -1 none
+    const float *offsets;    // C32X2
+    void *sat;               // table origin
+    int64_t ld_sat;
+    const float *edges;
+    int n_bins;
+    int layout;              // 0 per-bin, 1 cumulative
+    int n_planes;
+    uint32_t *hist;
+    int64_t ld_hist, plane_stride;
+};
+hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipStream_t s);
+
+// ---------------------------------------------------------------- query (a4)
+struct QueryParams {
+    int n_bins, n_scales;
+    int rx[8], ry[8];
+    float eps, ld_min, ld_max;
+};
+hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void *sat,
+                          int64_t ld_sat, int prec, const float *offsets, const uint32_t *hist,
+                          int64_t ld_hist, int64_t plane_stride, const float *edges,
+                          const QueryParams &p, float *out, int64_t ld_out, hipStream_t s);
+
+}  // namespace tmo

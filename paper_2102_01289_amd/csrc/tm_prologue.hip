@@ -1,0 +1,298 @@
+// tm_prologue.hip -- stage a1: luminance (Eq. 11) and the image statistics the later stages
+// need: min / max of the luminance (range of the log-domain bins, Section II-A), the bin
+// edges, and the FP32 mean offsets of the compensated integral images.
+//
+// One streaming pass reads RGB (or luminance), writes luminance and leaves per-block
+// partials (min, max, FP64 sums of v and v^2); a one-block finalize kernel reduces the
+// partials in a fixed order (bit-reproducible) and places the bin edges.
+#include <float.h>
+#include <math.h>
+
+#include "tm_device.h"
+#include "tm_internal.h"
+
+namespace tmo {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSeg = kBlock * 4;   // pixels of one row segment handled by a block step
+
+// Eq. 11 in FP32, left to right with fused multiply-adds.
+__device__ __forceinline__ float luminance(float r, float g, float b) {
+    float t = 0.2126f * r;
+    t = __builtin_fmaf(0.7152f, g, t);
+    return __builtin_fmaf(0.0722f, b, t);
+}
+
+struct Stat {
+    float mn, mx;
+    double s1, s2;
+};
+
+__device__ __forceinline__ void stat_add(Stat &a, float v) {
+    a.mn = fminf(a.mn, v);
+    a.mx = fmaxf(a.mx, v);
+    double d = (double)v;
+    a.s1 += d;
+    a.s2 += d * d;
+}
+
+__device__ __forceinline__ Stat stat_merge(Stat a, Stat b) {
+    return Stat{fminf(a.mn, b.mn), fmaxf(a.mx, b.mx), a.s1 + b.s1, a.s2 + b.s2};
+}
+
+// Deterministic block reduction (butterfly within waves, fixed order across waves).
+__device__ Stat block_reduce(Stat st) {
+    for (int m = 32; m >= 1; m >>= 1) {
+        Stat o{__shfl_xor(st.mn, m), __shfl_xor(st.mx, m), __shfl_xor(st.s1, m),
+               __shfl_xor(st.s2, m)};
+        st = stat_merge(st, o);
+    }
+    __shared__ Stat sh[kBlock / kWave];
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) sh[w] = st;
+    __syncthreads();
+    Stat r = sh[0];
+    for (int i = 1; i < kBlock / kWave; ++i) r = stat_merge(r, sh[i]);
+    return r;
+}
+
+template <bool FROM_RGB, bool STATS>
+__global__ void __launch_bounds__(kBlock)
+lum_stats_kernel(const float *__restrict__ rgb, int64_t ch_stride, int64_t ld_rgb,
+                 const float *__restrict__ lum_in, int64_t ld_in, float *__restrict__ lum_out,
+                 int64_t ld_out, int H, int W, bool vec_in, bool vec_out,
+                 StatsPartial *__restrict__ partials) {
+    Stat st{INFINITY, -INFINITY, 0.0, 0.0};
+    const int segs_per_row = (W + kSeg - 1) / kSeg;
+    const int64_t nseg = (int64_t)H * segs_per_row;
+    for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        const int y = (int)(seg / segs_per_row);
+        const int x = (int)(seg % segs_per_row) * kSeg + (int)threadIdx.x * 4;
+        if (x >= W) continue;
+        float v[4];
+        const bool full = x + 4 <= W;
+        if (FROM_RGB) {
+            const float *R = rgb + (int64_t)y * ld_rgb + x;
+            const float *G = R + ch_stride;
+            const float *B = G + ch_stride;
+            if (full && vec_in) {
+                float4 r = *reinterpret_cast<const float4 *>(R);
+                float4 g = *reinterpret_cast<const float4 *>(G);
+                float4 b = *reinterpret_cast<const float4 *>(B);
+                v[0] = luminance(r.x, g.x, b.x);
+                v[1] = luminance(r.y, g.y, b.y);
+                v[2] = luminance(r.z, g.z, b.z);
+                v[3] = luminance(r.w, g.w, b.w);
+            } else {
+                for (int i = 0; i < 4; ++i)
+                    v[i] = (x + i < W) ? luminance(R[i], G[i], B[i]) : 0.f;
+            }
+            float *o = lum_out + (int64_t)y * ld_out + x;
+            if (full && vec_out) {
+                *reinterpret_cast<float4 *>(o) = make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+                for (int i = 0; i < 4; ++i)
+                    if (x + i < W) o[i] = v[i];
+            }
+        } else {
+            const float *L = lum_in + (int64_t)y * ld_in + x;
+            if (full && vec_in) {
+                float4 l = *reinterpret_cast<const float4 *>(L);
+                v[0] = l.x; v[1] = l.y; v[2] = l.z; v[3] = l.w;
+            } else {
+                for (int i = 0; i < 4; ++i) v[i] = (x + i < W) ? L[i] : 0.f;
+            }
+        }
+        if (STATS) {
+            for (int i = 0; i < 4; ++i)
+                if (x + i < W) stat_add(st, v[i]);
+        }
+    }
+    if (STATS) {
+        Stat r = block_reduce(st);
+        if (threadIdx.x == 0) {
+            StatsPartial p;
+            p.mn = r.mn;
+            p.mx = r.mx;
+            p.s1 = r.s1;
+            p.s2 = r.s2;
+            p.pad = 0.0;
+            partials[blockIdx.x] = p;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- exact edge placement
+// Unsigned big integers (little-endian 32-bit limbs), enough for x^n with 24-bit x and
+// n <= 256 shifted by up to n + 2 bits.
+constexpr int kLimbs = 208;
+struct Big {
+    uint32_t w[kLimbs];
+    int len;
+};
+
+__device__ void big_one(Big &a) {
+    a.w[0] = 1u;
+    a.len = 1;
+}
+__device__ void big_mul_small(Big &a, uint32_t m) {
+    uint64_t carry = 0;
+    for (int i = 0; i < a.len; ++i) {
+        uint64_t t = (uint64_t)a.w[i] * m + carry;
+        a.w[i] = (uint32_t)t;
+        carry = t >> 32;
+    }
+    if (carry && a.len < kLimbs) a.w[a.len++] = (uint32_t)carry;
+}
+__device__ void big_shl(Big &a, int d) {
+    const int ws = d >> 5, bs = d & 31;
+    int nl = a.len + ws + 1;
+    if (nl > kLimbs) nl = kLimbs;
+    for (int i = nl - 1; i >= 0; --i) {
+        const int s = i - ws;
+        uint64_t hi = (s >= 0 && s < a.len) ? a.w[s] : 0u;
+        uint64_t lo = (s - 1 >= 0 && s - 1 < a.len) ? a.w[s - 1] : 0u;
+        a.w[i] = bs ? (uint32_t)((hi << bs) | (lo >> (32 - bs))) : (uint32_t)hi;
+    }
+    a.len = nl;
+}
+__device__ int big_cmp(Big &a, Big &b) {
+    while (a.len > 1 && a.w[a.len - 1] == 0) --a.len;
+    while (b.len > 1 && b.w[b.len - 1] == 0) --b.len;
+    if (a.len != b.len) return a.len < b.len ? -1 : 1;
+    for (int i = a.len - 1; i >= 0; --i)
+        if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+    return 0;
+}
+
+// x = m * 2^e for a positive finite FP32 x (m < 2^24).
+__device__ void f32_split(float x, uint32_t &m, int &e) {
+    const uint32_t bits = __float_as_uint(x);
+    const uint32_t be = (bits >> 23) & 0xffu;
+    if (be == 0) {
+        m = bits & 0x7fffffu;
+        e = -149;
+    } else {
+        m = (bits & 0x7fffffu) | 0x800000u;
+        e = (int)be - 150;
+    }
+}
+
+// c^n >= a^(n-k) b^k, exactly (a, b, c positive finite FP32).
+__device__ bool pow_ge(float c, int n, int k, float a, float b, Big &X, Big &Y) {
+    uint32_t mc, ma, mb;
+    int ec, ea, eb;
+    f32_split(c, mc, ec);
+    f32_split(a, ma, ea);
+    f32_split(b, mb, eb);
+    big_one(X);
+    for (int i = 0; i < n; ++i) big_mul_small(X, mc);
+    big_one(Y);
+    for (int i = 0; i < n - k; ++i) big_mul_small(Y, ma);
+    for (int i = 0; i < k; ++i) big_mul_small(Y, mb);
+    const int d = ((n - k) * ea + k * eb) - n * ec;   // compare X vs Y * 2^d
+    if (d >= 0)
+        big_shl(Y, d);
+    else
+        big_shl(X, -d);
+    return big_cmp(X, Y) >= 0;
+}
+
+__device__ __forceinline__ float f32_next(float x) { return __uint_as_float(__float_as_uint(x) + 1u); }
+__device__ __forceinline__ float f32_prev(float x) { return __uint_as_float(__float_as_uint(x) - 1u); }
+
+// Smallest FP32 >= i_min^(1-k/n) i_max^(k/n).  An FP64 estimate decides unless an FP32
+// value lies within 2^-36 (relative) of it -- far wider than the estimate's own error --
+// in which case the candidates are tested exactly with big integers.
+__device__ float edge_value(int k, int n, float a, float b) {
+    const double la = log((double)a), lb = log((double)b);
+    const double e = exp(la + ((double)k / (double)n) * (lb - la));
+    float c = (float)e;
+    if (!(c < INFINITY)) c = FLT_MAX;
+    if ((double)c < e) c = f32_next(c);
+    const float p = f32_prev(c);
+    const double tol = e * 0x1p-36;
+    if ((double)c - e > tol && e - (double)p > tol) return c;
+    Big X, Y;
+    if (p > 0.f && pow_ge(p, n, k, a, b, X, Y)) return p;
+    if (pow_ge(c, n, k, a, b, X, Y)) return c;
+    return f32_next(c);
+}
+
+__global__ void __launch_bounds__(kBlock)
+stats_finalize_kernel(const StatsPartial *__restrict__ partials, int nparts, int H, int W,
+                      int n_bins, float *__restrict__ edges, float *__restrict__ offsets,
+                      float *__restrict__ minmax) {
+    Stat st{INFINITY, -INFINITY, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nparts; i += kBlock) {
+        StatsPartial p = partials[i];
+        st = stat_merge(st, Stat{p.mn, p.mx, p.s1, p.s2});
+    }
+    const Stat r = block_reduce(st);
+    const double np = (double)H * (double)W;
+    if (threadIdx.x == 0) {
+        if (offsets) {
+            offsets[0] = (float)(r.s1 / np);
+            offsets[1] = (float)(r.s2 / np);
+        }
+        if (minmax) {
+            minmax[0] = r.mn;
+            minmax[1] = r.mx;
+        }
+    }
+    const float a = fmaxf(r.mn, FLT_MIN);
+    const float b = r.mx;
+    for (int k = 1 + (int)threadIdx.x; k < n_bins; k += kBlock) {
+        float e = INFINITY;
+        if (b > a) e = edge_value(k, n_bins, a, b);
+        edges[k - 1] = e;
+    }
+}
+
+}  // namespace
+
+int stats_blocks(int H, int W) {
+    const int64_t nseg = (int64_t)H * ((W + kSeg - 1) / kSeg);
+    return (int)(nseg < kStatsMaxBlocks ? nseg : kStatsMaxBlocks);
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+hipError_t launch_luminance(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int H, int W,
+                            float *lum, int64_t ld_lum, hipStream_t s) {
+    const bool vin = aligned16(rgb) && (ld_rgb % 4 == 0) && (ch_stride % 4 == 0);
+    const bool vout = aligned16(lum) && (ld_lum % 4 == 0);
+    const int64_t nseg = (int64_t)H * ((W + kSeg - 1) / kSeg);
+    const int grid = (int)(nseg < 65536 ? nseg : 65536);
+    hipLaunchKernelGGL((lum_stats_kernel<true, false>), dim3(grid), dim3(kBlock), 0, s, rgb,
+                       ch_stride, ld_rgb, nullptr, 0, lum, ld_lum, H, W, vin, vout, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, const float *lum_in,
+                        int64_t ld_lum_in, float *lum_out, int64_t ld_lum_out, int H, int W,
+                        int n_bins, float *edges, float *offsets, float *minmax,
+                        StatsPartial *partials, hipStream_t s) {
+    const int nb = stats_blocks(H, W);
+    if (rgb) {
+        const bool vin = aligned16(rgb) && (ld_rgb % 4 == 0) && (ch_stride % 4 == 0);
+        const bool vout = aligned16(lum_out) && (ld_lum_out % 4 == 0);
+        hipLaunchKernelGGL((lum_stats_kernel<true, true>), dim3(nb), dim3(kBlock), 0, s, rgb,
+                           ch_stride, ld_rgb, nullptr, 0, lum_out, ld_lum_out, H, W, vin, vout,
+                           partials);
+    } else {
+        const bool vin = aligned16(lum_in) && (ld_lum_in % 4 == 0);
+        hipLaunchKernelGGL((lum_stats_kernel<false, true>), dim3(nb), dim3(kBlock), 0, s,
+                           nullptr, 0, 0, lum_in, ld_lum_in, nullptr, 0, H, W, vin, false,
+                           partials);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, partials, nb, H, W,
+                       n_bins, edges, offsets, minmax);
+    return hipGetLastError();
+}
+
+}  // namespace tmo

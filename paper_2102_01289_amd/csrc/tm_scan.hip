@@ -1,0 +1,621 @@
+// tm_scan.hip -- stages a2 and a3: the integral images of v and v^2 (Eq. 5) and the
+// integral histogram (Eq. 7-8), built in one pass over the luminance.
+//
+// Decomposition (reduce, then scan; no workgroup ever waits on another):
+//   stage 1  every 64-lane wave owns a tile of th rows x 64*VEC columns and writes the
+//            tile's row totals RS[y][tx], column totals CS[ty][x] and total TT[ty][tx];
+//   stage 2  three families of independent 1-D exclusive scans over those aggregates:
+//            XC  = prefix of RS along tx, CSE = prefix of CS along ty,
+//            TTE = prefix of TT along tx;
+//   stage 3  every tile re-reads its pixels and forms
+//              I(x, y) = sum_{ty'<ty} TTE[ty'][tx] + sum_{x0<=x'<=x} CSE[ty][x']
+//                        + sum_{y0<=y'<=y} (XC[y'][tx] + sum_{x0<=x'<=x} q(x', y')),
+//            i.e. the sums above the tile plus the tile's own 2-D prefix.  Row prefixes
+//            use an in-lane prefix over the lane's VEC consecutive columns and a DPP wave
+//            scan of the lane totals; column prefixes run down the tile in registers.
+// The image is read twice (4 bytes/pixel each) and every table entry is written once; the
+// aggregates are 1/th and 1/(64 VEC) of the image.  Histogram counts are exact uint32; the
+// integral image accumulates in the precision's own arithmetic (FP32, compensated FP32
+// pairs, or FP64), in a fixed order, so results are bit-reproducible.
+#include "tm_device.h"
+#include "tm_internal.h"
+
+namespace tmo {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+struct ScanK {
+    const float *v;
+    int64_t ld_v;
+    int H, W, th, tiles_x, tiles_y;
+    int vec_load;                 // rows of v are 16-byte aligned
+    const float *offsets;
+    void *sat;
+    int64_t ld_sat;
+    const float *edges;
+    int n_bins, layout, n_planes;
+    uint32_t *hist;
+    int64_t ld_hist, plane_stride;
+    // aggregates (each an array of quantities; see ScanPlan)
+    void *rs_sat, *cs_sat, *tt_sat, *xc_sat, *cse_sat, *tte_sat;
+    uint32_t *rs_h, *cs_h, *tt_h, *xc_h, *cse_h, *tte_h;
+};
+
+// ---------------------------------------------------------------- table entries
+template <int P>
+struct Entry;
+template <>
+struct Entry<kF32> {
+    using T = float2;
+    __device__ static T make(float a, float b) { return make_float2(a, b); }
+    __device__ static T zero() { return make_float2(0.f, 0.f); }
+};
+template <>
+struct Entry<kC32x2> {
+    using T = float4;
+    __device__ static T make(f2 a, f2 b) { return make_float4(a.hi, a.lo, b.hi, b.lo); }
+    __device__ static T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+};
+template <>
+struct Entry<kF64> {
+    using T = double2;
+    __device__ static T make(double a, double b) { return make_double2(a, b); }
+    __device__ static T zero() { return make_double2(0.0, 0.0); }
+};
+
+// Load the lane's VEC consecutive pixels of row y (zeros outside the image).
+template <int VEC>
+__device__ __forceinline__ void load_row(const ScanK &k, int y, int xl, float (&v)[VEC]) {
+    const float *row = k.v + (int64_t)y * k.ld_v;
+    if (k.vec_load && (VEC % 4 == 0) && xl + VEC <= k.W) {
+#pragma unroll
+        for (int i = 0; i < VEC; i += 4) {
+            float4 t = *reinterpret_cast<const float4 *>(row + xl + i);
+            v[i] = t.x; v[i + 1] = t.y; v[i + 2] = t.z; v[i + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) v[i] = (xl + i < k.W) ? row[xl + i] : 0.f;
+    }
+}
+
+// Histogram plane indicator: cumulative plane p counts bins < p+1 (v < edge[p]);
+// per-bin plane p counts bin p (edge[p-1] <= v < edge[p]).
+template <int CHUNK>
+struct PlaneEdges {
+    float lo[CHUNK], hi[CHUNK];
+    int np;   // planes in this chunk
+};
+template <int CHUNK>
+__device__ __forceinline__ PlaneEdges<CHUNK> chunk_edges(const ScanK &k, int p0) {
+    PlaneEdges<CHUNK> e;
+    e.np = k.n_planes - p0 < CHUNK ? k.n_planes - p0 : CHUNK;
+#pragma unroll
+    for (int c = 0; c < CHUNK; ++c) {
+        const int p = p0 + c;
+        if (k.layout == 1) {
+            e.lo[c] = -INFINITY;
+            e.hi[c] = (p < k.n_planes) ? k.edges[p] : -INFINITY;
+        } else {
+            e.lo[c] = (p == 0) ? -INFINITY : ((p < k.n_planes) ? k.edges[p - 1] : INFINITY);
+            e.hi[c] = (p == k.n_bins - 1) ? INFINITY : ((p < k.n_planes) ? k.edges[p] : -INFINITY);
+        }
+    }
+    return e;
+}
+
+__device__ __forceinline__ uint32_t ind(float v, float lo, float hi, bool in) {
+    return (in && v >= lo && v < hi) ? 1u : 0u;
+}
+
+// ================================================================ stage 1
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST>
+__global__ void __launch_bounds__(kBlock) scan_stage1(ScanK k) {
+    using A = Acc<P>;
+    using T = typename A::T;
+    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile >= k.tiles_x * k.tiles_y) return;
+    const int ty = tile / k.tiles_x, tx = tile % k.tiles_x;
+    const int lane = lane_id();
+    const int TW = kWave * VEC;
+    const int x0 = tx * TW, y0 = ty * k.th;
+    const int rows = min(k.th, k.H - y0);
+    const int xl = x0 + lane * VEC;
+    const int nchunks = HIST ? (k.n_planes + CHUNK - 1) / CHUNK : 0;
+
+    for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
+        const bool do_sat = SAT && ch == 0;
+        const bool do_h = HIST && ch < nchunks;
+        const int p0 = ch * CHUNK;
+        float mu1 = 0.f, mu2 = 0.f;
+        if (do_sat && P == kC32x2) { mu1 = k.offsets[0]; mu2 = k.offsets[1]; }
+        PlaneEdges<CHUNK> pe;
+        if (do_h) pe = chunk_edges<CHUNK>(k, p0);
+
+        T c1[VEC], c2[VEC], t1 = A::zero(), t2 = A::zero();
+        uint32_t cc[CHUNK][VEC], tc[CHUNK];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) { c1[i] = A::zero(); c2[i] = A::zero(); }
+#pragma unroll
+        for (int c = 0; c < CHUNK; ++c) {
+            tc[c] = 0u;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) cc[c][i] = 0u;
+        }
+
+        for (int r = 0; r < rows; ++r) {
+            const int y = y0 + r;
+            float v[VEC];
+            load_row<VEC>(k, y, xl, v);
+            if (do_sat) {
+                T s1 = A::zero(), s2 = A::zero();
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    const bool in = xl + i < k.W;
+                    T q1 = in ? A::of_v(v[i], mu1) : A::zero();
+                    T q2 = in ? A::of_v2(v[i], mu2) : A::zero();
+                    c1[i] = A::add(c1[i], q1);
+                    c2[i] = A::add(c2[i], q2);
+                    s1 = A::add(s1, q1);
+                    s2 = A::add(s2, q2);
+                }
+                s1 = wave_sum<A>(s1);
+                s2 = wave_sum<A>(s2);
+                t1 = A::add(t1, s1);
+                t2 = A::add(t2, s2);
+                if (lane == 0) {
+                    T *rs = reinterpret_cast<T *>(k.rs_sat);
+                    rs[(int64_t)y * k.tiles_x + tx] = s1;
+                    rs[((int64_t)k.H + y) * k.tiles_x + tx] = s2;
+                }
+            }
+            if (do_h) {
+                uint32_t lc[CHUNK];
+#pragma unroll
+                for (int c = 0; c < CHUNK; ++c) {
+                    lc[c] = 0u;
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) {
+                        const uint32_t b = ind(v[i], pe.lo[c], pe.hi[c], xl + i < k.W);
+                        cc[c][i] += b;
+                        lc[c] += b;
+                    }
+                }
+                // row totals <= 64*VEC < 2^16: two planes per 32-bit lane value
+#pragma unroll
+                for (int c = 0; c < CHUNK; c += 2) {
+                    const uint32_t pk = lc[c] | (c + 1 < CHUNK ? lc[c + 1] << 16 : 0u);
+                    const uint32_t s = wave_sum<AddU32>(pk);
+                    const uint32_t a = s & 0xffffu, b = s >> 16;
+                    tc[c] += a;
+                    if (c + 1 < CHUNK) tc[c + 1] += b;
+                    if (lane == 0) {
+                        if (c < pe.np) k.rs_h[((int64_t)(p0 + c) * k.H + y) * k.tiles_x + tx] = a;
+                        if (c + 1 < pe.np)
+                            k.rs_h[((int64_t)(p0 + c + 1) * k.H + y) * k.tiles_x + tx] = b;
+                    }
+                }
+            }
+        }
+        if (do_sat) {
+            T *cs = reinterpret_cast<T *>(k.cs_sat);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+                if (xl + i < k.W) {
+                    cs[(int64_t)ty * k.W + xl + i] = c1[i];
+                    cs[((int64_t)k.tiles_y + ty) * k.W + xl + i] = c2[i];
+                }
+            }
+            if (lane == 0) {
+                T *tt = reinterpret_cast<T *>(k.tt_sat);
+                tt[(int64_t)ty * k.tiles_x + tx] = t1;
+                tt[((int64_t)k.tiles_y + ty) * k.tiles_x + tx] = t2;
+            }
+        }
+        if (do_h) {
+#pragma unroll
+            for (int c = 0; c < CHUNK; ++c) {
+                if (c < pe.np) {
+                    const int64_t q = p0 + c;
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i)
+                        if (xl + i < k.W) k.cs_h[(q * k.tiles_y + ty) * k.W + xl + i] = cc[c][i];
+                    if (lane == 0) k.tt_h[(q * k.tiles_y + ty) * k.tiles_x + tx] = tc[c];
+                }
+            }
+        }
+    }
+}
+
+// ================================================================ stage 2
+// Blocks [0, b1) scan RS along tx, [b1, b2) scan CS along ty, [b2, b3) scan TT along tx.
+template <int P, bool SAT>
+__global__ void __launch_bounds__(kBlock) scan_stage2(ScanK k, int b1, int b2) {
+    using A = Acc<P>;
+    using T = typename A::T;
+    const int nq_sat = SAT ? 2 : 0;
+    const int nq = nq_sat + k.n_planes;
+    const int64_t idx = (int64_t)(blockIdx.x) * kBlock + threadIdx.x;
+    if ((int)blockIdx.x < b1) {
+        // XC[q][y][tx] = sum_{tx' < tx} RS[q][y][tx']
+        if (idx >= (int64_t)nq * k.H) return;
+        const int q = (int)(idx / k.H);
+        const int64_t y = idx % k.H;
+        if (q < nq_sat) {
+            const T *rs = reinterpret_cast<const T *>(k.rs_sat) + ((int64_t)q * k.H + y) * k.tiles_x;
+            T *xc = reinterpret_cast<T *>(k.xc_sat) + ((int64_t)q * k.H + y) * k.tiles_x;
+            T run = A::zero();
+            for (int t = 0; t < k.tiles_x; ++t) { T a = rs[t]; xc[t] = run; run = A::add(run, a); }
+        } else {
+            const int64_t qq = q - nq_sat;
+            const uint32_t *rs = k.rs_h + (qq * k.H + y) * k.tiles_x;
+            uint32_t *xc = k.xc_h + (qq * k.H + y) * k.tiles_x;
+            uint32_t run = 0;
+            for (int t = 0; t < k.tiles_x; ++t) { uint32_t a = rs[t]; xc[t] = run; run += a; }
+        }
+    } else if ((int)blockIdx.x < b2) {
+        // CSE[q][ty][x] = sum_{ty' < ty} CS[q][ty'][x]
+        const int64_t id = idx - (int64_t)b1 * kBlock;
+        if (id >= (int64_t)nq * k.W) return;
+        const int q = (int)(id / k.W);
+        const int64_t x = id % k.W;
+        if (q < nq_sat) {
+            const T *cs = reinterpret_cast<const T *>(k.cs_sat) + (int64_t)q * k.tiles_y * k.W + x;
+            T *ce = reinterpret_cast<T *>(k.cse_sat) + (int64_t)q * k.tiles_y * k.W + x;
+            T run = A::zero();
+            for (int t = 0; t < k.tiles_y; ++t) {
+                T a = cs[(int64_t)t * k.W];
+                ce[(int64_t)t * k.W] = run;
+                run = A::add(run, a);
+            }
+        } else {
+            const int64_t qq = q - nq_sat;
+            const uint32_t *cs = k.cs_h + qq * k.tiles_y * k.W + x;
+            uint32_t *ce = k.cse_h + qq * k.tiles_y * k.W + x;
+            uint32_t run = 0;
+            for (int t = 0; t < k.tiles_y; ++t) {
+                uint32_t a = cs[(int64_t)t * k.W];
+                ce[(int64_t)t * k.W] = run;
+                run += a;
+            }
+        }
+    } else {
+        // TTE[q][ty][tx] = sum_{tx' < tx} TT[q][ty][tx']
+        const int64_t id = idx - (int64_t)b2 * kBlock;
+        if (id >= (int64_t)nq * k.tiles_y) return;
+        const int q = (int)(id / k.tiles_y);
+        const int64_t ty = id % k.tiles_y;
+        if (q < nq_sat) {
+            const T *tt = reinterpret_cast<const T *>(k.tt_sat) + ((int64_t)q * k.tiles_y + ty) * k.tiles_x;
+            T *te = reinterpret_cast<T *>(k.tte_sat) + ((int64_t)q * k.tiles_y + ty) * k.tiles_x;
+            T run = A::zero();
+            for (int t = 0; t < k.tiles_x; ++t) { T a = tt[t]; te[t] = run; run = A::add(run, a); }
+        } else {
+            const int64_t qq = q - nq_sat;
+            const uint32_t *tt = k.tt_h + (qq * k.tiles_y + ty) * k.tiles_x;
+            uint32_t *te = k.tte_h + (qq * k.tiles_y + ty) * k.tiles_x;
+            uint32_t run = 0;
+            for (int t = 0; t < k.tiles_x; ++t) { uint32_t a = tt[t]; te[t] = run; run += a; }
+        }
+    }
+}
+
+// ================================================================ stage 3
+// Column carry at the top of the tile for the lane's VEC columns:
+//   sum_{ty'<ty} TTE[ty'][tx] + inclusive prefix over the tile of CSE[ty][.].
+template <class A, int VEC, class T>
+__device__ __forceinline__ void top_carry(const T *tte, const T *cse, int ty, int tx, int tiles_x,
+                                          int W, int xl, T (&col)[VEC]) {
+    T acc = A::zero();
+    for (int t = lane_id(); t < ty; t += kWave) acc = A::add(acc, tte[(int64_t)t * tiles_x + tx]);
+    const T above = wave_sum<A>(acc);
+    T p[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        T c = (xl + i < W) ? cse[xl + i] : A::zero();
+        p[i] = i ? A::add(p[i - 1], c) : c;
+    }
+    T ex = wave_shr1(wave_inclusive<A>(p[VEC - 1]));
+    T base = A::add(above, ex);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) col[i] = A::add(base, p[i]);
+}
+
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST>
+__global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
+    using A = Acc<P>;
+    using T = typename A::T;
+    using E = Entry<P>;
+    using ET = typename E::T;
+    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile >= k.tiles_x * k.tiles_y) return;
+    const int ty = tile / k.tiles_x, tx = tile % k.tiles_x;
+    const int lane = lane_id();
+    const int TW = kWave * VEC;
+    const int x0 = tx * TW, y0 = ty * k.th;
+    const int rows = min(k.th, k.H - y0);
+    const int xl = x0 + lane * VEC;
+    const int nchunks = HIST ? (k.n_planes + CHUNK - 1) / CHUNK : 0;
+    const bool last_tx = tx == k.tiles_x - 1;
+
+    for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
+        const bool do_sat = SAT && ch == 0;
+        const bool do_h = HIST && ch < nchunks;
+        const int p0 = ch * CHUNK;
+        float mu1 = 0.f, mu2 = 0.f;
+        if (do_sat && P == kC32x2) { mu1 = k.offsets[0]; mu2 = k.offsets[1]; }
+        PlaneEdges<CHUNK> pe;
+        if (do_h) pe = chunk_edges<CHUNK>(k, p0);
+
+        T c1[VEC], c2[VEC];
+        uint32_t cc[CHUNK][VEC];
+        if (do_sat) {
+            const T *tte = reinterpret_cast<const T *>(k.tte_sat);
+            const T *cse = reinterpret_cast<const T *>(k.cse_sat);
+            top_carry<A, VEC>(tte, cse + (int64_t)ty * k.W, ty, tx, k.tiles_x, k.W, xl, c1);
+            top_carry<A, VEC>(tte + (int64_t)k.tiles_y * k.tiles_x,
+                              cse + ((int64_t)k.tiles_y + ty) * k.W, ty, tx, k.tiles_x, k.W, xl, c2);
+        }
+        if (do_h) {
+#pragma unroll
+            for (int c = 0; c < CHUNK; ++c) {
+                const int64_t q = c < pe.np ? p0 + c : p0;
+                top_carry<AddU32, VEC>(k.tte_h + q * k.tiles_y * k.tiles_x,
+                                       k.cse_h + (q * k.tiles_y + ty) * k.W, ty, tx, k.tiles_x,
+                                       k.W, xl, cc[c]);
+            }
+        }
+
+        for (int r = 0; r < rows; ++r) {
+            const int y = y0 + r;
+            float v[VEC];
+            load_row<VEC>(k, y, xl, v);
+            if (do_sat) {
+                const T *xc = reinterpret_cast<const T *>(k.xc_sat);
+                const T xc1 = xc[(int64_t)y * k.tiles_x + tx];
+                const T xc2 = xc[((int64_t)k.H + y) * k.tiles_x + tx];
+                T p1[VEC], p2[VEC];
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    const bool in = xl + i < k.W;
+                    T q1 = in ? A::of_v(v[i], mu1) : A::zero();
+                    T q2 = in ? A::of_v2(v[i], mu2) : A::zero();
+                    p1[i] = i ? A::add(p1[i - 1], q1) : q1;
+                    p2[i] = i ? A::add(p2[i - 1], q2) : q2;
+                }
+                const T b1 = A::add(xc1, wave_shr1(wave_inclusive<A>(p1[VEC - 1])));
+                const T b2 = A::add(xc2, wave_shr1(wave_inclusive<A>(p2[VEC - 1])));
+                ET *out = reinterpret_cast<ET *>(k.sat) + (int64_t)y * k.ld_sat;
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    c1[i] = A::add(c1[i], A::add(b1, p1[i]));
+                    c2[i] = A::add(c2[i], A::add(b2, p2[i]));
+                    if (xl + i < k.W) out[xl + i] = E::make(c1[i], c2[i]);
+                }
+            }
+            if (do_h) {
+#pragma unroll
+                for (int c = 0; c < CHUNK; c += 2) {
+                    uint32_t pa[VEC], pb[VEC];
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) {
+                        const bool in = xl + i < k.W;
+                        const uint32_t a = ind(v[i], pe.lo[c], pe.hi[c], in);
+                        const uint32_t b = (c + 1 < CHUNK) ? ind(v[i], pe.lo[c + 1], pe.hi[c + 1], in) : 0u;
+                        pa[i] = i ? pa[i - 1] + a : a;
+                        pb[i] = i ? pb[i - 1] + b : b;
+                    }
+                    // lane-exclusive prefix of both planes packed in 16-bit halves (<= 64*VEC)
+                    const uint32_t pk = pa[VEC - 1] | (pb[VEC - 1] << 16);
+                    const uint32_t ex = wave_shr1(wave_inclusive<AddU32>(pk));
+                    const uint32_t exa = ex & 0xffffu, exb = ex >> 16;
+                    {
+                        const int64_t q = p0 + c;
+                        if (c < pe.np) {
+                            const uint32_t xc = k.xc_h[(q * k.H + y) * k.tiles_x + tx];
+                            uint32_t *out = k.hist + q * k.plane_stride + (int64_t)y * k.ld_hist;
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i) {
+                                cc[c][i] += xc + exa + pa[i];
+                                if (xl + i < k.W) out[xl + i] = cc[c][i];
+                            }
+                        }
+                    }
+                    if (c + 1 < CHUNK) {
+                        const int64_t q = p0 + c + 1;
+                        if (c + 1 < pe.np) {
+                            const uint32_t xc = k.xc_h[(q * k.H + y) * k.tiles_x + tx];
+                            uint32_t *out = k.hist + q * k.plane_stride + (int64_t)y * k.ld_hist;
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i) {
+                                cc[c + 1][i] += xc + exb + pb[i];
+                                if (xl + i < k.W) out[xl + i] = cc[c + 1][i];
+                            }
+                        }
+                    }
+                }
+            }
+        }
+
+        // zero border: row -1 over this tile's columns (plus x = -1 on the first tile) and
+        // the padding columns [W, ld) on the last tile column (rows y0..y0+rows-1, and
+        // row -1 when ty == 0).
+        if (do_sat) {
+            ET *t0 = reinterpret_cast<ET *>(k.sat);
+            if (ty == 0) {
+                for (int x = x0 - (tx == 0 ? 1 : 0) + lane; x < x0 + TW && x < k.W; x += kWave)
+                    t0[-k.ld_sat + x] = E::zero();
+            }
+            if (last_tx) {
+                for (int r = (ty == 0 ? -1 : 0); r < rows; ++r)
+                    for (int x = k.W + lane; x < k.ld_sat; x += kWave)
+                        t0[(int64_t)(y0 + r) * k.ld_sat + x] = E::zero();
+            }
+        }
+        if (do_h) {
+            for (int c = 0; c < pe.np; ++c) {
+                uint32_t *t0 = k.hist + (int64_t)(p0 + c) * k.plane_stride;
+                if (ty == 0) {
+                    for (int x = x0 - (tx == 0 ? 1 : 0) + lane; x < x0 + TW && x < k.W; x += kWave)
+                        t0[-k.ld_hist + x] = 0u;
+                }
+                if (last_tx) {
+                    for (int r = (ty == 0 ? -1 : 0); r < rows; ++r)
+                        for (int x = k.W + lane; x < k.ld_hist; x += kWave)
+                            t0[(int64_t)(y0 + r) * k.ld_hist + x] = 0u;
+                }
+            }
+        }
+    }
+}
+
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST>
+hipError_t run3(const ScanK &k, hipStream_t s) {
+    const int tiles = k.tiles_x * k.tiles_y;
+    const int grid = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL((scan_stage1<P, VEC, CHUNK, SAT, HIST>), dim3(grid), dim3(kBlock), 0, s, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nq = (SAT ? 2 : 0) + k.n_planes;
+    const int b1 = (int)(((int64_t)nq * k.H + kBlock - 1) / kBlock);
+    const int b2 = b1 + (int)(((int64_t)nq * k.W + kBlock - 1) / kBlock);
+    const int b3 = b2 + (int)(((int64_t)nq * k.tiles_y + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((scan_stage2<P, SAT>), dim3(b3), dim3(kBlock), 0, s, k, b1, b2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((scan_stage3<P, VEC, CHUNK, SAT, HIST>), dim3(grid), dim3(kBlock), 0, s, k);
+    return hipGetLastError();
+}
+
+template <int P, int VEC, int CHUNK>
+hipError_t dispatch_sh(const ScanK &k, bool sat, bool hist, hipStream_t s) {
+    if (sat && hist) return run3<P, VEC, CHUNK, true, true>(k, s);
+    if (sat) return run3<P, VEC, CHUNK, true, false>(k, s);
+    return run3<P, VEC, CHUNK, false, true>(k, s);
+}
+
+template <int P, int VEC>
+hipError_t dispatch_chunk(const ScanK &k, int chunk, bool sat, bool hist, hipStream_t s) {
+    switch (chunk) {
+        case 2: return dispatch_sh<P, VEC, 2>(k, sat, hist, s);
+        case 4: return dispatch_sh<P, VEC, 4>(k, sat, hist, s);
+        default: return dispatch_sh<P, VEC, 8>(k, sat, hist, s);
+    }
+}
+
+template <int P>
+hipError_t dispatch_vec(const ScanK &k, int vec, int chunk, bool sat, bool hist, hipStream_t s) {
+    switch (vec) {
+        case 2: return dispatch_chunk<P, 2>(k, chunk, sat, hist, s);
+        case 4: return dispatch_chunk<P, 4>(k, chunk, sat, hist, s);
+        default: return dispatch_chunk<P, 8>(k, chunk, sat, hist, s);
+    }
+}
+
+size_t round_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
+
+}  // namespace
+
+ScanTune scan_tune_default(int H, int W) {
+    ScanTune t;
+    t.vec = W >= 2048 ? 4 : 2;
+    t.th = 16;
+    // keep at least ~2048 tiles when the image allows
+    const int64_t tw = 64 * t.vec;
+    const int64_t tiles_x = (W + tw - 1) / tw;
+    while (t.th > 4 && tiles_x * ((H + t.th - 1) / t.th) < 2048) t.th /= 2;
+    t.chunk = 4;
+    return t;
+}
+
+bool scan_tune_valid(const ScanTune &t) {
+    return (t.vec == 2 || t.vec == 4 || t.vec == 8) && t.th >= 1 && t.th <= 256 &&
+           (t.chunk == 2 || t.chunk == 4 || t.chunk == 8);
+}
+
+ScanPlan make_scan_plan(int H, int W, int sat_prec, int n_planes, const ScanTune &t) {
+    ScanPlan p{};
+    p.H = H;
+    p.W = W;
+    p.vec = t.vec;
+    p.th = t.th;
+    p.chunk = t.chunk;
+    p.tiles_x = (W + 64 * t.vec - 1) / (64 * t.vec);
+    p.tiles_y = (H + t.th - 1) / t.th;
+    p.sat_prec = sat_prec;
+    p.n_planes = n_planes;
+    p.acc_bytes = sat_prec < 0 ? 0 : (sat_prec == kF32 ? 4 : 8);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = round_up(off + bytes, 256);
+        return o;
+    };
+    const size_t rs = (size_t)H * p.tiles_x, cs = (size_t)p.tiles_y * W,
+                 tt = (size_t)p.tiles_y * p.tiles_x;
+    const size_t a2 = 2 * p.acc_bytes, hq = (size_t)n_planes * 4;
+    p.rs_sat = take(rs * a2);
+    p.cs_sat = take(cs * a2);
+    p.tt_sat = take(tt * a2);
+    p.xc_sat = take(rs * a2);
+    p.cse_sat = take(cs * a2);
+    p.tte_sat = take(tt * a2);
+    p.rs_h = take(rs * hq);
+    p.cs_h = take(cs * hq);
+    p.tt_h = take(tt * hq);
+    p.xc_h = take(rs * hq);
+    p.cse_h = take(cs * hq);
+    p.tte_h = take(tt * hq);
+    p.total = off;
+    return p;
+}
+
+hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipStream_t s) {
+    ScanK k{};
+    char *w = static_cast<char *>(ws);
+    k.v = a.v;
+    k.ld_v = a.ld_v;
+    k.H = a.H;
+    k.W = a.W;
+    k.th = plan.th;
+    k.tiles_x = plan.tiles_x;
+    k.tiles_y = plan.tiles_y;
+    k.vec_load = (((uintptr_t)a.v & 15u) == 0) && (a.ld_v % 4 == 0);
+    k.offsets = a.offsets;
+    k.sat = a.sat;
+    k.ld_sat = a.ld_sat;
+    k.edges = a.edges;
+    k.n_bins = a.n_bins;
+    k.layout = a.layout;
+    k.n_planes = a.n_planes;
+    k.hist = a.hist;
+    k.ld_hist = a.ld_hist;
+    k.plane_stride = a.plane_stride;
+    k.rs_sat = w + plan.rs_sat;
+    k.cs_sat = w + plan.cs_sat;
+    k.tt_sat = w + plan.tt_sat;
+    k.xc_sat = w + plan.xc_sat;
+    k.cse_sat = w + plan.cse_sat;
+    k.tte_sat = w + plan.tte_sat;
+    k.rs_h = reinterpret_cast<uint32_t *>(w + plan.rs_h);
+    k.cs_h = reinterpret_cast<uint32_t *>(w + plan.cs_h);
+    k.tt_h = reinterpret_cast<uint32_t *>(w + plan.tt_h);
+    k.xc_h = reinterpret_cast<uint32_t *>(w + plan.xc_h);
+    k.cse_h = reinterpret_cast<uint32_t *>(w + plan.cse_h);
+    k.tte_h = reinterpret_cast<uint32_t *>(w + plan.tte_h);
+    const bool sat = a.sat_prec >= 0 && a.sat != nullptr;
+    const bool hist = a.n_planes > 0 && a.hist != nullptr;
+    if (!sat) k.n_planes = hist ? a.n_planes : 0;
+    if (!hist) k.n_planes = 0;
+    if (!sat && !hist) return hipSuccess;
+    switch (sat ? a.sat_prec : kF32) {
+        case kF32: return dispatch_vec<kF32>(k, plan.vec, plan.chunk, sat, hist, s);
+        case kC32x2: return dispatch_vec<kC32x2>(k, plan.vec, plan.chunk, sat, hist, s);
+        default: return dispatch_vec<kF64>(k, plan.vec, plan.chunk, sat, hist, s);
+    }
+}
+
+}  // namespace tmo

@@ -1,0 +1,129 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports every entry point
+declared in include/tm.h, and rejects bad arguments before launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch
+
+import paper_2102_01289_amd as tm
+from paper_2102_01289_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(tm_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _capi.load()
+    declared = _declared()
+    assert {"tm_integral_image", "tm_integral_histogram", "tm_tonemap_forward",
+            "tm_tonemap_backward"} <= declared
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    assert declared <= set(_capi.SIGNATURES)
+
+
+def test_status_strings():
+    lib = _capi.load()
+    for code in _capi.STATUS:
+        assert lib.tm_status_string(code)
+
+
+def test_geometry_and_radii():
+    ld, org, el = tm.table_geometry(3000, 4000)
+    assert ld >= 4001 and ld % 64 == 0 and org >= ld + 1 and org % 64 == 0
+    assert el >= org + 3000 * ld and el % 64 == 0
+    rx, ry = tm.paper_radii(3000, 4000, 5)
+    assert rx == [2000, 1000, 500, 250, 125] and ry == [1500, 750, 375, 187, 93]
+    rx, ry = tm.paper_radii(256, 256, 5)
+    assert rx == ry == [128, 64, 32, 16, 8]
+
+
+def test_workspace_sizes_grow_with_problem():
+    lib = _capi.load()
+    a = lib.tm_tables_workspace_bytes(256, 256, 5, 1, None)
+    b = lib.tm_tables_workspace_bytes(1080, 1920, 5, 1, None)
+    c = lib.tm_tables_workspace_bytes(1080, 1920, 64, 1, None)
+    assert 0 < a < b < c
+    assert lib.tm_tables_workspace_bytes(0, 10, 5, 1, None) == 0
+    assert lib.tm_tables_workspace_bytes(10, 10, 5, 7, None) == 0
+    assert lib.tm_image_stats_workspace_bytes(3000, 4000) > 0
+
+
+def _params(**kw):
+    p = tm.make_params(5, 2, [4, 2], [4, 2])
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_argument_checks_return_before_launch():
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    fake = P(1 << 20)      # never dereferenced: every call below fails its host checks
+    null = P(0)
+    # bad shapes / pointers
+    assert lib.tm_luminance(fake, 100, 10, 0, 10, fake, 10, null) == -2
+    assert lib.tm_luminance(null, 100, 10, 10, 10, fake, 10, null) == -1
+    assert lib.tm_luminance(fake, 10, 10, 10, 10, fake, 10, null) == -2     # ch_stride < H*ld
+    assert lib.tm_image_stats(fake, 10, 10, 10, 0, fake, null, null, fake, 1 << 20, null) == -1
+    assert lib.tm_image_stats(fake, 10, 10, 10, 257, fake, null, null, fake, 1 << 20, null) == -1
+    assert lib.tm_image_stats(fake, 10, 10, 10, 5, fake, null, null, null, 0, null) == -4
+    # integral tables: ld too small, misaligned table, missing offsets, bad layout
+    assert lib.tm_integral_image(fake, 10, 10, 10, 0, null, fake, 10, None, fake, 1 << 20,
+                                 null) == -2
+    assert lib.tm_integral_image(fake, 10, 10, 10, 0, null, P((1 << 20) + 4), 64, None, fake,
+                                 1 << 20, null) == -3
+    assert lib.tm_integral_image(fake, 10, 10, 10, 1, null, fake, 64, None, fake, 1 << 20,
+                                 null) == -1
+    assert lib.tm_integral_image(fake, 10, 10, 10, 9, null, fake, 64, None, fake, 1 << 20,
+                                 null) == -1
+    assert lib.tm_integral_histogram(fake, 10, 10, 10, fake, 5, 3, fake, 64, 1 << 12, None,
+                                     fake, 1 << 20, null) == -1
+    assert lib.tm_integral_histogram(fake, 10, 10, 10, fake, 5, 1, fake, 64, 64, None,
+                                     fake, 1 << 20, null) == -2           # planes overlap
+    assert lib.tm_integral_image(fake, 10, 10, 10, 0, null, fake, 64, None, P((1 << 20) + 8),
+                                 1 << 20, null) == -4                      # ws misaligned
+    bad_tune = tm.tune(3, 16, 4)
+    assert lib.tm_integral_image(fake, 10, 10, 10, 0, null, fake, 64, ctypes.byref(bad_tune),
+                                 fake, 1 << 20, null) == -1
+    # forward: parameter checks
+    for kw in (dict(n_bins=0), dict(n_bins=300), dict(n_scales=0), dict(n_scales=9),
+               dict(eps=0.0), dict(eps=float("nan")), dict(ld_min=1.0, ld_max=1.0)):
+        p = _params(**kw)
+        assert lib.tm_tonemap_forward(fake, 10, 10, 10, fake, 64, 1, fake, fake, 64, 1 << 12,
+                                      fake, ctypes.byref(p), fake, 10, null) == -1, kw
+    p = _params()
+    p.rx[1] = -1
+    assert lib.tm_tonemap_forward(fake, 10, 10, 10, fake, 64, 1, fake, fake, 64, 1 << 12, fake,
+                                  ctypes.byref(p), fake, 10, null) == -1
+
+
+def test_table_padded_view_layout_on_host():
+    # the layout helper itself, exercised on a CPU buffer filled by hand
+    H, W = 3, 5
+    t = tm.Table(H, W, "u32", planes=2, device="cpu")
+    t.buf.zero_()
+    b = t.buf.view(2, t.elems)
+    for p in range(2):
+        for y in range(H):
+            for x in range(W):
+                b[p, t.origin + y * t.ld + x] = 100 * p + 10 * y + x + 1
+    pad = t.padded()[..., 0].to(torch.int64)
+    assert pad.shape == (2, H + 1, W + 1)
+    assert torch.all(pad[:, 0, :] == 0) and torch.all(pad[:, :, 0] == 0)
+    for p in range(2):
+        for y in range(H):
+            for x in range(W):
+                assert pad[p, y + 1, x + 1] == 100 * p + 10 * y + x + 1
