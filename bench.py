@@ -46,23 +46,30 @@ def query_bytes_per_px(prec: str, n_bins: int) -> int:
     return 4 + sat + 4 * (n_bins - 1) + 4
 
 
-def cpu_baseline(rgb, params_np):
-    """The oracle, single-threaded, on the full image (about 10-20 s)."""
+def cpu_baseline(rgb, params_np, backward: bool):
+    """The oracle, single-threaded, on the full image (forward about 3-15 s; the backward
+    about three times that)."""
     import numpy as np
 
     import oracle
-    n, s, eps = params_np
+    from synth import gen_upstream_grad
+    n, s, eps, seed = params_np
+    H, W = rgb.shape[1:]
+    g = gen_upstream_grad((H, W), seed=seed).astype(np.float64) if backward else None
     t0 = time.perf_counter()
     lum = oracle.luminance(rgb)
     e = oracle.exact_edges(lum.min(), lum.max(), n)
-    rx, ry = oracle.paper_radii(lum.shape[0], lum.shape[1], s)
+    rx, ry = oracle.paper_radii(H, W, s)
     oracle.forward(lum, e, rx, ry, eps)
+    if backward:
+        oracle.backward(lum, e, rx, ry, g, eps)
     dt = time.perf_counter() - t0
-    H, W = lum.shape
+    what = "forward+backward" if backward else "forward"
     return {"value": round(H * W / dt / 1e6, 4), "unit": "megapixels/s", "cores": 1,
             "kind": "oracle",
-            "sample": (f"full {W}x{H} forward (luminance, exact edges, FP64 double-double "
-                       f"tables, per-pixel pass), one thread, {dt:.1f} s")}
+            "sample": (f"full {W}x{H} {what} (luminance, exact edges, FP64 double-double "
+                       f"tables, per-pixel pass{', adjoint' if backward else ''}), one thread, "
+                       f"{dt:.1f} s")}
 
 
 def main():
@@ -76,7 +83,7 @@ def main():
     import torch
 
     import paper_2102_01289_amd as tm
-    from synth import WORKLOADS, gen_wdr
+    from synth import WORKLOADS, gen_upstream_grad, gen_wdr
 
     cfg = WORKLOADS[WORKLOAD]
     H, W = cfg["H"], cfg["W"]
@@ -87,20 +94,27 @@ def main():
     mapper = tm.ToneMapper(H, W, params, args.prec, device=dev)
     stream = torch.cuda.current_stream()
 
+    g = torch.from_numpy(gen_upstream_grad((H, W), seed=cfg["seed"] + 1)).to(dev)
+    do_bwd = not args.no_backward
+
     def step(ev=None):
         ko = args.kernel_only
-        if ko is None or ko != "query":
+        if ko in (None, "tables"):
             mapper.prologue(rgb)
             mapper.tables()
-        if ko is None or ko == "query":
+        if ko in (None, "query"):
             if ev is not None:
                 ev[0].record(stream)
             mapper.query()
             if ev is not None:
                 ev[1].record(stream)
+        if do_bwd and ko in (None, "backward"):
+            mapper.backward(g)
 
-    # warm-up (also produces the tables a query-only loop reads)
+    # warm-up (also produces the tables a query-only or backward-only loop reads)
     mapper.run(rgb)
+    if do_bwd:
+        mapper.backward(g)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -114,12 +128,16 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / args.steps
-    q_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    q_ms = float(np.mean([a.elapsed_time(b) for a, b in evs])) if args.kernel_only in (
+        None, "query") else float("nan")
 
     # per-stage split (outside the timed loop)
     stage = {}
-    for name, fn in (("prologue", lambda: mapper.prologue(rgb)), ("tables", mapper.tables),
-                     ("query", mapper.query)):
+    stages = [("prologue", lambda: mapper.prologue(rgb)), ("tables", mapper.tables),
+              ("query", mapper.query)]
+    if do_bwd:
+        stages.append(("backward", lambda: mapper.backward(g)))
+    for name, fn in stages:
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         for _ in range(5):
@@ -127,6 +145,7 @@ def main():
         b.record(stream)
         torch.cuda.synchronize()
         stage[name] = round(a.elapsed_time(b) / 5, 4)
+    fwd_ms = stage["prologue"] + stage["tables"] + stage["query"]
 
     mpx = H * W / 1e6
     qbytes = query_bytes_per_px(args.prec, args.n_bins) * H * W
@@ -148,8 +167,11 @@ def main():
                    "n_scales": args.n_scales, "eps": args.eps, "sat_precision": args.prec,
                    "radii_x": list(params.rx[:args.n_scales]),
                    "radii_y": list(params.ry[:args.n_scales]),
-                   "step": "forward" if args.kernel_only is None else args.kernel_only},
-        "fwd_mp_s": round(mpx / (sum(stage.values()) * 1e-3), 3),
+                   "step": ("forward+backward" if do_bwd else "forward")
+                   if args.kernel_only is None else args.kernel_only},
+        "fwd_mp_s": round(mpx / (fwd_ms * 1e-3), 3),
+        "fwd_bwd_mp_s": round(mpx / (sum(stage.values()) * 1e-3), 3) if do_bwd else None,
+        "fwd_bwd_over_fwd": round(fwd_ms / sum(stage.values()), 4) if do_bwd else None,
         "stage_ms": stage,
         "roofline": {"bound": "hbm", "kernel": "forward_kernel (fused query+blend)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -158,7 +180,8 @@ def main():
                      "avg_kernel_ms": round(q_ms, 4)},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(img.rgb, (args.n_bins, args.n_scales, args.eps))
+        line["cpu_baseline"] = cpu_baseline(img.rgb, (args.n_bins, args.n_scales, args.eps,
+                                                      cfg["seed"] + 1), do_bwd)
     print(json.dumps(line), flush=True)
 
 

@@ -330,6 +330,25 @@ class ToneMapper:
         self.query(stream)
         return self.out
 
+    def backward(self, grad_out: torch.Tensor, stream=None):
+        """Adjoint of the last forward (its tables are reused): (grad_lum, grad_params)."""
+        if not hasattr(self, "grad_v"):
+            dev = self.lum.device
+            self.grad_v = torch.empty((self.H, self.W), dtype=torch.float32, device=dev)
+            self.grad_params = torch.empty(3, dtype=torch.float64, device=dev)
+            self.ws_bwd = _ws(_lib().tm_backward_workspace_bytes(self.H, self.W,
+                                                                 ctypes.byref(self.params)), dev)
+        h = self.hist
+        _, _, ldg = _img(grad_out, "grad_out")
+        _ck("tm_tonemap_backward", _lib().tm_tonemap_backward(
+            _vp(self.lum), self.lum.stride(0), self.H, self.W, _vp(self.sat.ptr), self.sat.ld,
+            _capi.SAT_PREC[self.prec], _vp(self.offsets), _vp(h.ptr if h else None),
+            h.ld if h else 0, h.plane_stride if h else 0, _vp(self.edges),
+            ctypes.byref(self.params), _vp(grad_out), ldg, _vp(self.grad_v),
+            self.grad_v.stride(0), _vp(self.grad_params), _vp(self.ws_bwd), self.ws_bwd.numel(),
+            _stream(stream)))
+        return self.grad_v, self.grad_params
+
 
 def tonemap(rgb: torch.Tensor, n_bins: int = 5, n_scales: int = 5, eps: float = 0.1,
             prec: str = "c32x2", ld_min: float = 0.0, ld_max: float = 1.0) -> torch.Tensor:

@@ -1,0 +1,60 @@
+"""torch.autograd.Function over the C ABI: forward = tables + fused query, backward = the
+hand-written adjoint (tm_tonemap_backward).
+
+Differentiable inputs: the luminance image and the scalars (eps, min L_d, max L_d).  The bin
+edges are statistics of the image held fixed in the backward (stop-gradient), and the bin
+counts are piecewise constant in the luminance, so their derivative is zero almost
+everywhere.  With recompute=True the integral tables are freed after the forward and
+rebuilt in the backward (memory: two images' worth of tables instead of a per-step copy).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (make_params, tm_image_stats, tm_integral_tables, tm_tonemap_backward,
+               tm_tonemap_forward)
+
+__all__ = ["TonemapFn", "tonemap_luminance"]
+
+
+def _params(H, W, n_bins, rx, ry, eps, ld_min, ld_max):
+    return make_params(n_bins, len(rx), rx, ry, float(eps), float(ld_min), float(ld_max), H, W)
+
+
+class TonemapFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, lum, eps, ld_min, ld_max, n_bins: int, rx, ry, prec: str = "c32x2",
+                recompute: bool = True):
+        H, W = lum.shape
+        p = _params(H, W, n_bins, rx, ry, eps.item(), ld_min.item(), ld_max.item())
+        edges, offsets, _ = tm_image_stats(lum, n_bins)
+        sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")
+        out = tm_tonemap_forward(lum, sat, hist, edges, p, offsets)
+        ctx.meta = (p, prec, n_bins, recompute, eps.dtype)
+        ctx.tables = None if recompute else (sat, hist)
+        ctx.save_for_backward(lum, edges, offsets)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        lum, edges, offsets = ctx.saved_tensors
+        p, prec, n_bins, recompute, sdt = ctx.meta
+        if ctx.tables is None:
+            sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")
+        else:
+            sat, hist = ctx.tables
+        gv, gp = tm_tonemap_backward(lum, sat, hist, edges, p, g.contiguous().float(), offsets)
+        ctx.tables = None
+        return (gv, gp[0].to(sdt), gp[1].to(sdt), gp[2].to(sdt), None, None, None, None, None)
+
+
+def tonemap_luminance(lum, eps, ld_min, ld_max, n_bins=5, rx=None, ry=None, n_scales=5,
+                      prec="c32x2", recompute=True):
+    """Differentiable tone mapping of a luminance image [H, W] (CUDA float32).  eps, ld_min,
+    ld_max are 0-d tensors; radii default to the paper's pyramid."""
+    H, W = lum.shape
+    if rx is None or ry is None:
+        from . import paper_radii
+        rx, ry = paper_radii(H, W, n_scales)
+    return TonemapFn.apply(lum, eps, ld_min, ld_max, n_bins, tuple(rx), tuple(ry), prec,
+                           recompute)

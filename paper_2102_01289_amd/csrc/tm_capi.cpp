@@ -82,6 +82,20 @@ ScanTune resolve_tune(const tm_tune *t, int H, int W, tm_status *st) {
 
 size_t round256(size_t a) { return (a + 255) / 256 * 256; }
 
+QueryParams to_query(const tm_params *p) {
+    QueryParams q{};
+    q.n_bins = p->n_bins;
+    q.n_scales = p->n_scales;
+    for (int j = 0; j < TM_MAX_SCALES; ++j) {
+        q.rx[j] = j < p->n_scales ? p->rx[j] : 0;
+        q.ry[j] = j < p->n_scales ? p->ry[j] : 0;
+    }
+    q.eps = p->eps;
+    q.ld_min = p->ld_min;
+    q.ld_max = p->ld_max;
+    return q;
+}
+
 #define TM_TRY(expr)                      \
     do {                                  \
         tm_status _s = (expr);            \
@@ -273,16 +287,7 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
         if (!edges) return TM_ERR_ARG;
         TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
     }
-    QueryParams q{};
-    q.n_bins = p->n_bins;
-    q.n_scales = p->n_scales;
-    for (int j = 0; j < TM_MAX_SCALES; ++j) {
-        q.rx[j] = j < p->n_scales ? p->rx[j] : 0;
-        q.ry[j] = j < p->n_scales ? p->ry[j] : 0;
-    }
-    q.eps = p->eps;
-    q.ld_min = p->ld_min;
-    q.ld_max = p->ld_max;
+    const QueryParams q = to_query(p);
     return from_hip(launch_forward(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
                                    ld_hist, plane_stride, edges, q, out, ld_out,
                                    (hipStream_t)stream));
@@ -290,10 +295,8 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
 
 // ------------------------------------------------------------------ a5
 size_t tm_backward_workspace_bytes(int32_t H, int32_t W, const tm_params *p) {
-    (void)H;
-    (void)W;
-    (void)p;
-    return 0;
+    if (check_image(H, W) != TM_OK || check_params(p) != TM_OK) return 0;
+    return make_bwd_plan(H, W, p->n_scales).total;
 }
 
 tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W,
@@ -303,11 +306,41 @@ tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W
                               const tm_params *p, const float *grad_out, int64_t ld_g,
                               float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
                               size_t ws_bytes, void *stream) {
-    (void)v; (void)ld_v; (void)H; (void)W; (void)sat; (void)ld_sat; (void)prec;
-    (void)offsets; (void)hist_cum; (void)ld_hist; (void)plane_stride; (void)edges; (void)p;
-    (void)grad_out; (void)ld_g; (void)grad_v; (void)ld_gv; (void)grad_params; (void)ws;
-    (void)ws_bytes; (void)stream;
-    return TM_ERR_UNSUPPORTED;
+    TM_TRY(check_image(H, W));
+    TM_TRY(check_params(p));
+    if (!v || !grad_out || !grad_v || !grad_params || !valid_prec(prec)) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_v));
+    TM_TRY(check_plane(H, W, ld_g));
+    TM_TRY(check_plane(H, W, ld_gv));
+    TM_TRY(check_table(H, W, ld_sat, sat));
+    if (prec == TM_SAT_C32X2 && !offsets) return TM_ERR_ARG;
+    if (p->n_bins > 1) {
+        if (!edges) return TM_ERR_ARG;
+        TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
+    }
+    if (!aligned(grad_params, 8)) return TM_ERR_ALIGN;
+    BwdPlan plan = make_bwd_plan(H, W, p->n_scales);
+    TM_TRY(check_ws(ws, ws_bytes, plan.total));
+    BwdArgs a{};
+    a.v = v;
+    a.ld_v = ld_v;
+    a.H = H;
+    a.W = W;
+    a.sat = sat;
+    a.ld_sat = ld_sat;
+    a.prec = (int)prec;
+    a.offsets = offsets;
+    a.hist = hist_cum;
+    a.ld_hist = ld_hist;
+    a.plane_stride = plane_stride;
+    a.edges = edges;
+    a.p = to_query(p);
+    a.g = grad_out;
+    a.ld_g = ld_g;
+    a.grad_v = grad_v;
+    a.ld_gv = ld_gv;
+    a.grad_params = grad_params;
+    return from_hip(launch_backward(a, plan, ws, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -74,4 +74,37 @@ hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void
                           int64_t ld_hist, int64_t plane_stride, const float *edges,
                           const QueryParams &p, float *out, int64_t ld_out, hipStream_t s);
 
+// Prefix scan of two FP64 planes stored in reversed pixel order (pitch ld_d), written back as
+// dv = s1 + 2 v s2 in forward order: the suffix sums of the backward.
+hipError_t launch_suffix_adjoint(const double2 *d, int64_t ld_d, const float *v, int64_t ld_v,
+                                 int H, int W, float *gv, int64_t ld_gv, const ScanPlan &plan,
+                                 void *ws, hipStream_t s);
+
+// ---------------------------------------------------------------- backward (a5)
+struct BwdArgs {
+    const float *v;
+    int64_t ld_v;
+    int H, W;
+    const void *sat;
+    int64_t ld_sat;
+    int prec;
+    const float *offsets;
+    const uint32_t *hist;
+    int64_t ld_hist, plane_stride;
+    const float *edges;
+    QueryParams p;
+    const float *g;
+    int64_t ld_g;
+    float *grad_v;
+    int64_t ld_gv;
+    double *grad_params;
+};
+struct BwdPlan {
+    int64_t nblocks;
+    size_t A, Rb, Cb, Dr, part, scan, total;
+    ScanPlan scan_plan;
+};
+BwdPlan make_bwd_plan(int H, int W, int n_scales);
+hipError_t launch_backward(const BwdArgs &a, const BwdPlan &plan, void *ws, hipStream_t s);
+
 }  // namespace tmo

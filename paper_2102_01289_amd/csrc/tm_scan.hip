@@ -42,6 +42,12 @@ struct ScanK {
     // aggregates (each an array of quantities; see ScanPlan)
     void *rs_sat, *cs_sat, *tt_sat, *xc_sat, *cse_sat, *tte_sat;
     uint32_t *rs_h, *cs_h, *tt_h, *xc_h, *cse_h, *tte_h;
+    // adjoint mode: the two FP64 planes to scan (row-major, pitch ld_d, already in reversed
+    // pixel order) and the gradient written back in forward order, dv = s1 + 2 v s2
+    const double2 *dsrc;
+    int64_t ld_d;
+    float *gv;
+    int64_t ld_gv;
 };
 
 // ---------------------------------------------------------------- table entries
@@ -111,8 +117,33 @@ __device__ __forceinline__ uint32_t ind(float v, float lo, float hi, bool in) {
     return (in && v >= lo && v < hi) ? 1u : 0u;
 }
 
+// Per-pixel terms of the two scanned quantities: (v - mu1, v^2 - mu2) of the luminance in
+// table mode; the two FP64 deposit planes in adjoint mode.  Zero outside the image.
+template <int P, int VEC, bool ADJ>
+__device__ __forceinline__ void sat_terms(const ScanK &k, int y, int xl, const float (&v)[VEC],
+                                          float mu1, float mu2, typename Acc<P>::T (&q1)[VEC],
+                                          typename Acc<P>::T (&q2)[VEC]) {
+    using A = Acc<P>;
+    if constexpr (ADJ) {
+        const double2 *row = k.dsrc + (int64_t)y * k.ld_d;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const double2 d = (xl + i < k.W) ? row[xl + i] : make_double2(0.0, 0.0);
+            q1[i] = d.x;
+            q2[i] = d.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const bool in = xl + i < k.W;
+            q1[i] = in ? A::of_v(v[i], mu1) : A::zero();
+            q2[i] = in ? A::of_v2(v[i], mu2) : A::zero();
+        }
+    }
+}
+
 // ================================================================ stage 1
-template <int P, int VEC, int CHUNK, bool SAT, bool HIST>
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
 __global__ void __launch_bounds__(kBlock) scan_stage1(ScanK k) {
     using A = Acc<P>;
     using T = typename A::T;
@@ -149,18 +180,17 @@ __global__ void __launch_bounds__(kBlock) scan_stage1(ScanK k) {
         for (int r = 0; r < rows; ++r) {
             const int y = y0 + r;
             float v[VEC];
-            load_row<VEC>(k, y, xl, v);
+            if (!ADJ) load_row<VEC>(k, y, xl, v);
             if (do_sat) {
                 T s1 = A::zero(), s2 = A::zero();
+                T q1[VEC], q2[VEC];
+                sat_terms<P, VEC, ADJ>(k, y, xl, v, mu1, mu2, q1, q2);
 #pragma unroll
                 for (int i = 0; i < VEC; ++i) {
-                    const bool in = xl + i < k.W;
-                    T q1 = in ? A::of_v(v[i], mu1) : A::zero();
-                    T q2 = in ? A::of_v2(v[i], mu2) : A::zero();
-                    c1[i] = A::add(c1[i], q1);
-                    c2[i] = A::add(c2[i], q2);
-                    s1 = A::add(s1, q1);
-                    s2 = A::add(s2, q2);
+                    c1[i] = A::add(c1[i], q1[i]);
+                    c2[i] = A::add(c2[i], q2[i]);
+                    s1 = A::add(s1, q1[i]);
+                    s2 = A::add(s2, q2[i]);
                 }
                 s1 = wave_sum<A>(s1);
                 s2 = wave_sum<A>(s2);
@@ -324,7 +354,7 @@ __device__ __forceinline__ void top_carry(const T *tte, const T *cse, int ty, in
     for (int i = 0; i < VEC; ++i) col[i] = A::add(base, p[i]);
 }
 
-template <int P, int VEC, int CHUNK, bool SAT, bool HIST>
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
 __global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
     using A = Acc<P>;
     using T = typename A::T;
@@ -372,28 +402,40 @@ __global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
         for (int r = 0; r < rows; ++r) {
             const int y = y0 + r;
             float v[VEC];
-            load_row<VEC>(k, y, xl, v);
+            if (!ADJ) load_row<VEC>(k, y, xl, v);
             if (do_sat) {
                 const T *xc = reinterpret_cast<const T *>(k.xc_sat);
                 const T xc1 = xc[(int64_t)y * k.tiles_x + tx];
                 const T xc2 = xc[((int64_t)k.H + y) * k.tiles_x + tx];
                 T p1[VEC], p2[VEC];
+                sat_terms<P, VEC, ADJ>(k, y, xl, v, mu1, mu2, p1, p2);
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    const bool in = xl + i < k.W;
-                    T q1 = in ? A::of_v(v[i], mu1) : A::zero();
-                    T q2 = in ? A::of_v2(v[i], mu2) : A::zero();
-                    p1[i] = i ? A::add(p1[i - 1], q1) : q1;
-                    p2[i] = i ? A::add(p2[i - 1], q2) : q2;
+                for (int i = 1; i < VEC; ++i) {
+                    p1[i] = A::add(p1[i - 1], p1[i]);
+                    p2[i] = A::add(p2[i - 1], p2[i]);
                 }
                 const T b1 = A::add(xc1, wave_shr1(wave_inclusive<A>(p1[VEC - 1])));
                 const T b2 = A::add(xc2, wave_shr1(wave_inclusive<A>(p2[VEC - 1])));
-                ET *out = reinterpret_cast<ET *>(k.sat) + (int64_t)y * k.ld_sat;
 #pragma unroll
                 for (int i = 0; i < VEC; ++i) {
                     c1[i] = A::add(c1[i], A::add(b1, p1[i]));
                     c2[i] = A::add(c2[i], A::add(b2, p2[i]));
-                    if (xl + i < k.W) out[xl + i] = E::make(c1[i], c2[i]);
+                }
+                if constexpr (ADJ) {
+                    // virtual (x', y) is pixel (W-1-x', H-1-y): dv = s1 + 2 v s2
+                    const int yo = k.H - 1 - y;
+                    const float *vr = k.v + (int64_t)yo * k.ld_v;
+                    float *gr = k.gv + (int64_t)yo * k.ld_gv;
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) {
+                        const int xo = k.W - 1 - (xl + i);
+                        if (xo >= 0) gr[xo] = (float)(c1[i] + 2.0 * (double)vr[xo] * c2[i]);
+                    }
+                } else {
+                    ET *out = reinterpret_cast<ET *>(k.sat) + (int64_t)y * k.ld_sat;
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i)
+                        if (xl + i < k.W) out[xl + i] = E::make(c1[i], c2[i]);
                 }
             }
             if (do_h) {
@@ -443,7 +485,7 @@ __global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
         // zero border: row -1 over this tile's columns (plus x = -1 on the first tile) and
         // the padding columns [W, ld) on the last tile column (rows y0..y0+rows-1, and
         // row -1 when ty == 0).
-        if (do_sat) {
+        if (do_sat && !ADJ) {
             ET *t0 = reinterpret_cast<ET *>(k.sat);
             if (ty == 0) {
                 for (int x = x0 - (tx == 0 ? 1 : 0) + lane; x < x0 + TW && x < k.W; x += kWave)
@@ -472,11 +514,11 @@ __global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
     }
 }
 
-template <int P, int VEC, int CHUNK, bool SAT, bool HIST>
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ = false>
 hipError_t run3(const ScanK &k, hipStream_t s) {
     const int tiles = k.tiles_x * k.tiles_y;
     const int grid = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL((scan_stage1<P, VEC, CHUNK, SAT, HIST>), dim3(grid), dim3(kBlock), 0, s, k);
+    hipLaunchKernelGGL((scan_stage1<P, VEC, CHUNK, SAT, HIST, ADJ>), dim3(grid), dim3(kBlock), 0, s, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nq = (SAT ? 2 : 0) + k.n_planes;
@@ -486,7 +528,7 @@ hipError_t run3(const ScanK &k, hipStream_t s) {
     hipLaunchKernelGGL((scan_stage2<P, SAT>), dim3(b3), dim3(kBlock), 0, s, k, b1, b2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((scan_stage3<P, VEC, CHUNK, SAT, HIST>), dim3(grid), dim3(kBlock), 0, s, k);
+    hipLaunchKernelGGL((scan_stage3<P, VEC, CHUNK, SAT, HIST, ADJ>), dim3(grid), dim3(kBlock), 0, s, k);
     return hipGetLastError();
 }
 
@@ -615,6 +657,36 @@ hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipS
         case kF32: return dispatch_vec<kF32>(k, plan.vec, plan.chunk, sat, hist, s);
         case kC32x2: return dispatch_vec<kC32x2>(k, plan.vec, plan.chunk, sat, hist, s);
         default: return dispatch_vec<kF64>(k, plan.vec, plan.chunk, sat, hist, s);
+    }
+}
+
+hipError_t launch_suffix_adjoint(const double2 *d, int64_t ld_d, const float *v, int64_t ld_v,
+                                 int H, int W, float *gv, int64_t ld_gv, const ScanPlan &plan,
+                                 void *ws, hipStream_t s) {
+    ScanK k{};
+    char *w = static_cast<char *>(ws);
+    k.v = v;
+    k.ld_v = ld_v;
+    k.H = H;
+    k.W = W;
+    k.th = plan.th;
+    k.tiles_x = plan.tiles_x;
+    k.tiles_y = plan.tiles_y;
+    k.n_planes = 0;
+    k.rs_sat = w + plan.rs_sat;
+    k.cs_sat = w + plan.cs_sat;
+    k.tt_sat = w + plan.tt_sat;
+    k.xc_sat = w + plan.xc_sat;
+    k.cse_sat = w + plan.cse_sat;
+    k.tte_sat = w + plan.tte_sat;
+    k.dsrc = d;
+    k.ld_d = ld_d;
+    k.gv = gv;
+    k.ld_gv = ld_gv;
+    switch (plan.vec) {
+        case 2: return run3<kF64, 2, 2, true, false, true>(k, s);
+        case 4: return run3<kF64, 4, 2, true, false, true>(k, s);
+        default: return run3<kF64, 8, 2, true, false, true>(k, s);
     }
 }
 

@@ -1,0 +1,108 @@
+"""GPU backward (the hand-written adjoint) against the FP64 oracle gradient, central
+differences of the GPU forward, and the autograd wrapper."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2102_01289_amd as tm
+from paper_2102_01289_amd.autograd import tonemap_luminance
+from _cases import edges_ref, lum_ref, rgb_case, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grad(lum, n, rx, ry, eps, prec, g, ld=(0.0, 1.0)):
+    v = to_dev(lum)
+    p = tm.make_params(n, len(rx), rx, ry, eps, ld[0], ld[1])
+    edges, offsets, _ = tm.tm_image_stats(v, n)
+    sat, hist = tm.tm_integral_tables(v, prec, offsets, edges, n, "cumulative")
+    gv, gp = tm.tm_tonemap_backward(v, sat, hist, edges, p, to_dev(g.astype(np.float32)), offsets)
+    torch.cuda.synchronize()
+    return gv.cpu().numpy().astype(np.float64), gp.cpu().numpy()
+
+
+def _check(lum, n, rx, ry, eps, prec, seed, ld=(0.0, 1.0), rtol=2e-4):
+    g = np.random.default_rng(seed).standard_normal(lum.shape).astype(np.float32)
+    gv, gp = _gpu_grad(lum, n, rx, ry, eps, prec, g, ld)
+    e = edges_ref(lum, n)
+    dv, gref = oracle.backward(lum, e, rx, ry, g.astype(np.float64), eps, ld[0], ld[1])
+    scale = np.max(np.abs(dv))
+    err = np.abs(gv - dv)
+    assert np.all(err <= rtol * scale + 1e-3 * np.abs(dv)), \
+        f"max err {err.max():.3e} vs scale {scale:.3e}"
+    for a, b in zip(gp, gref):
+        assert abs(a - b) <= 1e-6 * (1.0 + abs(b)) + rtol * abs(b), (gp, gref)
+    return gv, dv
+
+
+@pytest.mark.parametrize("prec", ["f64", "c32x2"])
+@pytest.mark.parametrize("H,W,n,s", [(48, 64, 5, 3), (96, 128, 5, 5), (37, 123, 3, 4),
+                                     (1, 200, 5, 2), (150, 1, 5, 2), (64, 64, 64, 3)])
+def test_backward_matches_oracle(prec, H, W, n, s):
+    lum = lum_ref(rgb_case(H, W, 5, -2.0, 4.0, seed=H + W + n))
+    rx, ry = oracle.paper_radii(H, W, s)
+    _check(lum, n, rx, ry, 0.1, prec, seed=s)
+
+
+@pytest.mark.parametrize("rx,ry", [([0, 3, 100], [0, 7, 100]), ([5, 1], [0, 9]),
+                                   ([40, 20, 10, 5, 2, 1, 0, 3], [30, 15, 8, 4, 2, 1, 0, 3])])
+def test_backward_radii_and_clamping(rx, ry):
+    lum = lum_ref(rgb_case(60, 80, 5, -2.0, 4.0, seed=len(rx)))
+    _check(lum, 5, rx, ry, 0.05, "f64", seed=3, ld=(0.2, 0.8))
+
+
+def test_backward_matches_central_differences_of_gpu_forward():
+    # directional derivative along a random direction on pixels far from every bin edge
+    H, W = 64, 96
+    lum = lum_ref(rgb_case(H, W, 5, -2.0, 4.0, seed=5))
+    n, s = 5, 4
+    rx, ry = oracle.paper_radii(H, W, s)
+    e = edges_ref(lum, n)
+    g = np.random.default_rng(1).standard_normal((H, W)).astype(np.float32)
+    gv, _ = _gpu_grad(lum, n, rx, ry, 0.1, "f64", g)
+    h = 1e-3
+    lv = np.log(lum.astype(np.float64))
+    safe = np.all(np.abs(lv[..., None] - np.log(e.astype(np.float64))) > 4 * h, axis=-1)
+    safe &= (lv > lv.min() + 4 * h) & (lv < lv.max() - 4 * h)
+    d = np.random.default_rng(2).standard_normal((H, W)) * safe
+    vp = (lum * np.exp(h * d)).astype(np.float32)
+    vm = (lum * np.exp(-h * d)).astype(np.float32)
+    p = tm.make_params(n, s, rx, ry, 0.1)
+
+    def F(v):
+        x = to_dev(v)
+        edges, offsets, _ = tm.tm_image_stats(x, n)
+        sat, hist = tm.tm_integral_tables(x, "f64", offsets, edges, n, "cumulative")
+        L = tm.tm_tonemap_forward(x, sat, hist, edges, p, offsets)
+        return float(np.sum(g.astype(np.float64) * L.cpu().numpy().astype(np.float64)))
+
+    fd = F(vp) - F(vm)
+    lin = float(np.sum(gv * (vp.astype(np.float64) - vm.astype(np.float64))))
+    assert abs(fd - lin) <= 2e-3 * abs(lin) + 1e-5
+
+
+def test_backward_deterministic():
+    lum = lum_ref(rgb_case(128, 160, 5, seed=8))
+    rx, ry = oracle.paper_radii(128, 160, 5)
+    g = np.random.default_rng(0).standard_normal(lum.shape).astype(np.float32)
+    a = _gpu_grad(lum, 5, rx, ry, 0.1, "c32x2", g)
+    b = _gpu_grad(lum, 5, rx, ry, 0.1, "c32x2", g)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("recompute", [True, False])
+def test_autograd_function(recompute):
+    H, W = 80, 100
+    lum = lum_ref(rgb_case(H, W, 5, seed=13))
+    x = to_dev(lum).requires_grad_(True)
+    eps = torch.tensor(0.1, device="cuda", requires_grad=True)
+    lo = torch.tensor(0.0, device="cuda", requires_grad=True)
+    hi = torch.tensor(1.0, device="cuda", requires_grad=True)
+    L = tonemap_luminance(x, eps, lo, hi, n_bins=5, n_scales=4, recompute=recompute)
+    g = torch.randn_like(L)
+    (L * g).sum().backward()
+    rx, ry = oracle.paper_radii(H, W, 4)
+    gv, gp = _gpu_grad(lum, 5, rx, ry, 0.1, "c32x2", g.cpu().numpy())
+    assert np.array_equal(x.grad.cpu().numpy().astype(np.float64), gv)
+    assert np.allclose([eps.grad.item(), lo.grad.item(), hi.grad.item()], gp, rtol=1e-6)
