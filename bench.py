@@ -36,7 +36,76 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", choices=["query", "tables", "backward"], default=None,
                     help="launch only that stage in the timed loop (profiling runs)")
+    ap.add_argument("--workload", choices=["image", "batch"], default="image",
+                    help="image: one 4000x3000 image (default); batch: 64 images of uneven "
+                         "size, persistent launches replayed from a HIP graph")
     return ap.parse_args()
+
+
+def bench_batch(args):
+    """64 images with H, W ~ U{360..4000}: aggregate MP/s of the graph-replayed batched
+    forward, the eager batched forward and 64 per-image launch sequences."""
+    import numpy as np
+    import torch
+
+    import paper_2102_01289_amd as tm
+    from paper_2102_01289_amd import autotune
+    from synth import WORKLOADS, gen_batch_shapes, gen_wdr
+
+    cfg = WORKLOADS["wdr_batch64_uneven"]
+    shapes = gen_batch_shapes(cfg["count"], 360, 4000, seed=cfg["shape_seed"])
+    dev = torch.device("cuda:0")
+    imgs = []
+    for i, (h, w) in enumerate(shapes):
+        imgs.append(torch.from_numpy(gen_wdr(h, w, cfg["K"], cfg["lo"], cfg["hi"],
+                                             cfg["seed"] + i).rgb).to(dev))
+        print(f"bench: generated image {i + 1}/{len(shapes)} ({h}x{w})", file=sys.stderr,
+              flush=True)
+    mpx = sum(h * w for h, w in shapes) / 1e6
+    cands = [(4, 16, 4), (2, 16, 4), (8, 16, 4), (4, 8, 4), (4, 32, 4)]
+    t, _ = autotune.tune_batch(imgs, args.n_bins, args.n_scales, args.prec, reps=3,
+                               use_cache=False, cands=cands)
+    b = tm.Batch(imgs, args.n_bins, args.n_scales, args.eps, prec=args.prec, tune=t)
+
+    def timed(fn, stream=None):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(e) / args.steps
+
+    eager_ms = timed(b.forward)
+    s = torch.cuda.Stream()
+    b.capture(s)
+    graph_ms = timed(lambda: b.replay(s), s)
+    mappers = []
+    for rgb in imgs:
+        _, H, W = rgb.shape
+        mappers.append(tm.ToneMapper(H, W, tm.make_params(args.n_bins, args.n_scales,
+                                                          eps=args.eps, H=H, W=W),
+                                     args.prec, tune=t, device=dev))
+    per_ms = timed(lambda: [m.run(r) for m, r in zip(mappers, imgs)])
+    line = {
+        "metric": "aggregate megapixels/s, batched forward (HIP graph) vs per-image launches",
+        "value": round(mpx / (graph_ms * 1e-3), 3), "unit": "megapixels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(graph_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"c32x2": "f32x2", "f32": "f32", "f64": "f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "wdr_batch64_uneven", "images": len(shapes),
+                   "megapixels": round(mpx, 3), "n_bins": args.n_bins,
+                   "n_scales": args.n_scales, "eps": args.eps, "sat_precision": args.prec,
+                   "tune": [t.tile_w_vec, t.tile_h, t.bin_chunk]},
+        "eager_batched_mp_s": round(mpx / (eager_ms * 1e-3), 3),
+        "per_image_launches_mp_s": round(mpx / (per_ms * 1e-3), 3),
+        "graph_over_per_image": round(per_ms / graph_ms, 4),
+    }
+    print(json.dumps(line), flush=True)
 
 
 def query_bytes_per_px(prec: str, n_bins: int) -> int:
@@ -78,6 +147,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "see DESIGN.md for how the path would shard", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     import numpy as np
     import torch

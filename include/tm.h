@@ -94,7 +94,7 @@ typedef struct {
 } tm_params;
 
 /* Scan tiling (chosen by the autotuner; NULL anywhere means the built-in default).
- *   tile_w_vec  columns per lane of one 64-lane tile: 1, 2, 4 or 8 (tile width 64*vec)
+ *   tile_w_vec  columns per lane of one 64-lane tile: 2, 4 or 8 (tile width 64*vec)
  *   tile_h      rows per tile, 1..256
  *   bin_chunk   histogram planes accumulated per pass over the image tile: 2, 4 or 8 */
 typedef struct {
@@ -213,6 +213,55 @@ tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W
                               const tm_params *p, const float *grad_out, int64_t ld_g,
                               float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
                               size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- batched forward */
+
+/* One image of a batch.  The method (Section II) is applied to each image independently,
+ * with its own statistics, tables and fields. */
+typedef struct {
+    const float *rgb;       /* planar RGB: channel c of (x, y) at rgb[c*ch_stride + y*ld_rgb + x] */
+    int64_t ch_stride, ld_rgb;
+    float *out;             /* tone-mapped luminance, H x W, row pitch ld_out */
+    int64_t ld_out;
+    int32_t H, W;
+    int32_t rx[TM_MAX_SCALES], ry[TM_MAX_SCALES];   /* this image's fields (tm_paper_radii) */
+} tm_image_desc;
+
+/* Opaque host object holding a batch's layout in the caller's workspace, the device-side
+ * descriptor tables and (after tm_batch_capture) an instantiated HIP graph. */
+typedef struct tm_batch tm_batch;
+
+/* Workspace for a batch: every image's luminance, statistics, integral image (prec),
+ * cumulative histogram (p->n_bins - 1 planes) and scan aggregates, plus the descriptor
+ * tables.  p supplies n_bins, n_scales, eps, ld_min, ld_max (its rx, ry are ignored). */
+size_t tm_batch_workspace_bytes(const tm_image_desc *descs, int32_t count, const tm_params *p,
+                                tm_sat_prec prec, const tm_tune *tune);
+
+/* Lay the batch out in ws and upload its descriptor tables on `stream` (asynchronously; the
+ * object keeps the host copies alive).  descs is read during the call only.  tune: one scan
+ * tiling for all images (NULL: 4 columns per lane, 16 rows, 4 planes per pass). */
+tm_status tm_batch_create(const tm_image_desc *descs, int32_t count, const tm_params *p,
+                          tm_sat_prec prec, const tm_tune *tune, void *ws, size_t ws_bytes,
+                          void *stream, tm_batch **batch);
+
+/* The forward of every image: one persistent launch per phase over all images (prologue
+ * parts, per-image finalize, scan stages 1-3, fused query) -- 6 launches, no host sync. */
+tm_status tm_batch_forward(tm_batch *batch, void *stream);
+
+/* Record tm_batch_forward into a HIP graph (stream must not be the null stream; nothing is
+ * executed).  A later call replaces the graph. */
+tm_status tm_batch_capture(tm_batch *batch, void *stream);
+
+/* Launch the captured graph on stream. */
+tm_status tm_batch_replay(tm_batch *batch, void *stream);
+
+tm_status tm_batch_destroy(tm_batch *batch);
+
+/* Device buffers of image i inside the workspace (luminance with its pitch, bin edges, the
+ * C32X2 offsets, the integral image origin and pitch, the cumulative planes). */
+tm_status tm_batch_image_buffers(const tm_batch *batch, int32_t i, float **lum, int64_t *ld_lum,
+                                 float **edges, float **offsets, void **sat, int64_t *ld_sat,
+                                 uint32_t **hist, int64_t *ld_hist, int64_t *plane_stride);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,7 @@ __all__ = [
     "TmError", "Table", "table_geometry", "paper_radii", "make_params", "tune",
     "tm_luminance", "tm_image_stats", "tm_prologue", "tm_integral_image",
     "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
-    "tm_tonemap_backward", "ToneMapper", "tonemap",
+    "tm_tonemap_backward", "ToneMapper", "tonemap", "Batch",
 ]
 
 
@@ -356,3 +356,81 @@ def tonemap(rgb: torch.Tensor, n_bins: int = 5, n_scales: int = 5, eps: float = 
     _, H, W = rgb.shape
     p = make_params(n_bins, n_scales, eps=eps, ld_min=ld_min, ld_max=ld_max, H=H, W=W)
     return ToneMapper(H, W, p, prec, device=rgb.device).run(rgb).clone()
+
+
+# ------------------------------------------------------------------------ batches
+class Batch:
+    """Forward of many images of uneven size: per-image buffers laid out in one workspace,
+    one persistent launch per phase over all images (tm_batch_forward), optionally recorded
+    once into a HIP graph and replayed (tm_batch_capture / tm_batch_replay)."""
+
+    def __init__(self, rgbs, n_bins: int = 5, n_scales: int = 5, eps: float = 0.1,
+                 ld_min: float = 0.0, ld_max: float = 1.0, prec: str = "c32x2", tune=None,
+                 stream=None):
+        self.count = len(rgbs)
+        self.rgbs = list(rgbs)
+        self.outs = []
+        self.descs = (_capi.TmImageDesc * self.count)()
+        for i, rgb in enumerate(self.rgbs):
+            if rgb.dtype != torch.float32 or rgb.dim() != 3 or rgb.shape[0] != 3 \
+                    or rgb.stride(2) != 1 or not rgb.is_cuda:
+                raise ValueError("each image must be a CUDA float32 [3, H, W] tensor")
+            _, H, W = rgb.shape
+            out = torch.empty((H, W), dtype=torch.float32, device=rgb.device)
+            self.outs.append(out)
+            d = self.descs[i]
+            d.rgb, d.ch_stride, d.ld_rgb = rgb.data_ptr(), rgb.stride(0), rgb.stride(1)
+            d.out, d.ld_out, d.H, d.W = out.data_ptr(), out.stride(0), H, W
+            rx, ry = paper_radii(H, W, n_scales)
+            for j in range(n_scales):
+                d.rx[j], d.ry[j] = rx[j], ry[j]
+        self.params = make_params(n_bins, n_scales, [0] * n_scales, [0] * n_scales, eps,
+                                  ld_min, ld_max)
+        self.prec = prec
+        self.tune = tune
+        pc = _capi.SAT_PREC[prec]
+        nbytes = _lib().tm_batch_workspace_bytes(self.descs, self.count,
+                                                 ctypes.byref(self.params), pc, _tune_ref(tune))
+        if nbytes == 0:
+            raise TmError("tm_batch_workspace_bytes", -1)
+        self.ws = _ws(nbytes, self.rgbs[0].device)
+        h = ctypes.c_void_p()
+        _ck("tm_batch_create", _lib().tm_batch_create(
+            self.descs, self.count, ctypes.byref(self.params), pc, _tune_ref(tune), _vp(self.ws),
+            self.ws.numel(), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def forward(self, stream=None):
+        _ck("tm_batch_forward", _lib().tm_batch_forward(self.handle, _stream(stream)))
+        return self.outs
+
+    def capture(self, stream):
+        """Record forward() into a HIP graph on a non-null stream (nothing runs)."""
+        _ck("tm_batch_capture", _lib().tm_batch_capture(self.handle, _stream(stream)))
+
+    def replay(self, stream=None):
+        _ck("tm_batch_replay", _lib().tm_batch_replay(self.handle, _stream(stream)))
+        return self.outs
+
+    def image_buffers(self, i: int):
+        P = ctypes.c_void_p
+        lum, edges, offs, sat, hist = P(), P(), P(), P(), P()
+        ldl, lds, ldh, ps = (ctypes.c_int64() for _ in range(4))
+        _ck("tm_batch_image_buffers", _lib().tm_batch_image_buffers(
+            self.handle, i, ctypes.byref(lum), ctypes.byref(ldl), ctypes.byref(edges),
+            ctypes.byref(offs), ctypes.byref(sat), ctypes.byref(lds), ctypes.byref(hist),
+            ctypes.byref(ldh), ctypes.byref(ps)))
+        return dict(lum=lum.value, ld_lum=ldl.value, edges=edges.value, offsets=offs.value,
+                    sat=sat.value, ld_sat=lds.value, hist=hist.value, ld_hist=ldh.value,
+                    plane_stride=ps.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib().tm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -28,6 +28,13 @@ class TmTune(ctypes.Structure):
                 ("bin_chunk", ctypes.c_int32)]
 
 
+class TmImageDesc(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_void_p), ("ch_stride", ctypes.c_int64),
+                ("ld_rgb", ctypes.c_int64), ("out", ctypes.c_void_p), ("ld_out", ctypes.c_int64),
+                ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("rx", ctypes.c_int32 * TM_MAX_SCALES), ("ry", ctypes.c_int32 * TM_MAX_SCALES)]
+
+
 # (name, restype, argtypes) for every entry point of include/tm.h
 P, I32, I64, SZ, F, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t,
                          ctypes.c_float, ctypes.c_double)
@@ -53,6 +60,15 @@ SIGNATURES = {
     "tm_tonemap_forward": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
                                           I64, P, PP, P, I64, P]),
     "tm_backward_workspace_bytes": (SZ, [I32, I32, PP]),
+    "tm_batch_workspace_bytes": (SZ, [ctypes.POINTER(TmImageDesc), I32, PP, ctypes.c_int, PT]),
+    "tm_batch_create": (ctypes.c_int, [ctypes.POINTER(TmImageDesc), I32, PP, ctypes.c_int, PT, P,
+                                       SZ, P, ctypes.POINTER(P)]),
+    "tm_batch_forward": (ctypes.c_int, [P, P]),
+    "tm_batch_capture": (ctypes.c_int, [P, P]),
+    "tm_batch_replay": (ctypes.c_int, [P, P]),
+    "tm_batch_destroy": (ctypes.c_int, [P]),
+    "tm_batch_image_buffers": (ctypes.c_int, [P, I32] + [ctypes.POINTER(P), PI64] +
+                               [ctypes.POINTER(P)] * 3 + [PI64, ctypes.POINTER(P), PI64, PI64]),
     "tm_tonemap_backward": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
                                            I64, P, PP, P, I64, P, I64, P, P, SZ, P]),
 }

@@ -1,0 +1,305 @@
+// tm_batch.cpp -- batched forward: many images of uneven size in one persistent launch per
+// phase, recordable as one HIP graph.
+//
+// tm_batch_create lays every image's buffers out in the caller's workspace, builds the
+// per-image kernel descriptors (StatsK, ScanK, FwdK) and prefix sums of each phase's work
+// items, and uploads them; tm_batch_forward then launches six kernels whose grids walk the
+// flattened work of all images.  Every image keeps exactly the reduction structure and scan
+// tiling of a single-image call with the same tiling, so batched outputs equal per-image
+// outputs bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tm.h"
+#include "tm_internal.h"
+
+using namespace tmo;
+
+struct tm_batch {
+    int count = 0, prec = 0;
+    ScanTune tune{};
+    std::vector<StatsK> sk;
+    std::vector<ScanK> ck;
+    std::vector<FwdK> fk;
+    std::vector<int64_t> parts, tiles, items, qtiles;   // prefixes, count + 1 each
+    StatsK *d_sk = nullptr;
+    ScanK *d_ck = nullptr;
+    FwdK *d_fk = nullptr;
+    int64_t *d_parts = nullptr, *d_tiles = nullptr, *d_items = nullptr, *d_qtiles = nullptr;
+    unsigned g_stats = 1, g_tiles = 1, g_items = 1, g_query = 8;
+    struct Bufs {
+        float *lum, *edges, *offsets;
+        int64_t ld_lum;
+        void *sat;
+        int64_t ld_sat;
+        uint32_t *hist;
+        int64_t ld_hist, plane_stride;
+    };
+    std::vector<Bufs> bufs;
+    std::vector<char> host_tables;   // staging of the uploaded descriptor tables
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t up(size_t a, size_t b) { return (a + b - 1) / b * b; }
+
+size_t entry_bytes(int prec) { return prec == TM_SAT_F32 ? 8 : 16; }
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off = up(off + bytes, kAlign);
+        return o;
+    }
+    template <class T>
+    T *ptr(size_t o) const {
+        return base ? reinterpret_cast<T *>(base + o) : nullptr;
+    }
+};
+
+tm_status check(const tm_image_desc *d, int32_t count, const tm_params *p, tm_sat_prec prec,
+                const tm_tune *tune, ScanTune &t) {
+    if (!d || count < 1 || !p) return TM_ERR_ARG;
+    if (prec != TM_SAT_F32 && prec != TM_SAT_C32X2 && prec != TM_SAT_F64) return TM_ERR_ARG;
+    if (p->n_bins < 1 || p->n_bins > TM_MAX_BINS || p->n_scales < 1 ||
+        p->n_scales > TM_MAX_SCALES)
+        return TM_ERR_ARG;
+    if (!(p->eps > 0.f) || !(p->ld_max > p->ld_min)) return TM_ERR_ARG;
+    t = tune ? ScanTune{tune->tile_w_vec, tune->tile_h, tune->bin_chunk} : ScanTune{4, 16, 4};
+    if (!scan_tune_valid(t)) return TM_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        const tm_image_desc &x = d[i];
+        if (x.H < 1 || x.W < 1 || (int64_t)x.H * x.W >= ((int64_t)1 << 31)) return TM_ERR_SHAPE;
+        if (!x.rgb || !x.out) return TM_ERR_ARG;
+        if (x.ld_rgb < x.W || x.ld_out < x.W || x.ch_stride < (int64_t)x.H * x.ld_rgb)
+            return TM_ERR_SHAPE;
+        for (int j = 0; j < p->n_scales; ++j)
+            if (x.rx[j] < 0 || x.ry[j] < 0) return TM_ERR_ARG;
+    }
+    return TM_OK;
+}
+
+// Lays the batch out from `base` (nullptr: sizing only) and fills the host descriptors.
+size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int prec,
+              const ScanTune &t, char *base, tm_batch *b) {
+    Carver c{base};
+    const size_t o_sk = c.take(sizeof(StatsK) * count);
+    const size_t o_ck = c.take(sizeof(ScanK) * count);
+    const size_t o_fk = c.take(sizeof(FwdK) * count);
+    const size_t o_pf = c.take(sizeof(int64_t) * 4 * (count + 1));
+    const int n = p->n_bins;
+    QueryParams q{};
+    q.n_bins = n;
+    q.n_scales = p->n_scales;
+    q.eps = p->eps;
+    q.ld_min = p->ld_min;
+    q.ld_max = p->ld_max;
+    if (b) {
+        b->sk.resize(count);
+        b->ck.resize(count);
+        b->fk.resize(count);
+        b->bufs.resize(count);
+        b->parts.assign(count + 1, 0);
+        b->tiles.assign(count + 1, 0);
+        b->items.assign(count + 1, 0);
+        b->qtiles.assign(count + 1, 0);
+    }
+    for (int i = 0; i < count; ++i) {
+        const tm_image_desc &x = d[i];
+        const int H = x.H, W = x.W;
+        int64_t ld, org, elems;
+        tm_table_geometry(H, W, &ld, &org, &elems);
+        const int64_t ld_lum = (W + 63) / 64 * 64;
+        const size_t o_lum = c.take(sizeof(float) * (size_t)H * ld_lum);
+        const size_t o_edges = c.take(sizeof(float) * 260);
+        const size_t o_part = c.take(sizeof(StatsPartial) * (size_t)stats_blocks(H, W));
+        const size_t o_sat = c.take(entry_bytes(prec) * (size_t)elems);
+        const size_t o_hist = c.take(4 * (size_t)elems * (size_t)(n > 1 ? n - 1 : 1));
+        const ScanPlan sp = make_scan_plan(H, W, prec, n - 1, t);
+        const size_t o_scan = c.take(sp.total);
+        if (!b) continue;
+        float *lum = c.ptr<float>(o_lum);
+        float *edges = c.ptr<float>(o_edges);
+        float *offsets = edges + 256;
+        float *minmax = edges + 258;
+        void *sat = c.ptr<char>(o_sat) + org * entry_bytes(prec);
+        uint32_t *hist = c.ptr<uint32_t>(o_hist) + org;
+        b->bufs[i] = {lum, edges, offsets, ld_lum, sat, ld, hist, ld, elems};
+        b->sk[i] = make_statsk(x.rgb, x.ch_stride, x.ld_rgb, nullptr, 0, lum, ld_lum, H, W, n,
+                               edges, offsets, minmax, c.ptr<StatsPartial>(o_part));
+        ScanArgs a{};
+        a.v = lum;
+        a.ld_v = ld_lum;
+        a.H = H;
+        a.W = W;
+        a.sat_prec = prec;
+        a.offsets = offsets;
+        a.sat = sat;
+        a.ld_sat = ld;
+        a.edges = edges;
+        a.n_bins = n;
+        a.layout = TM_HIST_CUMULATIVE;
+        a.n_planes = n - 1;
+        a.hist = n > 1 ? hist : nullptr;
+        a.ld_hist = ld;
+        a.plane_stride = elems;
+        b->ck[i] = make_scank(a, sp, c.ptr<char>(o_scan));
+        QueryParams qi = q;
+        for (int j = 0; j < TM_MAX_SCALES; ++j) {
+            qi.rx[j] = j < p->n_scales ? x.rx[j] : 0;
+            qi.ry[j] = j < p->n_scales ? x.ry[j] : 0;
+        }
+        b->fk[i] = make_fwdk(lum, ld_lum, H, W, sat, ld, offsets, n > 1 ? hist : nullptr, ld,
+                             elems, edges, qi, x.out, x.ld_out);
+        b->parts[i + 1] = b->parts[i] + b->sk[i].nparts;
+        b->tiles[i + 1] = b->tiles[i] + (int64_t)sp.tiles_x * sp.tiles_y;
+        b->items[i + 1] = b->items[i] + scan_stage2_items(b->ck[i], true);
+        b->qtiles[i + 1] = b->qtiles[i] + query_tiles(H, W);
+    }
+    if (b) {
+        b->d_sk = c.ptr<StatsK>(o_sk);
+        b->d_ck = c.ptr<ScanK>(o_ck);
+        b->d_fk = c.ptr<FwdK>(o_fk);
+        int64_t *pf = c.ptr<int64_t>(o_pf);
+        b->d_parts = pf;
+        b->d_tiles = pf + (count + 1);
+        b->d_items = pf + 2 * (count + 1);
+        b->d_qtiles = pf + 3 * (count + 1);
+    }
+    return c.off;
+}
+
+tm_status from_hip(hipError_t e) { return e == hipSuccess ? TM_OK : TM_ERR_HIP; }
+
+unsigned clampu(int64_t v, int64_t lo, int64_t hi) {
+    return (unsigned)(v < lo ? lo : (v > hi ? hi : v));
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tm_batch_workspace_bytes(const tm_image_desc *descs, int32_t count, const tm_params *p,
+                                tm_sat_prec prec, const tm_tune *tune) {
+    ScanTune t;
+    if (check(descs, count, p, prec, tune, t) != TM_OK) return 0;
+    return layout(descs, count, p, (int)prec, t, nullptr, nullptr);
+}
+
+tm_status tm_batch_create(const tm_image_desc *descs, int32_t count, const tm_params *p,
+                          tm_sat_prec prec, const tm_tune *tune, void *ws, size_t ws_bytes,
+                          void *stream, tm_batch **batch) {
+    if (!batch) return TM_ERR_ARG;
+    *batch = nullptr;
+    ScanTune t;
+    tm_status st = check(descs, count, p, prec, tune, t);
+    if (st != TM_OK) return st;
+    const size_t need = layout(descs, count, p, (int)prec, t, nullptr, nullptr);
+    if (!ws || ((uintptr_t)ws & (kAlign - 1)) || ws_bytes < need) return TM_ERR_WORKSPACE;
+    tm_batch *b = new (std::nothrow) tm_batch;
+    if (!b) return TM_ERR_HIP;
+    b->count = count;
+    b->prec = (int)prec;
+    b->tune = t;
+    layout(descs, count, p, (int)prec, t, static_cast<char *>(ws), b);
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    b->g_stats = clampu(b->parts[count], 1, 4 * (int64_t)cus);
+    b->g_tiles = clampu((b->tiles[count] + 3) / 4, 1, 8 * (int64_t)cus);
+    b->g_items = clampu((b->items[count] + 255) / 256, 1, 4 * (int64_t)cus);
+    b->g_query = clampu((b->qtiles[count] + 7) / 8 * 8, 8, 8 * (int64_t)cus) / 8 * 8;
+    // upload the descriptor tables (contiguous in ws from d_sk to the end of the prefixes)
+    const size_t n_sk = sizeof(StatsK) * count, n_ck = sizeof(ScanK) * count,
+                 n_fk = sizeof(FwdK) * count, n_pf = sizeof(int64_t) * (count + 1);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(b->d_sk, b->sk.data(), n_sk, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_ck, b->ck.data(), n_ck, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_fk, b->fk.data(), n_fk, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_parts, b->parts.data(), n_pf, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_tiles, b->tiles.data(), n_pf, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_items, b->items.data(), n_pf, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_qtiles, b->qtiles.data(), n_pf, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host vectors back the copies
+    if (e != hipSuccess) {
+        delete b;
+        return TM_ERR_HIP;
+    }
+    *batch = b;
+    return TM_OK;
+}
+
+tm_status tm_batch_forward(tm_batch *b, void *stream) {
+    if (!b) return TM_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_stats_batch(b->d_sk, b->d_parts, b->count, b->g_stats, s);
+    if (e != hipSuccess) return TM_ERR_HIP;
+    BatchScan bs{b->d_ck, b->d_tiles, b->d_items, b->count, b->prec, b->tune.vec, b->tune.chunk,
+                 b->g_tiles, b->g_items};
+    e = launch_tables_batch(bs, s);
+    if (e != hipSuccess) return TM_ERR_HIP;
+    return from_hip(launch_forward_batch(b->d_fk, b->d_qtiles, b->count, b->prec, b->g_query, s));
+}
+
+tm_status tm_batch_capture(tm_batch *b, void *stream) {
+    if (!b || !stream) return TM_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return TM_ERR_HIP;
+    tm_status st = tm_batch_forward(b, stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != TM_OK || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return st != TM_OK ? st : TM_ERR_HIP;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return TM_ERR_HIP;
+    }
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->graph = g;
+    b->exec = x;
+    return TM_OK;
+}
+
+tm_status tm_batch_replay(tm_batch *b, void *stream) {
+    if (!b || !b->exec) return TM_ERR_ARG;
+    return from_hip(hipGraphLaunch(b->exec, (hipStream_t)stream));
+}
+
+tm_status tm_batch_destroy(tm_batch *b) {
+    if (!b) return TM_ERR_ARG;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    delete b;
+    return TM_OK;
+}
+
+tm_status tm_batch_image_buffers(const tm_batch *b, int32_t i, float **lum, int64_t *ld_lum,
+                                 float **edges, float **offsets, void **sat, int64_t *ld_sat,
+                                 uint32_t **hist, int64_t *ld_hist, int64_t *plane_stride) {
+    if (!b || i < 0 || i >= b->count) return TM_ERR_ARG;
+    const auto &x = b->bufs[i];
+    if (lum) *lum = x.lum;
+    if (ld_lum) *ld_lum = x.ld_lum;
+    if (edges) *edges = x.edges;
+    if (offsets) *offsets = x.offsets;
+    if (sat) *sat = x.sat;
+    if (ld_sat) *ld_sat = x.ld_sat;
+    if (hist) *hist = x.hist;
+    if (ld_hist) *ld_hist = x.ld_hist;
+    if (plane_stride) *plane_stride = x.plane_stride;
+    return TM_OK;
+}
+
+}  // extern "C"

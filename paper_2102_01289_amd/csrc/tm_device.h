@@ -175,4 +175,15 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
     return k * q + (k < r ? k : r) + i;
 }
 
+// Batched launches walk one flattened list of work items spanning every image; the image
+// of item g is the last i with prefix[i] <= g (prefix has count+1 entries, prefix[0] = 0).
+__device__ __forceinline__ int find_image(const int64_t *prefix, int count, int64_t g) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 }  // namespace tmo

@@ -13,8 +13,27 @@ struct StatsPartial {          // one per reduction block, 32 bytes
     double s1, s2;
     double pad;
 };
+// One image of the prologue: RGB (or luminance) in, luminance out, nparts partials.
+struct StatsK {
+    const float *rgb;
+    int64_t ch_stride, ld_rgb;
+    const float *lum_in;
+    int64_t ld_in;
+    float *lum_out;
+    int64_t ld_out;
+    int H, W, vec_in, vec_out, nparts, n_bins;
+    StatsPartial *partials;
+    float *edges, *offsets, *minmax;
+};
 constexpr int kStatsMaxBlocks = 1024;
 int stats_blocks(int H, int W);
+StatsK make_statsk(const float *rgb, int64_t ch_stride, int64_t ld_rgb, const float *lum_in,
+                   int64_t ld_in, float *lum_out, int64_t ld_out, int H, int W, int n_bins,
+                   float *edges, float *offsets, float *minmax, StatsPartial *partials);
+// Prologue of a batch: parts of every image in one persistent launch, then one finalize
+// block per image (device arrays ks[count], part_prefix[count+1]).
+hipError_t launch_stats_batch(const StatsK *ks, const int64_t *part_prefix, int count,
+                              unsigned grid, hipStream_t s);
 
 hipError_t launch_luminance(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int H, int W,
                             float *lum, int64_t ld_lum, hipStream_t s);
@@ -46,6 +65,30 @@ struct ScanPlan {
 };
 ScanPlan make_scan_plan(int H, int W, int sat_prec, int n_planes, const ScanTune &t);
 
+// Kernel parameters of one image's three-stage scan (device-side copy in batched mode).
+struct ScanK {
+    const float *v;
+    int64_t ld_v;
+    int H, W, th, tiles_x, tiles_y;
+    int vec_load;                 // rows of v are 16-byte aligned
+    const float *offsets;
+    void *sat;
+    int64_t ld_sat;
+    const float *edges;
+    int n_bins, layout, n_planes;
+    uint32_t *hist;
+    int64_t ld_hist, plane_stride;
+    // aggregates (each an array of quantities; see ScanPlan)
+    void *rs_sat, *cs_sat, *tt_sat, *xc_sat, *cse_sat, *tte_sat;
+    uint32_t *rs_h, *cs_h, *tt_h, *xc_h, *cse_h, *tte_h;
+    // adjoint mode: the two FP64 planes to scan (row-major, pitch ld_d, already in reversed
+    // pixel order) and the gradient written back in forward order, dv = s1 + 2 v s2
+    const double2 *dsrc;
+    int64_t ld_d;
+    float *gv;
+    int64_t ld_gv;
+};
+
 struct ScanArgs {
     const float *v;
     int64_t ld_v;
@@ -62,6 +105,19 @@ struct ScanArgs {
     int64_t ld_hist, plane_stride;
 };
 hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipStream_t s);
+ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws);
+
+// Integral image + cumulative histogram of a whole batch: three persistent launches over
+// flattened work lists (device arrays: ks[count], tile_prefix[count+1], item_prefix[count+1]).
+struct BatchScan {
+    const ScanK *ks;
+    const int64_t *tile_prefix, *item_prefix;
+    int count, prec, vec, chunk;
+    unsigned grid_tiles, grid_items;
+};
+hipError_t launch_tables_batch(const BatchScan &b, hipStream_t s);
+// Items of stage 2 of one image (thread-level): nq*H + nq*W + nq*tiles_y.
+int64_t scan_stage2_items(const ScanK &k, bool sat);
 
 // ---------------------------------------------------------------- query (a4)
 struct QueryParams {
@@ -69,6 +125,32 @@ struct QueryParams {
     int rx[8], ry[8];
     float eps, ld_min, ld_max;
 };
+
+struct FwdK {
+    const float *v;
+    int64_t ld_v;
+    int H, W;
+    const void *sat;
+    int64_t ld_sat;
+    const float *offsets;
+    const uint32_t *hist;
+    int64_t ld_hist, plane_stride;
+    const float *edges;
+    QueryParams p;
+    float *out;
+    int64_t ld_out;
+    int tiles_x;
+};
+constexpr int kQueryRows = 4;   // a query block covers 64 columns x 4 rows
+int64_t query_tiles(int H, int W);
+// Fused query of a batch: one persistent launch (grid a multiple of 8) over every image's
+// tiles (device arrays ks[count], tile_prefix[count+1]).
+hipError_t launch_forward_batch(const FwdK *ks, const int64_t *tile_prefix, int count, int prec,
+                                unsigned grid, hipStream_t s);
+FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int64_t ld_sat,
+                const float *offsets, const uint32_t *hist, int64_t ld_hist,
+                int64_t plane_stride, const float *edges, const QueryParams &p, float *out,
+                int64_t ld_out);
 hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void *sat,
                           int64_t ld_sat, int prec, const float *offsets, const uint32_t *hist,
                           int64_t ld_hist, int64_t plane_stride, const float *edges,

@@ -58,26 +58,25 @@ __device__ Stat block_reduce(Stat st) {
     return r;
 }
 
+// One reduction part of one image: row segments part, part + nparts, ... (so the partials,
+// and hence the statistics, do not depend on how parts are scheduled).
 template <bool FROM_RGB, bool STATS>
-__global__ void __launch_bounds__(kBlock)
-lum_stats_kernel(const float *__restrict__ rgb, int64_t ch_stride, int64_t ld_rgb,
-                 const float *__restrict__ lum_in, int64_t ld_in, float *__restrict__ lum_out,
-                 int64_t ld_out, int H, int W, bool vec_in, bool vec_out,
-                 StatsPartial *__restrict__ partials) {
+__device__ void stats_part(const StatsK &k, int part, int nparts) {
     Stat st{INFINITY, -INFINITY, 0.0, 0.0};
+    const int H = k.H, W = k.W;
     const int segs_per_row = (W + kSeg - 1) / kSeg;
     const int64_t nseg = (int64_t)H * segs_per_row;
-    for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+    for (int64_t seg = part; seg < nseg; seg += nparts) {
         const int y = (int)(seg / segs_per_row);
         const int x = (int)(seg % segs_per_row) * kSeg + (int)threadIdx.x * 4;
         if (x >= W) continue;
         float v[4];
         const bool full = x + 4 <= W;
         if (FROM_RGB) {
-            const float *R = rgb + (int64_t)y * ld_rgb + x;
-            const float *G = R + ch_stride;
-            const float *B = G + ch_stride;
-            if (full && vec_in) {
+            const float *R = k.rgb + (int64_t)y * k.ld_rgb + x;
+            const float *G = R + k.ch_stride;
+            const float *B = G + k.ch_stride;
+            if (full && k.vec_in) {
                 float4 r = *reinterpret_cast<const float4 *>(R);
                 float4 g = *reinterpret_cast<const float4 *>(G);
                 float4 b = *reinterpret_cast<const float4 *>(B);
@@ -89,16 +88,16 @@ lum_stats_kernel(const float *__restrict__ rgb, int64_t ch_stride, int64_t ld_rg
                 for (int i = 0; i < 4; ++i)
                     v[i] = (x + i < W) ? luminance(R[i], G[i], B[i]) : 0.f;
             }
-            float *o = lum_out + (int64_t)y * ld_out + x;
-            if (full && vec_out) {
+            float *o = k.lum_out + (int64_t)y * k.ld_out + x;
+            if (full && k.vec_out) {
                 *reinterpret_cast<float4 *>(o) = make_float4(v[0], v[1], v[2], v[3]);
             } else {
                 for (int i = 0; i < 4; ++i)
                     if (x + i < W) o[i] = v[i];
             }
         } else {
-            const float *L = lum_in + (int64_t)y * ld_in + x;
-            if (full && vec_in) {
+            const float *L = k.lum_in + (int64_t)y * k.ld_in + x;
+            if (full && k.vec_in) {
                 float4 l = *reinterpret_cast<const float4 *>(L);
                 v[0] = l.x; v[1] = l.y; v[2] = l.z; v[3] = l.w;
             } else {
@@ -119,8 +118,24 @@ lum_stats_kernel(const float *__restrict__ rgb, int64_t ch_stride, int64_t ld_rg
             p.s1 = r.s1;
             p.s2 = r.s2;
             p.pad = 0.0;
-            partials[blockIdx.x] = p;
+            k.partials[part] = p;
         }
+    }
+}
+
+template <bool FROM_RGB, bool STATS>
+__global__ void __launch_bounds__(kBlock) lum_stats_kernel(StatsK k) {
+    stats_part<FROM_RGB, STATS>(k, blockIdx.x, gridDim.x);
+}
+
+// Batched prologue: item g is part (g - prefix[i]) of image i.
+__global__ void __launch_bounds__(kBlock) lum_stats_batch(const StatsK *ks, const int64_t *prefix,
+                                                          int count) {
+    const int64_t total = prefix[count];
+    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const int i = find_image(prefix, count, g);
+        stats_part<true, true>(ks[i], (int)(g - prefix[i]), ks[i].nparts);
+        __syncthreads();
     }
 }
 
@@ -221,33 +236,39 @@ __device__ float edge_value(int k, int n, float a, float b) {
     return f32_next(c);
 }
 
-__global__ void __launch_bounds__(kBlock)
-stats_finalize_kernel(const StatsPartial *__restrict__ partials, int nparts, int H, int W,
-                      int n_bins, float *__restrict__ edges, float *__restrict__ offsets,
-                      float *__restrict__ minmax) {
+__device__ void finalize_body(const StatsK &k) {
     Stat st{INFINITY, -INFINITY, 0.0, 0.0};
-    for (int i = threadIdx.x; i < nparts; i += kBlock) {
-        StatsPartial p = partials[i];
+    for (int i = threadIdx.x; i < k.nparts; i += kBlock) {
+        StatsPartial p = k.partials[i];
         st = stat_merge(st, Stat{p.mn, p.mx, p.s1, p.s2});
     }
     const Stat r = block_reduce(st);
-    const double np = (double)H * (double)W;
+    const double np = (double)k.H * (double)k.W;
     if (threadIdx.x == 0) {
-        if (offsets) {
-            offsets[0] = (float)(r.s1 / np);
-            offsets[1] = (float)(r.s2 / np);
+        if (k.offsets) {
+            k.offsets[0] = (float)(r.s1 / np);
+            k.offsets[1] = (float)(r.s2 / np);
         }
-        if (minmax) {
-            minmax[0] = r.mn;
-            minmax[1] = r.mx;
+        if (k.minmax) {
+            k.minmax[0] = r.mn;
+            k.minmax[1] = r.mx;
         }
     }
     const float a = fmaxf(r.mn, FLT_MIN);
     const float b = r.mx;
-    for (int k = 1 + (int)threadIdx.x; k < n_bins; k += kBlock) {
+    for (int kk = 1 + (int)threadIdx.x; kk < k.n_bins; kk += kBlock) {
         float e = INFINITY;
-        if (b > a) e = edge_value(k, n_bins, a, b);
-        edges[k - 1] = e;
+        if (b > a) e = edge_value(kk, k.n_bins, a, b);
+        k.edges[kk - 1] = e;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) stats_finalize_kernel(StatsK k) { finalize_body(k); }
+
+__global__ void __launch_bounds__(kBlock) stats_finalize_batch(const StatsK *ks, int count) {
+    for (int i = blockIdx.x; i < count; i += gridDim.x) {
+        finalize_body(ks[i]);
+        __syncthreads();
     }
 }
 
@@ -260,14 +281,38 @@ int stats_blocks(int H, int W) {
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+StatsK make_statsk(const float *rgb, int64_t ch_stride, int64_t ld_rgb, const float *lum_in,
+                   int64_t ld_in, float *lum_out, int64_t ld_out, int H, int W, int n_bins,
+                   float *edges, float *offsets, float *minmax, StatsPartial *partials) {
+    StatsK k{};
+    k.rgb = rgb;
+    k.ch_stride = ch_stride;
+    k.ld_rgb = ld_rgb;
+    k.lum_in = lum_in;
+    k.ld_in = ld_in;
+    k.lum_out = lum_out;
+    k.ld_out = ld_out;
+    k.H = H;
+    k.W = W;
+    k.vec_in = rgb ? (aligned16(rgb) && ld_rgb % 4 == 0 && ch_stride % 4 == 0)
+                   : (aligned16(lum_in) && ld_in % 4 == 0);
+    k.vec_out = lum_out && aligned16(lum_out) && ld_out % 4 == 0;
+    k.nparts = stats_blocks(H, W);
+    k.n_bins = n_bins;
+    k.partials = partials;
+    k.edges = edges;
+    k.offsets = offsets;
+    k.minmax = minmax;
+    return k;
+}
+
 hipError_t launch_luminance(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int H, int W,
                             float *lum, int64_t ld_lum, hipStream_t s) {
-    const bool vin = aligned16(rgb) && (ld_rgb % 4 == 0) && (ch_stride % 4 == 0);
-    const bool vout = aligned16(lum) && (ld_lum % 4 == 0);
+    StatsK k = make_statsk(rgb, ch_stride, ld_rgb, nullptr, 0, lum, ld_lum, H, W, 1, nullptr,
+                           nullptr, nullptr, nullptr);
     const int64_t nseg = (int64_t)H * ((W + kSeg - 1) / kSeg);
     const int grid = (int)(nseg < 65536 ? nseg : 65536);
-    hipLaunchKernelGGL((lum_stats_kernel<true, false>), dim3(grid), dim3(kBlock), 0, s, rgb,
-                       ch_stride, ld_rgb, nullptr, 0, lum, ld_lum, H, W, vin, vout, nullptr);
+    hipLaunchKernelGGL((lum_stats_kernel<true, false>), dim3(grid), dim3(kBlock), 0, s, k);
     return hipGetLastError();
 }
 
@@ -275,23 +320,25 @@ hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, con
                         int64_t ld_lum_in, float *lum_out, int64_t ld_lum_out, int H, int W,
                         int n_bins, float *edges, float *offsets, float *minmax,
                         StatsPartial *partials, hipStream_t s) {
-    const int nb = stats_blocks(H, W);
-    if (rgb) {
-        const bool vin = aligned16(rgb) && (ld_rgb % 4 == 0) && (ch_stride % 4 == 0);
-        const bool vout = aligned16(lum_out) && (ld_lum_out % 4 == 0);
-        hipLaunchKernelGGL((lum_stats_kernel<true, true>), dim3(nb), dim3(kBlock), 0, s, rgb,
-                           ch_stride, ld_rgb, nullptr, 0, lum_out, ld_lum_out, H, W, vin, vout,
-                           partials);
-    } else {
-        const bool vin = aligned16(lum_in) && (ld_lum_in % 4 == 0);
-        hipLaunchKernelGGL((lum_stats_kernel<false, true>), dim3(nb), dim3(kBlock), 0, s,
-                           nullptr, 0, 0, lum_in, ld_lum_in, nullptr, 0, H, W, vin, false,
-                           partials);
-    }
+    StatsK k = make_statsk(rgb, ch_stride, ld_rgb, lum_in, ld_lum_in, lum_out, ld_lum_out, H, W,
+                           n_bins, edges, offsets, minmax, partials);
+    if (rgb)
+        hipLaunchKernelGGL((lum_stats_kernel<true, true>), dim3(k.nparts), dim3(kBlock), 0, s, k);
+    else
+        hipLaunchKernelGGL((lum_stats_kernel<false, true>), dim3(k.nparts), dim3(kBlock), 0, s, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, partials, nb, H, W,
-                       n_bins, edges, offsets, minmax);
+    hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_batch(const StatsK *ks, const int64_t *part_prefix, int count,
+                              unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL(lum_stats_batch, dim3(grid), dim3(kBlock), 0, s, ks, part_prefix, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned fg = (unsigned)(count < 4096 ? count : 4096);
+    hipLaunchKernelGGL(stats_finalize_batch, dim3(fg), dim3(kBlock), 0, s, ks, count);
     return hipGetLastError();
 }
 

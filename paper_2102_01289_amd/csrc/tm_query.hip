@@ -17,23 +17,8 @@ namespace tmo {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRows = kBlock / kWave;   // a block covers 64 columns x 4 rows
+constexpr int kRows = kQueryRows;   // a block covers 64 columns x 4 rows
 
-struct FwdK {
-    const float *v;
-    int64_t ld_v;
-    int H, W;
-    const void *sat;
-    int64_t ld_sat;
-    const float *offsets;
-    const uint32_t *hist;
-    int64_t ld_hist, plane_stride;
-    const float *edges;
-    QueryParams p;
-    float *out;
-    int64_t ld_out;
-    int tiles_x;
-};
 
 template <int P>
 struct Box;
@@ -88,14 +73,14 @@ struct Box<kF64> {
     }
 };
 
+// One 64 x 4 tile of one image.  sh_edges is the block's copy of the image's bin edges.
 template <int P>
-__global__ void __launch_bounds__(kBlock) forward_kernel(FwdK k) {
-    __shared__ float sh_edges[256];
+__device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float *sh_edges) {
     const int ne = k.p.n_bins - 1;
+    __syncthreads();   // the previous tile of this block may still read sh_edges
     for (int i = threadIdx.x; i < ne; i += kBlock) sh_edges[i] = k.edges[i];
     __syncthreads();
 
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = (int)(tile % (uint32_t)k.tiles_x), ty = (int)(tile / (uint32_t)k.tiles_x);
     const int x = tx * kWave + lane_id();
     const int y = ty * kRows + (int)(threadIdx.x / kWave);
@@ -135,12 +120,54 @@ __global__ void __launch_bounds__(kBlock) forward_kernel(FwdK k) {
     k.out[(int64_t)y * k.ld_out + x] = den > 0.f ? num / den : lsum / (float)k.p.n_scales;
 }
 
+template <int P>
+__global__ void __launch_bounds__(kBlock) forward_kernel(FwdK k) {
+    __shared__ float sh_edges[256];
+    forward_tile<P>(k, xcd_tile(blockIdx.x, gridDim.x), sh_edges);
+}
+
+// Batched query: a persistent grid whose blocks on XCD x (block % 8) walk the x-th eighth of
+// the flattened tile list, so each XCD's L2 sees one contiguous run of tiles.
+template <int P>
+__global__ void __launch_bounds__(kBlock) forward_batch(const FwdK *ks, const int64_t *prefix,
+                                                       int count) {
+    __shared__ float sh_edges[256];
+    const int64_t total = prefix[count];
+    const int64_t per = (total + 7) / 8;
+    const int64_t xcd = blockIdx.x % 8, nb = gridDim.x / 8;
+    const int64_t end = min(total, (xcd + 1) * per);
+    for (int64_t g = xcd * per + blockIdx.x / 8; g < end; g += nb) {
+        const int i = find_image(prefix, count, g);
+        forward_tile<P>(ks[i], (uint32_t)(g - prefix[i]), sh_edges);
+    }
+}
+
 }  // namespace
 
-hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void *sat,
-                          int64_t ld_sat, int prec, const float *offsets, const uint32_t *hist,
-                          int64_t ld_hist, int64_t plane_stride, const float *edges,
-                          const QueryParams &p, float *out, int64_t ld_out, hipStream_t s) {
+int64_t query_tiles(int H, int W) {
+    return (int64_t)((W + kWave - 1) / kWave) * ((H + kRows - 1) / kRows);
+}
+
+hipError_t launch_forward_batch(const FwdK *ks, const int64_t *tile_prefix, int count, int prec,
+                                unsigned grid, hipStream_t s) {
+    switch (prec) {
+        case kF32:
+            hipLaunchKernelGGL(forward_batch<kF32>, dim3(grid), dim3(kBlock), 0, s, ks, tile_prefix, count);
+            break;
+        case kC32x2:
+            hipLaunchKernelGGL(forward_batch<kC32x2>, dim3(grid), dim3(kBlock), 0, s, ks, tile_prefix, count);
+            break;
+        default:
+            hipLaunchKernelGGL(forward_batch<kF64>, dim3(grid), dim3(kBlock), 0, s, ks, tile_prefix, count);
+            break;
+    }
+    return hipGetLastError();
+}
+
+FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int64_t ld_sat,
+                const float *offsets, const uint32_t *hist, int64_t ld_hist,
+                int64_t plane_stride, const float *edges, const QueryParams &p, float *out,
+                int64_t ld_out) {
     FwdK k;
     k.v = v;
     k.ld_v = ld_v;
@@ -157,16 +184,25 @@ hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void
     k.out = out;
     k.ld_out = ld_out;
     k.tiles_x = (W + kWave - 1) / kWave;
-    const int64_t tiles = (int64_t)k.tiles_x * ((H + kRows - 1) / kRows);
+    return k;
+}
+
+hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void *sat,
+                          int64_t ld_sat, int prec, const float *offsets, const uint32_t *hist,
+                          int64_t ld_hist, int64_t plane_stride, const float *edges,
+                          const QueryParams &p, float *out, int64_t ld_out, hipStream_t s) {
+    const FwdK k = make_fwdk(v, ld_v, H, W, sat, ld_sat, offsets, hist, ld_hist, plane_stride,
+                             edges, p, out, ld_out);
+    const unsigned tiles = (unsigned)query_tiles(H, W);
     switch (prec) {
         case kF32:
-            hipLaunchKernelGGL(forward_kernel<kF32>, dim3((unsigned)tiles), dim3(kBlock), 0, s, k);
+            hipLaunchKernelGGL(forward_kernel<kF32>, dim3(tiles), dim3(kBlock), 0, s, k);
             break;
         case kC32x2:
-            hipLaunchKernelGGL(forward_kernel<kC32x2>, dim3((unsigned)tiles), dim3(kBlock), 0, s, k);
+            hipLaunchKernelGGL(forward_kernel<kC32x2>, dim3(tiles), dim3(kBlock), 0, s, k);
             break;
         default:
-            hipLaunchKernelGGL(forward_kernel<kF64>, dim3((unsigned)tiles), dim3(kBlock), 0, s, k);
+            hipLaunchKernelGGL(forward_kernel<kF64>, dim3(tiles), dim3(kBlock), 0, s, k);
             break;
     }
     return hipGetLastError();

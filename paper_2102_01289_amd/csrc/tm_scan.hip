@@ -27,28 +27,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-struct ScanK {
-    const float *v;
-    int64_t ld_v;
-    int H, W, th, tiles_x, tiles_y;
-    int vec_load;                 // rows of v are 16-byte aligned
-    const float *offsets;
-    void *sat;
-    int64_t ld_sat;
-    const float *edges;
-    int n_bins, layout, n_planes;
-    uint32_t *hist;
-    int64_t ld_hist, plane_stride;
-    // aggregates (each an array of quantities; see ScanPlan)
-    void *rs_sat, *cs_sat, *tt_sat, *xc_sat, *cse_sat, *tte_sat;
-    uint32_t *rs_h, *cs_h, *tt_h, *xc_h, *cse_h, *tte_h;
-    // adjoint mode: the two FP64 planes to scan (row-major, pitch ld_d, already in reversed
-    // pixel order) and the gradient written back in forward order, dv = s1 + 2 v s2
-    const double2 *dsrc;
-    int64_t ld_d;
-    float *gv;
-    int64_t ld_gv;
-};
 
 // ---------------------------------------------------------------- table entries
 template <int P>
@@ -144,11 +122,9 @@ __device__ __forceinline__ void sat_terms(const ScanK &k, int y, int xl, const f
 
 // ================================================================ stage 1
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
-__global__ void __launch_bounds__(kBlock) scan_stage1(ScanK k) {
+__device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
     using A = Acc<P>;
     using T = typename A::T;
-    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (tile >= k.tiles_x * k.tiles_y) return;
     const int ty = tile / k.tiles_x, tx = tile % k.tiles_x;
     const int lane = lane_id();
     const int TW = kWave * VEC;
@@ -261,17 +237,17 @@ __global__ void __launch_bounds__(kBlock) scan_stage1(ScanK k) {
 }
 
 // ================================================================ stage 2
-// Blocks [0, b1) scan RS along tx, [b1, b2) scan CS along ty, [b2, b3) scan TT along tx.
+// Item id in [0, nq H) scans RS along tx for one (quantity, row); [nq H, nq H + nq W) scans
+// CS along ty for one (quantity, column); the rest scan TT along tx for one (quantity, ty).
 template <int P, bool SAT>
-__global__ void __launch_bounds__(kBlock) scan_stage2(ScanK k, int b1, int b2) {
+__device__ __forceinline__ void stage2_item(const ScanK &k, int64_t idx) {
     using A = Acc<P>;
     using T = typename A::T;
     const int nq_sat = SAT ? 2 : 0;
     const int nq = nq_sat + k.n_planes;
-    const int64_t idx = (int64_t)(blockIdx.x) * kBlock + threadIdx.x;
-    if ((int)blockIdx.x < b1) {
+    const int64_t n1 = (int64_t)nq * k.H, n2 = (int64_t)nq * k.W;
+    if (idx < n1) {
         // XC[q][y][tx] = sum_{tx' < tx} RS[q][y][tx']
-        if (idx >= (int64_t)nq * k.H) return;
         const int q = (int)(idx / k.H);
         const int64_t y = idx % k.H;
         if (q < nq_sat) {
@@ -286,10 +262,9 @@ __global__ void __launch_bounds__(kBlock) scan_stage2(ScanK k, int b1, int b2) {
             uint32_t run = 0;
             for (int t = 0; t < k.tiles_x; ++t) { uint32_t a = rs[t]; xc[t] = run; run += a; }
         }
-    } else if ((int)blockIdx.x < b2) {
+    } else if (idx < n1 + n2) {
         // CSE[q][ty][x] = sum_{ty' < ty} CS[q][ty'][x]
-        const int64_t id = idx - (int64_t)b1 * kBlock;
-        if (id >= (int64_t)nq * k.W) return;
+        const int64_t id = idx - n1;
         const int q = (int)(id / k.W);
         const int64_t x = id % k.W;
         if (q < nq_sat) {
@@ -314,7 +289,7 @@ __global__ void __launch_bounds__(kBlock) scan_stage2(ScanK k, int b1, int b2) {
         }
     } else {
         // TTE[q][ty][tx] = sum_{tx' < tx} TT[q][ty][tx']
-        const int64_t id = idx - (int64_t)b2 * kBlock;
+        const int64_t id = idx - n1 - n2;
         if (id >= (int64_t)nq * k.tiles_y) return;
         const int q = (int)(id / k.tiles_y);
         const int64_t ty = id % k.tiles_y;
@@ -355,13 +330,11 @@ __device__ __forceinline__ void top_carry(const T *tte, const T *cse, int ty, in
 }
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
-__global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
+__device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
     using A = Acc<P>;
     using T = typename A::T;
     using E = Entry<P>;
     using ET = typename E::T;
-    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (tile >= k.tiles_x * k.tiles_y) return;
     const int ty = tile / k.tiles_x, tx = tile % k.tiles_x;
     const int lane = lane_id();
     const int TW = kWave * VEC;
@@ -514,6 +487,54 @@ __global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
     }
 }
 
+// ---------------------------------------------------------------- single-image kernels
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
+__global__ void __launch_bounds__(kBlock) scan_stage1(ScanK k) {
+    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile < k.tiles_x * k.tiles_y) stage1_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, tile);
+}
+
+template <int P, bool SAT>
+__global__ void __launch_bounds__(kBlock) scan_stage2(ScanK k, int64_t items) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx < items) stage2_item<P, SAT>(k, idx);
+}
+
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
+__global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
+    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile < k.tiles_x * k.tiles_y) stage3_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, tile);
+}
+
+// ---------------------------------------------------------------- batched kernels
+// A persistent grid walks one flattened list of work items spanning every image.
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool THIRD>
+__global__ void __launch_bounds__(kBlock) scan_tiles_batch(const ScanK *ks, const int64_t *prefix,
+                                                           int count) {
+    const int64_t total = prefix[count];
+    const int64_t step = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t g = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; g < total;
+         g += step) {
+        const int i = __builtin_amdgcn_readfirstlane(find_image(prefix, count, g));
+        const int tile = (int)(g - prefix[i]);
+        if (THIRD)
+            stage3_tile<P, VEC, CHUNK, SAT, HIST, false>(ks[i], tile);
+        else
+            stage1_tile<P, VEC, CHUNK, SAT, HIST, false>(ks[i], tile);
+    }
+}
+
+template <int P, bool SAT>
+__global__ void __launch_bounds__(kBlock) scan_stage2_batch(const ScanK *ks, const int64_t *prefix,
+                                                            int count) {
+    const int64_t total = prefix[count];
+    const int64_t step = (int64_t)gridDim.x * kBlock;
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < total; g += step) {
+        const int i = find_image(prefix, count, g);
+        stage2_item<P, SAT>(ks[i], g - prefix[i]);
+    }
+}
+
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ = false>
 hipError_t run3(const ScanK &k, hipStream_t s) {
     const int tiles = k.tiles_x * k.tiles_y;
@@ -521,11 +542,9 @@ hipError_t run3(const ScanK &k, hipStream_t s) {
     hipLaunchKernelGGL((scan_stage1<P, VEC, CHUNK, SAT, HIST, ADJ>), dim3(grid), dim3(kBlock), 0, s, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nq = (SAT ? 2 : 0) + k.n_planes;
-    const int b1 = (int)(((int64_t)nq * k.H + kBlock - 1) / kBlock);
-    const int b2 = b1 + (int)(((int64_t)nq * k.W + kBlock - 1) / kBlock);
-    const int b3 = b2 + (int)(((int64_t)nq * k.tiles_y + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((scan_stage2<P, SAT>), dim3(b3), dim3(kBlock), 0, s, k, b1, b2);
+    const int64_t items = scan_stage2_items(k, SAT);
+    hipLaunchKernelGGL((scan_stage2<P, SAT>), dim3((unsigned)((items + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, k, items);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((scan_stage3<P, VEC, CHUNK, SAT, HIST, ADJ>), dim3(grid), dim3(kBlock), 0, s, k);
@@ -557,9 +576,49 @@ hipError_t dispatch_vec(const ScanK &k, int vec, int chunk, bool sat, bool hist,
     }
 }
 
+template <int P, int VEC, int CHUNK>
+hipError_t batch3(const BatchScan &b, hipStream_t s) {
+    hipLaunchKernelGGL((scan_tiles_batch<P, VEC, CHUNK, true, true, false>), dim3(b.grid_tiles),
+                       dim3(kBlock), 0, s, b.ks, b.tile_prefix, b.count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((scan_stage2_batch<P, true>), dim3(b.grid_items), dim3(kBlock), 0, s, b.ks,
+                       b.item_prefix, b.count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((scan_tiles_batch<P, VEC, CHUNK, true, true, true>), dim3(b.grid_tiles),
+                       dim3(kBlock), 0, s, b.ks, b.tile_prefix, b.count);
+    return hipGetLastError();
+}
+
+template <int P, int VEC>
+hipError_t batch_chunk(const BatchScan &b, hipStream_t s) {
+    switch (b.chunk) {
+        case 2: return batch3<P, VEC, 2>(b, s);
+        case 4: return batch3<P, VEC, 4>(b, s);
+        default: return batch3<P, VEC, 8>(b, s);
+    }
+}
+
+template <int P>
+hipError_t batch_vec(const BatchScan &b, hipStream_t s) {
+    switch (b.vec) {
+        case 2: return batch_chunk<P, 2>(b, s);
+        case 4: return batch_chunk<P, 4>(b, s);
+        default: return batch_chunk<P, 8>(b, s);
+    }
+}
+
 size_t round_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
 
 }  // namespace
+
+hipError_t launch_tables_batch(const BatchScan &b, hipStream_t s) {
+    switch (b.prec) {
+        case kF32: return batch_vec<kF32>(b, s);
+        case kC32x2: return batch_vec<kC32x2>(b, s);
+        default: return batch_vec<kF64>(b, s);
+    }
+}
 
 ScanTune scan_tune_default(int H, int W) {
     ScanTune t;
@@ -615,7 +674,7 @@ ScanPlan make_scan_plan(int H, int W, int sat_prec, int n_planes, const ScanTune
     return p;
 }
 
-hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipStream_t s) {
+ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws) {
     ScanK k{};
     char *w = static_cast<char *>(ws);
     k.v = a.v;
@@ -632,7 +691,7 @@ hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipS
     k.edges = a.edges;
     k.n_bins = a.n_bins;
     k.layout = a.layout;
-    k.n_planes = a.n_planes;
+    k.n_planes = (a.n_planes > 0 && a.hist != nullptr) ? a.n_planes : 0;
     k.hist = a.hist;
     k.ld_hist = a.ld_hist;
     k.plane_stride = a.plane_stride;
@@ -648,10 +707,18 @@ hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipS
     k.xc_h = reinterpret_cast<uint32_t *>(w + plan.xc_h);
     k.cse_h = reinterpret_cast<uint32_t *>(w + plan.cse_h);
     k.tte_h = reinterpret_cast<uint32_t *>(w + plan.tte_h);
+    return k;
+}
+
+int64_t scan_stage2_items(const ScanK &k, bool sat) {
+    const int64_t nq = (sat ? 2 : 0) + k.n_planes;
+    return nq * ((int64_t)k.H + k.W + k.tiles_y);
+}
+
+hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipStream_t s) {
+    const ScanK k = make_scank(a, plan, ws);
     const bool sat = a.sat_prec >= 0 && a.sat != nullptr;
-    const bool hist = a.n_planes > 0 && a.hist != nullptr;
-    if (!sat) k.n_planes = hist ? a.n_planes : 0;
-    if (!hist) k.n_planes = 0;
+    const bool hist = k.n_planes > 0;
     if (!sat && !hist) return hipSuccess;
     switch (sat ? a.sat_prec : kF32) {
         case kF32: return dispatch_vec<kF32>(k, plan.vec, plan.chunk, sat, hist, s);

@@ -1,0 +1,82 @@
+"""Batched forward: equal to per-image calls bit for bit, graph replays equal to eager runs,
+and the autotuner's choice valid."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2102_01289_amd as tm
+from paper_2102_01289_amd import autotune
+from _cases import rgb_case, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(37, 123), (256, 256), (1, 1), (1, 300), (300, 1), (130, 1030), (64, 2100), (90, 91)]
+
+
+def _images(seed=0, shapes=SHAPES):
+    return [to_dev(rgb_case(h, w, 5, -2.0, 4.0, seed=seed + 7 * i)) for i, (h, w) in
+            enumerate(shapes)]
+
+
+@pytest.mark.parametrize("prec", ["c32x2", "f64", "f32"])
+@pytest.mark.parametrize("t", [(4, 16, 4), (2, 5, 2), (8, 32, 8)])
+def test_batch_equals_per_image(prec, t):
+    imgs = _images()
+    b = tm.Batch(imgs, 5, 5, prec=prec, tune=tm.tune(*t))
+    outs = [o.clone() for o in b.forward()]
+    torch.cuda.synchronize()
+    for i, rgb in enumerate(imgs):
+        _, H, W = rgb.shape
+        p = tm.make_params(5, 5, eps=0.1, H=H, W=W)
+        ref = tm.ToneMapper(H, W, p, prec, tune=tm.tune(*t)).run(rgb)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], ref), i
+
+
+def test_batch_other_parameters():
+    imgs = _images(seed=5, shapes=[(50, 70), (33, 300), (200, 20)])
+    b = tm.Batch(imgs, n_bins=64, n_scales=3, eps=0.05, ld_min=0.1, ld_max=0.9)
+    outs = [o.clone() for o in b.forward()]
+    for i, rgb in enumerate(imgs):
+        _, H, W = rgb.shape
+        p = tm.make_params(64, 3, eps=0.05, ld_min=0.1, ld_max=0.9, H=H, W=W)
+        ref = tm.ToneMapper(H, W, p, "c32x2", tune=tm.tune(4, 16, 4)).run(rgb)
+        assert torch.equal(outs[i], ref)
+
+
+def test_batch_graph_replays_match_eager():
+    imgs = _images(seed=11)
+    b = tm.Batch(imgs)
+    eager = [o.clone() for o in b.forward()]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    b.capture(s)
+    for rep in range(3):
+        for o in b.outs:
+            o.fill_(-1.0)                      # eager work between replays
+        b.replay(s)
+        s.synchronize()
+        for i, o in enumerate(b.outs):
+            assert torch.equal(o, eager[i]), (rep, i)
+        _ = torch.randn(1000, device="cuda").sum().item()
+    # the graph reads the inputs at replay time
+    for r in imgs:
+        r.mul_(2.0)
+    b.replay(s)
+    s.synchronize()
+    scaled = [o.clone() for o in b.outs]
+    fresh = [o.clone() for o in tm.Batch(imgs).forward()]
+    torch.cuda.synchronize()
+    for a, c in zip(scaled, fresh):
+        assert torch.equal(a, c)
+
+
+def test_autotune_picks_a_valid_tiling(tmp_path, monkeypatch):
+    monkeypatch.setenv("TM355_TUNE_CACHE", str(tmp_path / "tune.json"))
+    imgs = _images(seed=3, shapes=[(120, 500), (300, 200)])
+    t, ms = autotune.tune_batch(imgs, reps=2, cands=[(2, 8, 4), (4, 16, 4)])
+    assert (t.tile_w_vec, t.tile_h, t.bin_chunk) in [(2, 8, 4), (4, 16, 4)] and ms > 0
+    t2, _ = autotune.tune_image(imgs[0], reps=2)
+    assert t2.tile_w_vec in (2, 4, 8)
+    t3, _ = autotune.tune_image(imgs[0], reps=2)       # second call is served by the cache
+    assert (t3.tile_w_vec, t3.tile_h, t3.bin_chunk) == (t2.tile_w_vec, t2.tile_h, t2.bin_chunk)
