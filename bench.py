@@ -36,10 +36,63 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", choices=["query", "tables", "backward"], default=None,
                     help="launch only that stage in the timed loop (profiling runs)")
-    ap.add_argument("--workload", choices=["image", "batch"], default="image",
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed loop, copy 1 GiB device-to-device once (a plain copy "
+                         "kernel of known size, for calibrating HBM counters) and report its "
+                         "bandwidth")
+    ap.add_argument("--workload", choices=["image", "batch", "precision"], default="image",
                     help="image: one 4000x3000 image (default); batch: 64 images of uneven "
                          "size, persistent launches replayed from a HIP graph")
     return ap.parse_args()
+
+
+def bench_precision(args):
+    """Output error of each integral-image precision against the FP64 oracle on the whole
+    image: the paper set at 4000x3000 (10^8:1) and the n = 64, radii {4, 16, 64} stress set
+    at 1920x1080."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2102_01289_amd as tm
+    from synth import WORKLOADS, gen_wdr
+
+    dev = torch.device("cuda:0")
+    cases = [("wdr_4000x3000", 5, None), ("wdr_1920x1080", 64, [4, 16, 64])]
+    out = {"metric": "max-abs / p99.9 output error vs FP64 oracle per integral-image precision",
+           "data": "synthetic", "cases": []}
+    for name, n, radii in cases:
+        c = WORKLOADS[name]
+        H, W = c["H"], c["W"]
+        rgb = gen_wdr(H, W, c["K"], c["lo"], c["hi"], c["seed"]).rgb
+        lum = oracle.luminance(rgb)
+        e = oracle.exact_edges(lum.min(), lum.max(), n)
+        if radii is None:
+            rx, ry = oracle.paper_radii(H, W, 5)
+        else:
+            rx, ry = radii, radii
+        t0 = time.perf_counter()
+        ref = oracle.forward(lum, e, rx, ry, 0.1)
+        t_orc = time.perf_counter() - t0
+        p = tm.make_params(n, len(rx), rx, ry, 0.1)
+        case = {"workload": name, "n_bins": n, "radii_x": list(rx), "radii_y": list(ry),
+                "dynamic_range": float(lum.max() / lum.min()), "oracle_s": round(t_orc, 2),
+                "variants": {}}
+        for prec in ("f32", "c32x2", "f64"):
+            m = tm.ToneMapper(H, W, p, prec, device=dev)
+            L = m.run(torch.from_numpy(rgb).to(dev)).cpu().numpy().astype(np.float64)
+            G = m.hist.padded()[..., 0].numpy().astype(np.uint64)
+            exact = bool(np.array_equal(
+                G, oracle.integral_histogram(oracle.bins(lum, e), n, cumulative=True)))
+            err = np.abs(L - ref)
+            case["variants"][prec] = {
+                "max_abs": float(err.max()), "p99_9": float(np.quantile(err, 0.999)),
+                "mean_abs": float(err.mean()), "frac_above_1_255": float(np.mean(err > 1 / 255)),
+                "histogram_bit_exact": exact}
+            del m
+            print(f"bench: {name} {prec} max {err.max():.3e}", file=sys.stderr, flush=True)
+        out["cases"].append(case)
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args):
@@ -108,11 +161,12 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def query_bytes_per_px(prec: str, n_bins: int) -> int:
+def query_bytes_per_px(prec: str, n_bins: int, resid_planes: int = 0) -> int:
     """Algorithmic bytes of the fused query per pixel: luminance in, every table entry read
-    once (interleaved integral image + n-1 cumulative planes), tone value out."""
+    once (interleaved integral image + n-1 cumulative planes), tone value out, and in the
+    training form the FP32 residual planes out."""
     sat = {"f32": 8, "c32x2": 16, "f64": 16}[prec]
-    return 4 + sat + 4 * (n_bins - 1) + 4
+    return 4 + sat + 4 * (n_bins - 1) + 4 + 4 * resid_planes
 
 
 def cpu_baseline(rgb, params_np, backward: bool):
@@ -150,6 +204,9 @@ def main():
     if args.workload == "batch":
         bench_batch(args)
         return
+    if args.workload == "precision":
+        bench_precision(args)
+        return
 
     import numpy as np
     import torch
@@ -169,6 +226,9 @@ def main():
     g = torch.from_numpy(gen_upstream_grad((H, W), seed=cfg["seed"] + 1)).to(dev)
     do_bwd = not args.no_backward
 
+    # forward+backward: the training forward writes the residual planes the backward reads
+    query = mapper.query_train if do_bwd else mapper.query
+
     def step(ev=None):
         ko = args.kernel_only
         if ko in (None, "tables"):
@@ -177,16 +237,16 @@ def main():
         if ko in (None, "query"):
             if ev is not None:
                 ev[0].record(stream)
-            mapper.query()
+            query()
             if ev is not None:
                 ev[1].record(stream)
         if do_bwd and ko in (None, "backward"):
-            mapper.backward(g)
+            mapper.backward_resid(g)
 
     # warm-up (also produces the tables a query-only or backward-only loop reads)
-    mapper.run(rgb)
+    mapper.run_train(rgb) if do_bwd else mapper.run(rgb)
     if do_bwd:
-        mapper.backward(g)
+        mapper.backward_resid(g)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -208,7 +268,8 @@ def main():
     stages = [("prologue", lambda: mapper.prologue(rgb)), ("tables", mapper.tables),
               ("query", mapper.query)]
     if do_bwd:
-        stages.append(("backward", lambda: mapper.backward(g)))
+        stages += [("query_train", mapper.query_train),
+                   ("backward", lambda: mapper.backward_resid(g))]
     for name, fn in stages:
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -218,9 +279,25 @@ def main():
         torch.cuda.synchronize()
         stage[name] = round(a.elapsed_time(b) / 5, 4)
     fwd_ms = stage["prologue"] + stage["tables"] + stage["query"]
+    step_ms = fwd_ms + (stage["query_train"] - stage["query"] + stage["backward"] if do_bwd else 0)
+
+    copy_gbs = None
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dst.copy_(src)
+        b.record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = round(2 * src.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9, 1)
+        del src, dst
 
     mpx = H * W / 1e6
-    qbytes = query_bytes_per_px(args.prec, args.n_bins) * H * W
+    qbytes = query_bytes_per_px(args.prec, args.n_bins,
+                                tm.residual_planes(args.n_scales) if do_bwd else 0) * H * W
     achieved = qbytes / (q_ms * 1e-3) / 1e9
     line = {
         "metric": "megapixels/s fwd and fwd+bwd at 12MP vs plain fwd; HBM GB/s fraction",
@@ -242,10 +319,14 @@ def main():
                    "step": ("forward+backward" if do_bwd else "forward")
                    if args.kernel_only is None else args.kernel_only},
         "fwd_mp_s": round(mpx / (fwd_ms * 1e-3), 3),
-        "fwd_bwd_mp_s": round(mpx / (sum(stage.values()) * 1e-3), 3) if do_bwd else None,
-        "fwd_bwd_over_fwd": round(fwd_ms / sum(stage.values()), 4) if do_bwd else None,
+        "fwd_bwd_mp_s": round(mpx / (step_ms * 1e-3), 3) if do_bwd else None,
+        "fwd_bwd_over_fwd": round(fwd_ms / step_ms, 4) if do_bwd else None,
         "stage_ms": stage,
-        "roofline": {"bound": "hbm", "kernel": "forward_kernel (fused query+blend)",
+        "copy_probe_gbs": copy_gbs,
+        "roofline": {"bound": "hbm",
+                     "kernel": ("forward_kernel (fused query+blend, training form writing the "
+                                "residual planes)") if do_bwd else
+                     "forward_kernel (fused query+blend)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "algorithmic_bytes_per_launch": qbytes,

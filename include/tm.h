@@ -193,7 +193,39 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
                              int64_t plane_stride, const float *edges, const tm_params *p,
                              float *out, int64_t ld_out, void *stream);
 
+/* Number of FP32 residual planes a training forward writes: 2 * n_scales + 2 (0 if
+ * n_scales is out of range). */
+int32_t tm_residual_planes(int32_t n_scales);
+
+/* The forward of tm_tonemap_forward plus, for the backward, per-pixel residual planes that
+ * do not depend on the upstream gradient (Eq. 3, 4, 10 differentiated): with
+ * c_j = (L_j - L)/D eps/(var_j + eps)^2 (zero where var_j was clamped or D = 0),
+ *   plane j       R1_j = -2 c_j (S1_j/N_j) / N_j      (j < s)
+ *   plane s + j   R2_j = c_j / N_j
+ *   plane 2s      E = sum_j (L_j - L)/D (-var_j/(var_j + eps)^2)
+ *   plane 2s + 1  Pbar = sum_j W_j P_j / D (mean of P_j where D = 0)
+ * resid: tm_residual_planes(s) planes of H*W FP32, pitch W, plane stride H*W, caller-owned.
+ * A window of one pixel has zero variance by definition. */
+tm_status tm_tonemap_forward_train(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                   const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                                   const float *offsets, const uint32_t *hist_cum,
+                                   int64_t ld_hist, int64_t plane_stride, const float *edges,
+                                   const tm_params *p, float *out, int64_t ld_out, float *resid,
+                                   void *stream);
+
 /* ---------------------------------------------------------------- stage a5: backward */
+
+/* Gradient from the residual planes of tm_tonemap_forward_train: no integral table is read.
+ *   dv(q) = sum_j sum_{p: q in w_j(p)} g(p) (R1_j(p) + 2 v(q) R2_j(p)),
+ *   grad_params = {sum g E, sum g (1 - Pbar), sum g Pbar}.
+ * Workspace: tm_backward_resid_workspace_bytes. */
+size_t tm_backward_resid_workspace_bytes(int32_t H, int32_t W, const tm_params *p);
+tm_status tm_tonemap_backward_resid(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                    const tm_params *p, const float *resid,
+                                    const float *grad_out, int64_t ld_g, float *grad_v,
+                                    int64_t ld_gv, double *grad_params, void *ws,
+                                    size_t ws_bytes, void *stream);
+
 
 /* Gradient of sum_p g(p) L(p) (g = grad_out) with respect to v and to (eps, ld_min,
  * ld_max), from the same tables the forward read.  The histogram terms are piecewise
@@ -203,8 +235,9 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
  *   dv(q) = sum_j sum_{p: q in w_j(p)} (-2 a_j S1_j/N_j^2 + 2 v(q) a_j/N_j),
  * evaluated by depositing the per-pixel coefficients at the window corners and taking two
  * reverse (suffix) 2-D scans.  grad_v: FP32 H x W, pitch ld_gv.  grad_params: device
- * double[3] = {d/d eps, d/d ld_min, d/d ld_max}, deterministic.
- * Workspace: tm_backward_workspace_bytes. */
+ * double[3] = {d/d eps, d/d ld_min, d/d ld_max}, deterministic.  This entry point rebuilds
+ * the residual planes of tm_tonemap_forward_train from the tables in its workspace and then
+ * runs tm_tonemap_backward_resid.  Workspace: tm_backward_workspace_bytes. */
 size_t tm_backward_workspace_bytes(int32_t H, int32_t W, const tm_params *p);
 tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W,
                               const void *sat, int64_t ld_sat, tm_sat_prec prec,

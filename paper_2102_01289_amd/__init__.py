@@ -18,7 +18,8 @@ __all__ = [
     "TmError", "Table", "table_geometry", "paper_radii", "make_params", "tune",
     "tm_luminance", "tm_image_stats", "tm_prologue", "tm_integral_image",
     "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
-    "tm_tonemap_backward", "ToneMapper", "tonemap", "Batch",
+    "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
+    "residual_planes", "ToneMapper", "tonemap", "Batch",
 ]
 
 
@@ -254,6 +255,43 @@ def tm_tonemap_forward(v, sat: Table, hist: Table | None, edges, params, offsets
     return out
 
 
+def residual_planes(n_scales: int) -> int:
+    return int(_lib().tm_residual_planes(n_scales))
+
+
+def tm_tonemap_forward_train(v, sat: Table, hist: Table | None, edges, params, offsets=None,
+                             out=None, resid=None, stream=None):
+    """Forward plus the residual planes of the backward: (L [H, W], resid [2s+2, H, W])."""
+    H, W, ld = _img(v, "v")
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=v.device)
+    if resid is None:
+        resid = torch.empty((residual_planes(params.n_scales), H, W), dtype=torch.float32,
+                            device=v.device)
+    _ck("tm_tonemap_forward_train", _lib().tm_tonemap_forward_train(
+        _vp(v), ld, H, W, _vp(sat.ptr), sat.ld, _capi.SAT_PREC[sat.kind], _vp(offsets),
+        _vp(hist.ptr if hist else None), hist.ld if hist else 0,
+        hist.plane_stride if hist else 0, _vp(edges), ctypes.byref(params), _vp(out),
+        out.stride(0), _vp(resid), _stream(stream)))
+    return out, resid
+
+
+def tm_tonemap_backward_resid(v, params, resid, grad_out, stream=None, ws=None, out=None):
+    """Gradient from residual planes: (grad_v [H, W] float32, grad_params [3] float64)."""
+    H, W, ld = _img(v, "v")
+    _, _, ldg = _img(grad_out, "grad_out")
+    if out is None:
+        out = (torch.empty((H, W), dtype=torch.float32, device=v.device),
+               torch.empty(3, dtype=torch.float64, device=v.device))
+    gv, gp = out
+    if ws is None:
+        ws = _ws(_lib().tm_backward_resid_workspace_bytes(H, W, ctypes.byref(params)), v.device)
+    _ck("tm_tonemap_backward_resid", _lib().tm_tonemap_backward_resid(
+        _vp(v), ld, H, W, ctypes.byref(params), _vp(resid), _vp(grad_out), ldg, _vp(gv),
+        gv.stride(0), _vp(gp), _vp(ws), ws.numel(), _stream(stream)))
+    return gv, gp
+
+
 def tm_tonemap_backward(v, sat: Table, hist: Table | None, edges, params, grad_out,
                         offsets=None, stream=None):
     """(grad_v [H, W] float32, grad_params [3] float64 = d/d(eps, ld_min, ld_max))."""
@@ -330,14 +368,42 @@ class ToneMapper:
         self.query(stream)
         return self.out
 
-    def backward(self, grad_out: torch.Tensor, stream=None):
-        """Adjoint of the last forward (its tables are reused): (grad_lum, grad_params)."""
+    def query_train(self, stream=None):
+        """Fused query that also writes the backward's residual planes."""
+        if not hasattr(self, "resid"):
+            self.resid = torch.empty((residual_planes(self.params.n_scales), self.H, self.W),
+                                     dtype=torch.float32, device=self.lum.device)
+        tm_tonemap_forward_train(self.lum, self.sat, self.hist, self.edges, self.params,
+                                 self.offsets, self.out, self.resid, stream)
+
+    def run_train(self, rgb, stream=None) -> torch.Tensor:
+        self.prologue(rgb, stream)
+        self.tables(stream)
+        self.query_train(stream)
+        return self.out
+
+    def _bwd_buffers(self):
         if not hasattr(self, "grad_v"):
             dev = self.lum.device
             self.grad_v = torch.empty((self.H, self.W), dtype=torch.float32, device=dev)
             self.grad_params = torch.empty(3, dtype=torch.float64, device=dev)
+
+    def backward_resid(self, grad_out: torch.Tensor, stream=None):
+        """Adjoint from the residual planes of the last run_train: (grad_lum, grad_params)."""
+        self._bwd_buffers()
+        if not hasattr(self, "ws_bwd_resid"):
+            self.ws_bwd_resid = _ws(_lib().tm_backward_resid_workspace_bytes(
+                self.H, self.W, ctypes.byref(self.params)), self.lum.device)
+        return tm_tonemap_backward_resid(self.lum, self.params, self.resid, grad_out, stream,
+                                         self.ws_bwd_resid, (self.grad_v, self.grad_params))
+
+    def backward(self, grad_out: torch.Tensor, stream=None):
+        """Adjoint of the last forward from its tables: (grad_lum, grad_params)."""
+        self._bwd_buffers()
+        if not hasattr(self, "ws_bwd"):
             self.ws_bwd = _ws(_lib().tm_backward_workspace_bytes(self.H, self.W,
-                                                                 ctypes.byref(self.params)), dev)
+                                                                 ctypes.byref(self.params)),
+                              self.lum.device)
         h = self.hist
         _, _, ldg = _img(grad_out, "grad_out")
         _ck("tm_tonemap_backward", _lib().tm_tonemap_backward(

@@ -60,6 +60,12 @@ SIGNATURES = {
     "tm_tonemap_forward": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
                                           I64, P, PP, P, I64, P]),
     "tm_backward_workspace_bytes": (SZ, [I32, I32, PP]),
+    "tm_residual_planes": (I32, [I32]),
+    "tm_tonemap_forward_train": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P,
+                                                I64, I64, P, PP, P, I64, P, P]),
+    "tm_backward_resid_workspace_bytes": (SZ, [I32, I32, PP]),
+    "tm_tonemap_backward_resid": (ctypes.c_int, [P, I64, I32, I32, PP, P, P, I64, P, I64, P, P,
+                                                 SZ, P]),
     "tm_batch_workspace_bytes": (SZ, [ctypes.POINTER(TmImageDesc), I32, PP, ctypes.c_int, PT]),
     "tm_batch_create": (ctypes.c_int, [ctypes.POINTER(TmImageDesc), I32, PP, ctypes.c_int, PT, P,
                                        SZ, P, ctypes.POINTER(P)]),

@@ -4,15 +4,17 @@ hand-written adjoint (tm_tonemap_backward).
 Differentiable inputs: the luminance image and the scalars (eps, min L_d, max L_d).  The bin
 edges are statistics of the image held fixed in the backward (stop-gradient), and the bin
 counts are piecewise constant in the luminance, so their derivative is zero almost
-everywhere.  With recompute=True the integral tables are freed after the forward and
-rebuilt in the backward (memory: two images' worth of tables instead of a per-step copy).
+everywhere.  recompute=False (fastest): the forward writes the backward's residual planes
+(2s + 2 FP32 per pixel) and the backward reads no table.  recompute=True (least memory kept
+between the passes): only the luminance, edges and offsets are kept; the backward rebuilds
+the integral tables and derives the residual planes from them.
 """
 from __future__ import annotations
 
 import torch
 
 from . import (make_params, tm_image_stats, tm_integral_tables, tm_tonemap_backward,
-               tm_tonemap_forward)
+               tm_tonemap_backward_resid, tm_tonemap_forward, tm_tonemap_forward_train)
 
 __all__ = ["TonemapFn", "tonemap_luminance"]
 
@@ -29,22 +31,27 @@ class TonemapFn(torch.autograd.Function):
         p = _params(H, W, n_bins, rx, ry, eps.item(), ld_min.item(), ld_max.item())
         edges, offsets, _ = tm_image_stats(lum, n_bins)
         sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")
-        out = tm_tonemap_forward(lum, sat, hist, edges, p, offsets)
-        ctx.meta = (p, prec, n_bins, recompute, eps.dtype)
-        ctx.tables = None if recompute else (sat, hist)
+        if recompute:
+            out = tm_tonemap_forward(lum, sat, hist, edges, p, offsets)
+            ctx.resid = None
+        else:
+            out, ctx.resid = tm_tonemap_forward_train(lum, sat, hist, edges, p, offsets)
+        del sat, hist
+        ctx.meta = (p, prec, n_bins, eps.dtype)
         ctx.save_for_backward(lum, edges, offsets)
         return out
 
     @staticmethod
     def backward(ctx, g):
         lum, edges, offsets = ctx.saved_tensors
-        p, prec, n_bins, recompute, sdt = ctx.meta
-        if ctx.tables is None:
+        p, prec, n_bins, sdt = ctx.meta
+        g = g.contiguous().float()
+        if ctx.resid is None:
             sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")
+            gv, gp = tm_tonemap_backward(lum, sat, hist, edges, p, g, offsets)
         else:
-            sat, hist = ctx.tables
-        gv, gp = tm_tonemap_backward(lum, sat, hist, edges, p, g.contiguous().float(), offsets)
-        ctx.tables = None
+            gv, gp = tm_tonemap_backward_resid(lum, p, ctx.resid, g)
+            ctx.resid = None
         return (gv, gp[0].to(sdt), gp[1].to(sdt), gp[2].to(sdt), None, None, None, None, None)
 
 

@@ -162,7 +162,7 @@ size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int pre
         b->parts[i + 1] = b->parts[i] + b->sk[i].nparts;
         b->tiles[i + 1] = b->tiles[i] + (int64_t)sp.tiles_x * sp.tiles_y;
         b->items[i + 1] = b->items[i] + scan_stage2_items(b->ck[i], true);
-        b->qtiles[i + 1] = b->qtiles[i] + query_tiles(H, W);
+        b->qtiles[i + 1] = b->qtiles[i] + query_blocks(b->fk[i]);
     }
     if (b) {
         b->d_sk = c.ptr<StatsK>(o_sk);

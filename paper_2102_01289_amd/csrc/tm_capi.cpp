@@ -289,14 +289,95 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
     }
     const QueryParams q = to_query(p);
     return from_hip(launch_forward(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
-                                   ld_hist, plane_stride, edges, q, out, ld_out,
+                                   ld_hist, plane_stride, edges, q, out, ld_out, nullptr,
+                                   (hipStream_t)stream));
+}
+
+int32_t tm_residual_planes(int32_t n_scales) {
+    return (n_scales < 1 || n_scales > TM_MAX_SCALES) ? 0 : 2 * n_scales + 2;
+}
+
+tm_status tm_tonemap_forward_train(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                   const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                                   const float *offsets, const uint32_t *hist_cum,
+                                   int64_t ld_hist, int64_t plane_stride, const float *edges,
+                                   const tm_params *p, float *out, int64_t ld_out, float *resid,
+                                   void *stream) {
+    if (!resid) return TM_ERR_ARG;
+    if (!aligned(resid, 4)) return TM_ERR_ALIGN;
+    TM_TRY(check_image(H, W));
+    TM_TRY(check_params(p));
+    if (!v || !out || !valid_prec(prec)) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_v));
+    TM_TRY(check_plane(H, W, ld_out));
+    TM_TRY(check_table(H, W, ld_sat, sat));
+    if (prec == TM_SAT_C32X2 && !offsets) return TM_ERR_ARG;
+    if (p->n_bins > 1) {
+        if (!edges) return TM_ERR_ARG;
+        TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
+    }
+    const QueryParams q = to_query(p);
+    return from_hip(launch_forward(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
+                                   ld_hist, plane_stride, edges, q, out, ld_out, resid,
                                    (hipStream_t)stream));
 }
 
 // ------------------------------------------------------------------ a5
 size_t tm_backward_workspace_bytes(int32_t H, int32_t W, const tm_params *p) {
     if (check_image(H, W) != TM_OK || check_params(p) != TM_OK) return 0;
-    return make_bwd_plan(H, W, p->n_scales).total;
+    return make_bwd_plan(H, W, p->n_scales, p->ry, true).total;
+}
+
+size_t tm_backward_resid_workspace_bytes(int32_t H, int32_t W, const tm_params *p) {
+    if (check_image(H, W) != TM_OK || check_params(p) != TM_OK) return 0;
+    return make_bwd_plan(H, W, p->n_scales, p->ry, false).total;
+}
+
+static tm_status run_backward_resid(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                    const tm_params *p, const float *resid,
+                                    const float *grad_out, int64_t ld_g, float *grad_v,
+                                    int64_t ld_gv, double *grad_params, const BwdPlan &plan,
+                                    void *ws, hipStream_t s) {
+    BwdResidArgs a{};
+    a.v = v;
+    a.ld_v = ld_v;
+    a.H = H;
+    a.W = W;
+    a.p = to_query(p);
+    a.resid = resid;
+    a.g = grad_out;
+    a.ld_g = ld_g;
+    a.grad_v = grad_v;
+    a.ld_gv = ld_gv;
+    a.grad_params = grad_params;
+    return from_hip(launch_backward_resid(a, plan, ws, s));
+}
+
+static tm_status check_bwd_common(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                  const tm_params *p, const float *grad_out, int64_t ld_g,
+                                  float *grad_v, int64_t ld_gv, double *grad_params) {
+    TM_TRY(check_image(H, W));
+    TM_TRY(check_params(p));
+    if (!v || !grad_out || !grad_v || !grad_params) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_v));
+    TM_TRY(check_plane(H, W, ld_g));
+    TM_TRY(check_plane(H, W, ld_gv));
+    if (!aligned(grad_params, 8)) return TM_ERR_ALIGN;
+    return TM_OK;
+}
+
+tm_status tm_tonemap_backward_resid(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                    const tm_params *p, const float *resid,
+                                    const float *grad_out, int64_t ld_g, float *grad_v,
+                                    int64_t ld_gv, double *grad_params, void *ws,
+                                    size_t ws_bytes, void *stream) {
+    TM_TRY(check_bwd_common(v, ld_v, H, W, p, grad_out, ld_g, grad_v, ld_gv, grad_params));
+    if (!resid) return TM_ERR_ARG;
+    if (!aligned(resid, 4)) return TM_ERR_ALIGN;
+    BwdPlan plan = make_bwd_plan(H, W, p->n_scales, p->ry, false);
+    TM_TRY(check_ws(ws, ws_bytes, plan.total));
+    return run_backward_resid(v, ld_v, H, W, p, resid, grad_out, ld_g, grad_v, ld_gv,
+                              grad_params, plan, ws, (hipStream_t)stream);
 }
 
 tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W,
@@ -306,41 +387,26 @@ tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W
                               const tm_params *p, const float *grad_out, int64_t ld_g,
                               float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
                               size_t ws_bytes, void *stream) {
-    TM_TRY(check_image(H, W));
-    TM_TRY(check_params(p));
-    if (!v || !grad_out || !grad_v || !grad_params || !valid_prec(prec)) return TM_ERR_ARG;
-    TM_TRY(check_plane(H, W, ld_v));
-    TM_TRY(check_plane(H, W, ld_g));
-    TM_TRY(check_plane(H, W, ld_gv));
+    TM_TRY(check_bwd_common(v, ld_v, H, W, p, grad_out, ld_g, grad_v, ld_gv, grad_params));
+    if (!valid_prec(prec)) return TM_ERR_ARG;
     TM_TRY(check_table(H, W, ld_sat, sat));
     if (prec == TM_SAT_C32X2 && !offsets) return TM_ERR_ARG;
     if (p->n_bins > 1) {
         if (!edges) return TM_ERR_ARG;
         TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
     }
-    if (!aligned(grad_params, 8)) return TM_ERR_ALIGN;
-    BwdPlan plan = make_bwd_plan(H, W, p->n_scales);
+    BwdPlan plan = make_bwd_plan(H, W, p->n_scales, p->ry, true);
     TM_TRY(check_ws(ws, ws_bytes, plan.total));
-    BwdArgs a{};
-    a.v = v;
-    a.ld_v = ld_v;
-    a.H = H;
-    a.W = W;
-    a.sat = sat;
-    a.ld_sat = ld_sat;
-    a.prec = (int)prec;
-    a.offsets = offsets;
-    a.hist = hist_cum;
-    a.ld_hist = ld_hist;
-    a.plane_stride = plane_stride;
-    a.edges = edges;
-    a.p = to_query(p);
-    a.g = grad_out;
-    a.ld_g = ld_g;
-    a.grad_v = grad_v;
-    a.ld_gv = ld_gv;
-    a.grad_params = grad_params;
-    return from_hip(launch_backward(a, plan, ws, (hipStream_t)stream));
+    float *resid = reinterpret_cast<float *>(static_cast<char *>(ws) + plan.resid);
+    hipStream_t s = (hipStream_t)stream;
+    // the residual planes from the tables (the query in training mode, no tone output)
+    const QueryParams q = to_query(p);
+    tm_status st = from_hip(launch_forward(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets,
+                                           hist_cum, ld_hist, plane_stride, edges, q, nullptr,
+                                           W, resid, s));
+    if (st != TM_OK) return st;
+    return run_backward_resid(v, ld_v, H, W, p, resid, grad_out, ld_g, grad_v, ld_gv,
+                              grad_params, plan, ws, s);
 }
 
 }  // extern "C"

@@ -175,6 +175,16 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
     return k * q + (k < r ? k : r) + i;
 }
 
+// Comb schedule of the per-pixel kernels that read window corners: block b covers column
+// tile tx and row group rg, ordered by phase inside a period of p4 row groups, then tooth,
+// then column tile (see comb_params).
+__device__ __forceinline__ void comb_map(uint32_t b, int tiles_x, int p4, int teeth, int &tx,
+                                         int &rg) {
+    tx = (int)(b % (uint32_t)tiles_x);
+    const uint32_t r = b / (uint32_t)tiles_x;
+    rg = (int)(r % (uint32_t)teeth) * p4 + (int)(r / (uint32_t)teeth);
+}
+
 // Batched launches walk one flattened list of work items spanning every image; the image
 // of item g is the last i with prefix[i] <= g (prefix has count+1 entries, prefix[0] = 0).
 __device__ __forceinline__ int find_image(const int64_t *prefix, int count, int64_t g) {

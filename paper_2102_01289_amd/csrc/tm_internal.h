@@ -119,6 +119,14 @@ hipError_t launch_tables_batch(const BatchScan &b, hipStream_t s);
 // Items of stage 2 of one image (thread-level): nq*H + nq*W + nq*tiles_y.
 int64_t scan_stage2_items(const ScanK &k, bool sat);
 
+// ---------------------------------------------------------------- comb schedule
+// Output rows y and y + 2r + 1 read the same table row at the field of radius r, and the
+// pyramid's halving radii put the other fields' shared rows a few rows apart.  Ordering
+// blocks by phase within a period of the smallest window height, then by tooth, keeps every
+// shared corner row in flight at once.  p4 = period in row groups of `rows` rows; teeth =
+// number of periods; one tooth (plain row-major order) for short windows.
+void comb_params(int H, int rows, const int *ry, int n_scales, int *p4, int *teeth);
+
 // ---------------------------------------------------------------- query (a4)
 struct QueryParams {
     int n_bins, n_scales;
@@ -140,9 +148,13 @@ struct FwdK {
     float *out;
     int64_t ld_out;
     int tiles_x;
+    int p4, teeth;      // comb schedule: period in 4-row groups, number of teeth
+    float *resid;       // training forward: 2s + 2 residual planes of H*W (else null)
+    int64_t rstride;
 };
 constexpr int kQueryRows = 4;   // a query block covers 64 columns x 4 rows
-int64_t query_tiles(int H, int W);
+// Blocks of one image's fused query (the comb schedule may include idle blocks).
+int64_t query_blocks(const FwdK &k);
 // Fused query of a batch: one persistent launch (grid a multiple of 8) over every image's
 // tiles (device arrays ks[count], tile_prefix[count+1]).
 hipError_t launch_forward_batch(const FwdK *ks, const int64_t *tile_prefix, int count, int prec,
@@ -154,7 +166,8 @@ FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int6
 hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void *sat,
                           int64_t ld_sat, int prec, const float *offsets, const uint32_t *hist,
                           int64_t ld_hist, int64_t plane_stride, const float *edges,
-                          const QueryParams &p, float *out, int64_t ld_out, hipStream_t s);
+                          const QueryParams &p, float *out, int64_t ld_out, float *resid,
+                          hipStream_t s);
 
 // Prefix scan of two FP64 planes stored in reversed pixel order (pitch ld_d), written back as
 // dv = s1 + 2 v s2 in forward order: the suffix sums of the backward.
@@ -163,18 +176,12 @@ hipError_t launch_suffix_adjoint(const double2 *d, int64_t ld_d, const float *v,
                                  void *ws, hipStream_t s);
 
 // ---------------------------------------------------------------- backward (a5)
-struct BwdArgs {
+struct BwdResidArgs {
     const float *v;
     int64_t ld_v;
     int H, W;
-    const void *sat;
-    int64_t ld_sat;
-    int prec;
-    const float *offsets;
-    const uint32_t *hist;
-    int64_t ld_hist, plane_stride;
-    const float *edges;
     QueryParams p;
+    const float *resid;      // 2s + 2 planes of H*W (pitch W)
     const float *g;
     int64_t ld_g;
     float *grad_v;
@@ -183,10 +190,13 @@ struct BwdArgs {
 };
 struct BwdPlan {
     int64_t nblocks;
-    size_t A, Rb, Cb, Dr, part, scan, total;
+    int p4, teeth, nchunks;
+    size_t resid, Rb, Cp, Cb, Dr, part, scan, total;
     ScanPlan scan_plan;
 };
-BwdPlan make_bwd_plan(int H, int W, int n_scales);
-hipError_t launch_backward(const BwdArgs &a, const BwdPlan &plan, void *ws, hipStream_t s);
+// with_resid: also reserve the residual planes (the table-based backward rebuilds them).
+BwdPlan make_bwd_plan(int H, int W, int n_scales, const int *ry, bool with_resid);
+hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, void *ws,
+                                 hipStream_t s);
 
 }  // namespace tmo

@@ -237,6 +237,29 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
 }
 
 // ================================================================ stage 2
+// Exclusive prefix of n values at stride `stride`, the loads issued 8 at a time so that the
+// scan's add chain does not serialise the memory latency.
+template <class A, class T>
+__device__ __forceinline__ void excl_scan(const T *src, T *dst, int n, int64_t stride) {
+    T run = A::zero();
+    int t = 0;
+    for (; t + 8 <= n; t += 8) {
+        T a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = src[(int64_t)(t + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dst[(int64_t)(t + u) * stride] = run;
+            run = A::add(run, a[u]);
+        }
+    }
+    for (; t < n; ++t) {
+        const T a = src[(int64_t)t * stride];
+        dst[(int64_t)t * stride] = run;
+        run = A::add(run, a);
+    }
+}
+
 // Item id in [0, nq H) scans RS along tx for one (quantity, row); [nq H, nq H + nq W) scans
 // CS along ty for one (quantity, column); the rest scan TT along tx for one (quantity, ty).
 template <int P, bool SAT>
@@ -251,16 +274,12 @@ __device__ __forceinline__ void stage2_item(const ScanK &k, int64_t idx) {
         const int q = (int)(idx / k.H);
         const int64_t y = idx % k.H;
         if (q < nq_sat) {
-            const T *rs = reinterpret_cast<const T *>(k.rs_sat) + ((int64_t)q * k.H + y) * k.tiles_x;
-            T *xc = reinterpret_cast<T *>(k.xc_sat) + ((int64_t)q * k.H + y) * k.tiles_x;
-            T run = A::zero();
-            for (int t = 0; t < k.tiles_x; ++t) { T a = rs[t]; xc[t] = run; run = A::add(run, a); }
+            const int64_t o = ((int64_t)q * k.H + y) * k.tiles_x;
+            excl_scan<A>(reinterpret_cast<const T *>(k.rs_sat) + o,
+                         reinterpret_cast<T *>(k.xc_sat) + o, k.tiles_x, 1);
         } else {
-            const int64_t qq = q - nq_sat;
-            const uint32_t *rs = k.rs_h + (qq * k.H + y) * k.tiles_x;
-            uint32_t *xc = k.xc_h + (qq * k.H + y) * k.tiles_x;
-            uint32_t run = 0;
-            for (int t = 0; t < k.tiles_x; ++t) { uint32_t a = rs[t]; xc[t] = run; run += a; }
+            const int64_t o = ((int64_t)(q - nq_sat) * k.H + y) * k.tiles_x;
+            excl_scan<AddU32>(k.rs_h + o, k.xc_h + o, k.tiles_x, 1);
         }
     } else if (idx < n1 + n2) {
         // CSE[q][ty][x] = sum_{ty' < ty} CS[q][ty'][x]
@@ -268,24 +287,12 @@ __device__ __forceinline__ void stage2_item(const ScanK &k, int64_t idx) {
         const int q = (int)(id / k.W);
         const int64_t x = id % k.W;
         if (q < nq_sat) {
-            const T *cs = reinterpret_cast<const T *>(k.cs_sat) + (int64_t)q * k.tiles_y * k.W + x;
-            T *ce = reinterpret_cast<T *>(k.cse_sat) + (int64_t)q * k.tiles_y * k.W + x;
-            T run = A::zero();
-            for (int t = 0; t < k.tiles_y; ++t) {
-                T a = cs[(int64_t)t * k.W];
-                ce[(int64_t)t * k.W] = run;
-                run = A::add(run, a);
-            }
+            const int64_t o = (int64_t)q * k.tiles_y * k.W + x;
+            excl_scan<A>(reinterpret_cast<const T *>(k.cs_sat) + o,
+                         reinterpret_cast<T *>(k.cse_sat) + o, k.tiles_y, k.W);
         } else {
-            const int64_t qq = q - nq_sat;
-            const uint32_t *cs = k.cs_h + qq * k.tiles_y * k.W + x;
-            uint32_t *ce = k.cse_h + qq * k.tiles_y * k.W + x;
-            uint32_t run = 0;
-            for (int t = 0; t < k.tiles_y; ++t) {
-                uint32_t a = cs[(int64_t)t * k.W];
-                ce[(int64_t)t * k.W] = run;
-                run += a;
-            }
+            const int64_t o = (int64_t)(q - nq_sat) * k.tiles_y * k.W + x;
+            excl_scan<AddU32>(k.cs_h + o, k.cse_h + o, k.tiles_y, k.W);
         }
     } else {
         // TTE[q][ty][tx] = sum_{tx' < tx} TT[q][ty][tx']
@@ -294,16 +301,12 @@ __device__ __forceinline__ void stage2_item(const ScanK &k, int64_t idx) {
         const int q = (int)(id / k.tiles_y);
         const int64_t ty = id % k.tiles_y;
         if (q < nq_sat) {
-            const T *tt = reinterpret_cast<const T *>(k.tt_sat) + ((int64_t)q * k.tiles_y + ty) * k.tiles_x;
-            T *te = reinterpret_cast<T *>(k.tte_sat) + ((int64_t)q * k.tiles_y + ty) * k.tiles_x;
-            T run = A::zero();
-            for (int t = 0; t < k.tiles_x; ++t) { T a = tt[t]; te[t] = run; run = A::add(run, a); }
+            const int64_t o = ((int64_t)q * k.tiles_y + ty) * k.tiles_x;
+            excl_scan<A>(reinterpret_cast<const T *>(k.tt_sat) + o,
+                         reinterpret_cast<T *>(k.tte_sat) + o, k.tiles_x, 1);
         } else {
-            const int64_t qq = q - nq_sat;
-            const uint32_t *tt = k.tt_h + (qq * k.tiles_y + ty) * k.tiles_x;
-            uint32_t *te = k.tte_h + (qq * k.tiles_y + ty) * k.tiles_x;
-            uint32_t run = 0;
-            for (int t = 0; t < k.tiles_x; ++t) { uint32_t a = tt[t]; te[t] = run; run += a; }
+            const int64_t o = ((int64_t)(q - nq_sat) * k.tiles_y + ty) * k.tiles_x;
+            excl_scan<AddU32>(k.tt_h + o, k.tte_h + o, k.tiles_x, 1);
         }
     }
 }

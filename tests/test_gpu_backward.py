@@ -106,3 +106,30 @@ def test_autograd_function(recompute):
     gv, gp = _gpu_grad(lum, 5, rx, ry, 0.1, "c32x2", g.cpu().numpy())
     assert np.array_equal(x.grad.cpu().numpy().astype(np.float64), gv)
     assert np.allclose([eps.grad.item(), lo.grad.item(), hi.grad.item()], gp, rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["c32x2", "f64"])
+def test_training_forward_and_residual_backward(prec):
+    H, W = 96, 130
+    rgb = rgb_case(H, W, 5, seed=21)
+    p = tm.make_params(5, 5, eps=0.1, H=H, W=W)
+    m = tm.ToneMapper(H, W, p, prec)
+    L = m.run(to_dev(rgb)).clone()
+    Lt = m.run_train(to_dev(rgb)).clone()
+    assert torch.equal(L, Lt)                     # the training form changes no output bit
+    g = to_dev(np.random.default_rng(4).standard_normal((H, W)).astype(np.float32))
+    a = [t.clone() for t in m.backward_resid(g)]
+    b = [t.clone() for t in m.backward(g)]        # from the tables
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # residual planes against the oracle's per-field quantities
+    lum = lum_ref(rgb)
+    e = edges_ref(lum, 5)
+    rx, ry = oracle.paper_radii(H, W, 5)
+    Lr, Lj, Wj, varj = oracle.forward(lum, e, rx, ry, 0.1, per_scale=True)
+    R = m.resid.cpu().numpy().astype(np.float64)
+    D = Wj.sum(0)
+    Pj = (Lj - 0.0) / 1.0
+    pbar = np.where(D > 0, (Wj * Pj).sum(0) / np.where(D > 0, D, 1), Pj.mean(0))
+    assert np.max(np.abs(R[11] - pbar)) <= 1e-4
+    E = np.where(D > 0, ((Lj - Lr) / np.where(D > 0, D, 1) * (-varj / (varj + 0.1) ** 2)).sum(0), 0)
+    assert np.max(np.abs(R[10] - E)) <= 1e-3 * (1 + np.max(np.abs(E)))
