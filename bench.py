@@ -11,6 +11,7 @@ backward (adjoint of the same path) when it is enabled.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +22,11 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "wdr_4000x3000"
 PEAK_HBM_GBS = 8000.0
+# PMC summary of the roofline kernel (FETCH_SIZE and WRITE_SIZE per dispatch, calibrated on a
+# plain copy kernel), and the sources whose digest it records
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forward_kernel_wdr_4000x3000_traffic.md")
+QUERY_SOURCES = ("paper_2102_01289_amd/csrc/tm_query.hip", "paper_2102_01289_amd/csrc/tm_device.h",
+                 "paper_2102_01289_amd/csrc/tm_internal.h", "paper_2102_01289_amd/build.py")
 
 
 def _parse():
@@ -167,6 +173,39 @@ def query_bytes_per_px(prec: str, n_bins: int, resid_planes: int = 0) -> int:
     training form the FP32 residual planes out."""
     sat = {"f32": 8, "c32x2": 16, "f64": 16}[prec]
     return 4 + sat + 4 * (n_bins - 1) + 4 + 4 * resid_planes
+
+
+def query_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in QUERY_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(variant: str, prec: str, n_bins: int, n_scales: int):
+    """HBM bytes per launch of the fused query from the committed counter summary: FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch) each times its copy-kernel calibration factor.  None when
+    no record matches this configuration or the kernel's sources changed since the counters
+    were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    digest = query_source_digest()
+    for ln in lines:
+        if not ln.startswith("traffic-record: "):
+            continue
+        r = json.loads(ln[len("traffic-record: "):])
+        if (r["variant"], r["prec"], r["n_bins"], r["n_scales"], r["workload"]) != (
+                variant, prec, n_bins, n_scales, WORKLOAD):
+            continue
+        if r["source_digest"] != digest:
+            return None
+        return int(round(r["fetch_kib"] * 1024 * r["fetch_factor"] +
+                         r["write_kib"] * 1024 * r["write_factor"]))
+    return None
 
 
 def cpu_baseline(rgb, params_np, backward: bool):
@@ -328,7 +367,9 @@ def main():
                                 "residual planes)") if do_bwd else
                      "forward_kernel (fused query+blend)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic("train" if do_bwd else "forward", args.prec,
+                                                 args.n_bins, args.n_scales),
                      "algorithmic_bytes_per_launch": qbytes,
                      "avg_kernel_ms": round(q_ms, 4)},
     }

@@ -200,11 +200,13 @@ int32_t tm_residual_planes(int32_t n_scales);
 /* The forward of tm_tonemap_forward plus, for the backward, per-pixel residual planes that
  * do not depend on the upstream gradient (Eq. 3, 4, 10 differentiated): with
  * c_j = (L_j - L)/D eps/(var_j + eps)^2 (zero where var_j was clamped or D = 0),
- *   plane j       R1_j = -2 c_j (S1_j/N_j) / N_j      (j < s)
- *   plane s + j   R2_j = c_j / N_j
- *   plane 2s      E = sum_j (L_j - L)/D (-var_j/(var_j + eps)^2)
- *   plane 2s + 1  Pbar = sum_j W_j P_j / D (mean of P_j where D = 0)
- * resid: tm_residual_planes(s) planes of H*W FP32, pitch W, plane stride H*W, caller-owned.
+ *   R1_j = -2 c_j (S1_j/N_j) / N_j,  R2_j = c_j / N_j          (j < s)
+ *   E    = sum_j (L_j - L)/D (-var_j/(var_j + eps)^2)
+ *   Pbar = sum_j W_j P_j / D (mean of P_j where D = 0)
+ * resid: tm_residual_planes(s) * H * W FP32 values, caller-owned, laid out as s interleaved
+ * pair planes (pair plane j starts at resid + 2*j*H*W and holds {R1_j, R2_j} of pixel (x, y)
+ * at offset 2*(y*W + x)), then the E plane at resid + 2*s*H*W and the Pbar plane at
+ * resid + (2*s + 1)*H*W (pitch W).
  * A window of one pixel has zero variance by definition. */
 tm_status tm_tonemap_forward_train(const float *v, int64_t ld_v, int32_t H, int32_t W,
                                    const void *sat, int64_t ld_sat, tm_sat_prec prec,

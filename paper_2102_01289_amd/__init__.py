@@ -19,7 +19,7 @@ __all__ = [
     "tm_luminance", "tm_image_stats", "tm_prologue", "tm_integral_image",
     "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
-    "residual_planes", "ToneMapper", "tonemap", "Batch",
+    "residual_planes", "residual_pairs", "ToneMapper", "tonemap", "Batch",
 ]
 
 
@@ -259,9 +259,17 @@ def residual_planes(n_scales: int) -> int:
     return int(_lib().tm_residual_planes(n_scales))
 
 
+def residual_pairs(resid: torch.Tensor, n_scales: int) -> torch.Tensor:
+    """View of the interleaved {R1_j, R2_j} pairs of a residual buffer: [s, H, W, 2]."""
+    _, H, W = resid.shape
+    return resid[:2 * n_scales].reshape(n_scales, H, W, 2)
+
+
 def tm_tonemap_forward_train(v, sat: Table, hist: Table | None, edges, params, offsets=None,
                              out=None, resid=None, stream=None):
-    """Forward plus the residual planes of the backward: (L [H, W], resid [2s+2, H, W])."""
+    """Forward plus the residual planes of the backward: (L [H, W], resid [2s+2, H, W]).
+    resid holds the s interleaved {R1_j, R2_j} pair planes (see residual_pairs) in its first
+    2s planes, then E and Pbar."""
     H, W, ld = _img(v, "v")
     if out is None:
         out = torch.empty((H, W), dtype=torch.float32, device=v.device)

@@ -31,7 +31,6 @@ constexpr int kBlock = 256;
 constexpr int kRows = kBlock / kWave;
 constexpr int kS = 8;            // TM_MAX_SCALES
 constexpr int kChunk = 64;       // rows per partial of the column sums
-constexpr int kScalarBlocks = 1024;
 
 struct BwdK {
     const float *v;
@@ -40,17 +39,19 @@ struct BwdK {
     QueryParams p;
     const float *g;
     int64_t ld_g;
-    const float *R;  // residual planes: R1_j at j, R2_j at s + j, E at 2s, Pbar at 2s + 1
+    const float *R;  // residuals: pair planes {R1_j, R2_j} for j < s, then E, then Pbar
+    double *Rp;      // [2][s][ncol][H] row range sums of g R per 64-column tile
     double *Rb;      // [2][s][H]  row range sums of g R
     double *Cp;      // [2][s][nchunks][W] partial column range sums
     double *Cb;      // [2][s][W]  column range sums
     double2 *Dr;     // [H][W] deposits {D1, D2} in reversed order
-    double *part;    // [kScalarBlocks][3] scalar partials
+    double *part;    // [ncol * nchunks][3] scalar partials
     int tiles_x, p4, teeth, nchunks;
 };
 
-__device__ __forceinline__ const float *rplane(const BwdK &k, int q, int j) {
-    return k.R + ((int64_t)q * k.p.n_scales + j) * (int64_t)k.H * k.W;
+// Residual pair plane of field j: {R1_j, R2_j} per pixel, pitch W.
+__device__ __forceinline__ const float2 *rpair(const BwdK &k, int j) {
+    return reinterpret_cast<const float2 *>(k.R) + (int64_t)j * k.H * k.W;
 }
 
 struct Sum3 {
@@ -76,130 +77,144 @@ __device__ Sum3 block_sum3(Sum3 v) {
     return r;
 }
 
-// (1a) Rb[q][j][y] = sum over x >= W-1-rx_j of g R_qj at (x, y): one block per row, every
-// field and both planes in one pass, combined in a fixed order.
-__global__ void __launch_bounds__(kBlock) border_rows_kernel(BwdK k) {
-    const int s = k.p.n_scales, y = blockIdx.x;
-    int lo[kS], x0 = k.W;
-    double acc[2][kS];
-#pragma unroll
-    for (int j = 0; j < kS; ++j) {
-        acc[0][j] = acc[1][j] = 0.0;
-        lo[j] = j < s ? max(k.W - 1 - k.p.rx[j], 0) : k.W;
-        x0 = min(x0, lo[j]);
-    }
-    const int64_t row = (int64_t)y * k.W;
-    for (int x = x0 + (int)threadIdx.x; x < k.W; x += kBlock) {
-        const double gx = (double)k.g[(int64_t)y * k.ld_g + x];
-#pragma unroll
-        for (int j = 0; j < kS; ++j) {
-            if (j < s && x >= lo[j]) {
-                acc[0][j] = __builtin_fma(gx, (double)rplane(k, 0, j)[row + x], acc[0][j]);
-                acc[1][j] = __builtin_fma(gx, (double)rplane(k, 1, j)[row + x], acc[1][j]);
-            }
-        }
-    }
-    __shared__ double sh[kRows][2 * kS];
-#pragma unroll
-    for (int j = 0; j < kS; ++j)
-        for (int m = 32; m >= 1; m >>= 1) {
-            acc[0][j] += __shfl_xor(acc[0][j], m);
-            acc[1][j] += __shfl_xor(acc[1][j], m);
-        }
-    if (lane_id() == 0) {
-#pragma unroll
-        for (int j = 0; j < kS; ++j) {
-            sh[threadIdx.x / kWave][j] = acc[0][j];
-            sh[threadIdx.x / kWave][kS + j] = acc[1][j];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < (unsigned)(2 * s)) {
-        const int q = threadIdx.x / s, j = threadIdx.x % s;
-        double r = sh[0][q * kS + j];
-        for (int w = 1; w < kRows; ++w) r += sh[w][q * kS + j];
-        k.Rb[((int64_t)q * s + j) * k.H + y] = r;
-    }
-}
-
-// (1b) partial column sums over y >= H-1-ry_j of g R_qj, one block per (64 columns, 64
-// rows): Cp[q][j][chunk][x].
-__global__ void __launch_bounds__(kBlock) border_cols_kernel(BwdK k) {
+// (1) One streaming pass over g, the residual pairs, E and Pbar, one block per (64 columns,
+// kChunk rows):
+//   Rp[q][j][ct][y] = sum over the tile's columns x >= W-1-rx_j of g R_qj(x, y),
+//   Cp[q][j][chunk][x] = sum over the tile's rows y >= H-1-ry_j of g R_qj(x, y),
+//   part[block] = {sum g E, sum g (1 - Pbar), sum g Pbar},
+// each combined in a fixed order.  A residual pair is loaded only where some field needs it.
+__global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
     const int s = k.p.n_scales;
     const int ncol = (k.W + kWave - 1) / kWave;
     const int ct = blockIdx.x % ncol, ch = blockIdx.x / ncol;
-    const int x = ct * kWave + lane_id(), w = threadIdx.x / kWave;
-    int lo[kS];
-    double acc[2][kS];
+    const int x = ct * kWave + lane_id(), w = wave_id();
+    const int y0 = ch * kChunk, y1 = min(k.H, y0 + kChunk);
+    const int64_t hw = (int64_t)k.H * k.W;
+    const float *E = k.R + 2 * (int64_t)s * hw, *Pb = E + hw;
+    int lox[kS], loy[kS];
+    double cacc[2][kS];
 #pragma unroll
     for (int j = 0; j < kS; ++j) {
-        acc[0][j] = acc[1][j] = 0.0;
-        lo[j] = j < s ? max(k.H - 1 - k.p.ry[j], 0) : k.H;
+        lox[j] = j < s ? max(k.W - 1 - k.p.rx[j], 0) : k.W;
+        loy[j] = j < s ? max(k.H - 1 - k.p.ry[j], 0) : k.H;
+        cacc[0][j] = cacc[1][j] = 0.0;
     }
-    if (x < k.W) {
-        const int y1 = min(k.H, (ch + 1) * kChunk);
-        for (int y = ch * kChunk + w; y < y1; y += kRows) {
-            const double gx = (double)k.g[(int64_t)y * k.ld_g + x];
-            const int64_t o = (int64_t)y * k.W + x;
+    __shared__ double shr[2 * kS][kChunk];
+    Sum3 sacc{0.0, 0.0, 0.0};
+    const int xc = min(x, k.W - 1);      // in-image address for the lanes past the edge
+    const bool in = x < k.W;
+    const int tile_end = min(ct * kWave + kWave, k.W);
+    for (int y = y0 + w; y < y1; y += kRows) {   // y is wave-uniform
+        const int64_t o = (int64_t)y * k.W + xc;
+        // load phase: every load of the row issued before any reduction
+        const float gf = k.g[(int64_t)y * k.ld_g + xc];
+        const float ef = E[o], pf = Pb[o];
+        float2 rr[kS];
 #pragma unroll
-            for (int j = 0; j < kS; ++j) {
-                if (j < s && y >= lo[j]) {
-                    acc[0][j] = __builtin_fma(gx, (double)rplane(k, 0, j)[o], acc[0][j]);
-                    acc[1][j] = __builtin_fma(gx, (double)rplane(k, 1, j)[o], acc[1][j]);
+        for (int j = 0; j < kS; ++j) {
+            rr[j] = make_float2(0.f, 0.f);
+            // wave-uniform: does any field-j range sum need this tile row?
+            if (j < s && (tile_end > lox[j] || y >= loy[j])) rr[j] = rpair(k, j)[o];
+        }
+        const double gx = in ? (double)gf : 0.0;
+        const double pb = (double)pf;
+        sacc.a = __builtin_fma(gx, (double)ef, sacc.a);
+        sacc.b = __builtin_fma(gx, 1.0 - pb, sacc.b);
+        sacc.c = __builtin_fma(gx, pb, sacc.c);
+#pragma unroll
+        for (int j = 0; j < kS; ++j) {
+            if (j < s) {
+                const double a = gx * (double)rr[j].x, b = gx * (double)rr[j].y;
+                if (y >= loy[j]) { cacc[0][j] += a; cacc[1][j] += b; }
+                double ra = 0.0, rb = 0.0;
+                if (tile_end > lox[j]) {   // block-uniform: the row range reaches this tile
+                    const bool inr = x >= lox[j];
+                    ra = wave_sum<Acc<kF64>>(inr ? a : 0.0);
+                    rb = wave_sum<Acc<kF64>>(inr ? b : 0.0);
+                }
+                if (lane_id() == 0) {
+                    shr[j][y - y0] = ra;
+                    shr[kS + j][y - y0] = rb;
                 }
             }
         }
     }
-    __shared__ double sh[kRows][2 * kS][kWave];
+    // column partials: the four waves' sums in a fixed order
+    __shared__ double shc[kRows][kWave];
+    for (int qj = 0; qj < 2 * s; ++qj) {
+        const int q = qj / s, j = qj % s;
+        double v = 0.0;
 #pragma unroll
-    for (int j = 0; j < kS; ++j) {
-        sh[w][j][lane_id()] = acc[0][j];
-        sh[w][kS + j][lane_id()] = acc[1][j];
+        for (int jj = 0; jj < kS; ++jj)
+            if (jj == j) v = q ? cacc[1][jj] : cacc[0][jj];
+        __syncthreads();
+        shc[w][lane_id()] = v;
+        __syncthreads();
+        if (w == 0 && x < k.W) {
+            double r = shc[0][lane_id()];
+            for (int i = 1; i < kRows; ++i) r += shc[i][lane_id()];
+            k.Cp[(((int64_t)q * s + j) * k.nchunks + ch) * k.W + x] = r;
+        }
     }
-    __syncthreads();
-    if (w == 0 && x < k.W) {
-        for (int q = 0; q < 2; ++q)
-            for (int j = 0; j < s; ++j) {
-                double r = sh[0][q * kS + j][lane_id()];
-                for (int i = 1; i < kRows; ++i) r += sh[i][q * kS + j][lane_id()];
-                k.Cp[(((int64_t)q * s + j) * k.nchunks + ch) * k.W + x] = r;
-            }
+    // row partials, coalesced along y
+    for (int t = threadIdx.x; t < 2 * s * (y1 - y0); t += kBlock) {
+        const int qj = t / (y1 - y0), r = t % (y1 - y0);
+        const int q = qj / s, j = qj % s;
+        k.Rp[(((int64_t)q * s + j) * ncol + ct) * k.H + y0 + r] = shr[q * kS + j][r];
+    }
+    const Sum3 tot = block_sum3(sacc);
+    if (threadIdx.x == 0) {
+        k.part[3 * blockIdx.x] = tot.a;
+        k.part[3 * blockIdx.x + 1] = tot.b;
+        k.part[3 * blockIdx.x + 2] = tot.c;
     }
 }
 
-// (1c) Cb[q][j][x] = sum over chunks of Cp (loads issued 8 at a time).
-__global__ void __launch_bounds__(kBlock) border_cols_reduce_kernel(BwdK k) {
-    const int s = k.p.n_scales;
-    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (id >= (int64_t)2 * s * k.W) return;
-    const int64_t qj = id / k.W, x = id % k.W;
-    const double *src = k.Cp + qj * k.nchunks * k.W + x;
+// (1') Rb[q][j][y] = sum over column tiles of Rp and Cb[q][j][x] = sum over row chunks of Cp,
+// in a fixed order, loads issued 8 at a time.
+__device__ __forceinline__ double strided_sum(const double *src, int n, int64_t stride) {
     double r = 0.0;
     int c = 0;
-    for (; c + 8 <= k.nchunks; c += 8) {
+    for (; c + 8 <= n; c += 8) {
         double a[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = src[(int64_t)(c + u) * k.W];
+        for (int u = 0; u < 8; ++u) a[u] = src[(int64_t)(c + u) * stride];
 #pragma unroll
         for (int u = 0; u < 8; ++u) r += a[u];
     }
-    for (; c < k.nchunks; ++c) r += src[(int64_t)c * k.W];
-    k.Cb[qj * k.W + x] = r;
+    for (; c < n; ++c) r += src[(int64_t)c * stride];
+    return r;
+}
+
+__global__ void __launch_bounds__(kBlock) border_reduce_kernel(BwdK k) {
+    const int s = k.p.n_scales;
+    const int ncol = (k.W + kWave - 1) / kWave;
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t nr = (int64_t)2 * s * k.H, nc = (int64_t)2 * s * k.W;
+    if (id < nr) {
+        const int64_t qj = id / k.H, y = id % k.H;
+        k.Rb[qj * k.H + y] = strided_sum(k.Rp + qj * ncol * k.H + y, ncol, k.H);
+    } else if (id < nr + nc) {
+        const int64_t i = id - nr, qj = i / k.W, x = i % k.W;
+        k.Cb[qj * k.W + x] = strided_sum(k.Cp + qj * k.nchunks * k.W + x, k.nchunks, k.W);
+    }
 }
 
 // (2) deposits.  Virtual pixel (x', y') holds the deposit at corner c = (W-1-x', H-1-y').
 // For field j the corners that equal c come from at most one pixel per corner type,
 // except where clamping maps a whole range of pixels onto the last column / row; those
 // ranges use Rb, Cb and (for the bottom-right corner) their total K, which the block holding
-// virtual pixel (0, 0) forms cooperatively before use.
+// virtual pixel (0, 0) forms cooperatively before use.  The four gathers of a field are
+// issued together, branch-free: a corner that does not exist reads a clamped in-image
+// address with weight 0 (such lanes share one cache line).  Rows are wave-uniform.
 __global__ void __launch_bounds__(kBlock) deposit_kernel(BwdK k) {
     const int s = k.p.n_scales;
     __shared__ double shK[2][kS];
     int tx, rg;
-    comb_map(blockIdx.x, k.tiles_x, k.p4, k.teeth, tx, rg);
+    comb_map(xcd_tile(blockIdx.x, gridDim.x), k.tiles_x, k.p4, k.teeth, tx, rg);
     if (tx == 0 && rg == 0) {
         __shared__ double shp[kRows][2 * kS];
-        const int w = threadIdx.x / kWave;
+        const int w = wave_id();
         for (int qj = 0; qj < 2 * s; ++qj) {
             const int q = qj / s, j = qj % s;
             const int y0 = max(k.H - 1 - k.p.ry[j], 0);
@@ -218,86 +233,57 @@ __global__ void __launch_bounds__(kBlock) deposit_kernel(BwdK k) {
         __syncthreads();
     }
     const int xv = tx * kWave + lane_id();
-    const int yv = rg * kRows + (int)(threadIdx.x / kWave);
+    const int yv = rg * kRows + wave_id();
     if (xv >= k.W || yv >= k.H) return;
-    const int cx = k.W - 1 - xv, cy = k.H - 1 - yv;
+    const int cx = k.W - 1 - xv, cy = k.H - 1 - yv;   // cy is wave-uniform
     const bool lastx = cx == k.W - 1, lasty = cy == k.H - 1;
     double d0 = 0.0, d1 = 0.0;
-    // g R1 and g R2 at pixel (px, py), added with sign sg
-    auto add = [&](int j, int px, int py, double sg) {
-        const int64_t o = (int64_t)py * k.W + px;
-        const double gs = sg * (double)k.g[(int64_t)py * k.ld_g + px];
-        d0 = __builtin_fma(gs, (double)rplane(k, 0, j)[o], d0);
-        d1 = __builtin_fma(gs, (double)rplane(k, 1, j)[o], d1);
-    };
-    for (int j = 0; j < s; ++j) {
-        const int rx = k.p.rx[j], ry = k.p.ry[j];
-        const int pxp = cx - rx;            // pixel whose x+ corner is cx (cx < W-1)
-        const int pxm = cx + rx + 1;        // pixel whose x- corner is cx
-        const int pyp = cy - ry;
-        const int pym = cy + ry + 1;
-        const bool vxm = pxm <= k.W - 1, vym = pym <= k.H - 1;
-        const double *R0 = k.Rb + (int64_t)j * k.H, *R1 = k.Rb + ((int64_t)s + j) * k.H;
-        const double *C0 = k.Cb + (int64_t)j * k.W, *C1 = k.Cb + ((int64_t)s + j) * k.W;
-        // (x+, y+) corner
-        if (!lastx && !lasty) {
-            if (pxp >= 0 && pyp >= 0) add(j, pxp, pyp, 1.0);
-        } else if (lastx && !lasty) {
-            if (pyp >= 0) { d0 += R0[pyp]; d1 += R1[pyp]; }
-        } else if (!lastx && lasty) {
-            if (pxp >= 0) { d0 += C0[pxp]; d1 += C1[pxp]; }
-        } else {
-            d0 += shK[0][j];
-            d1 += shK[1][j];
-        }
-        // (x-, y+) corner, sign -
-        if (vxm) {
-            if (!lasty) {
-                if (pyp >= 0) add(j, pxm, pyp, -1.0);
-            } else {
-                d0 -= C0[pxm];
-                d1 -= C1[pxm];
+#pragma unroll
+    for (int j = 0; j < kS; ++j) {
+        if (j < s) {
+            const int rx = k.p.rx[j], ry = k.p.ry[j];
+            const int pxp = cx - rx;        // pixel whose x+ corner is cx (cx < W-1)
+            const int pxm = cx + rx + 1;    // pixel whose x- corner is cx
+            const int pyp = cy - ry;
+            const int pym = cy + ry + 1;
+            const bool okxp = !lastx && pxp >= 0, okxm = pxm <= k.W - 1;
+            const bool okyp = !lasty && pyp >= 0, okym = pym <= k.H - 1;
+            const int ax = max(pxp, 0), bx = min(pxm, k.W - 1);
+            const int ay = max(pyp, 0), by = min(pym, k.H - 1);
+            const float2 *Rj = rpair(k, j);
+            const float2 *Ra = Rj + (int64_t)ay * k.W, *Rb_ = Rj + (int64_t)by * k.W;
+            const float *ga = k.g + (int64_t)ay * k.ld_g, *gb = k.g + (int64_t)by * k.ld_g;
+            const float2 r_pp = Ra[ax], r_mp = Ra[bx], r_pm = Rb_[ax], r_mm = Rb_[bx];
+            const float g_pp = ga[ax], g_mp = ga[bx], g_pm = gb[ax], g_mm = gb[bx];
+            const double w_pp = okxp && okyp ? (double)g_pp : 0.0;
+            const double w_mp = okxm && okyp ? -(double)g_mp : 0.0;
+            const double w_pm = okxp && okym ? -(double)g_pm : 0.0;
+            const double w_mm = okxm && okym ? (double)g_mm : 0.0;
+            d0 = __builtin_fma(w_pp, (double)r_pp.x, d0);
+            d1 = __builtin_fma(w_pp, (double)r_pp.y, d1);
+            d0 = __builtin_fma(w_mp, (double)r_mp.x, d0);
+            d1 = __builtin_fma(w_mp, (double)r_mp.y, d1);
+            d0 = __builtin_fma(w_pm, (double)r_pm.x, d0);
+            d1 = __builtin_fma(w_pm, (double)r_pm.y, d1);
+            d0 = __builtin_fma(w_mm, (double)r_mm.x, d0);
+            d1 = __builtin_fma(w_mm, (double)r_mm.y, d1);
+            if (lastx || lasty) {
+                // clamped corners: whole ranges of pixels deposit on the last column / row
+                const double *R0 = k.Rb + (int64_t)j * k.H, *R1 = k.Rb + ((int64_t)s + j) * k.H;
+                const double *C0 = k.Cb + (int64_t)j * k.W, *C1 = k.Cb + ((int64_t)s + j) * k.W;
+                if (lastx && !lasty && pyp >= 0) { d0 += R0[pyp]; d1 += R1[pyp]; }
+                if (lasty && !lastx && pxp >= 0) { d0 += C0[pxp]; d1 += C1[pxp]; }
+                if (lastx && lasty) { d0 += shK[0][j]; d1 += shK[1][j]; }
+                if (lasty && okxm) { d0 -= C0[pxm]; d1 -= C1[pxm]; }
+                if (lastx && okym) { d0 -= R0[pym]; d1 -= R1[pym]; }
             }
         }
-        // (x+, y-) corner, sign -
-        if (vym) {
-            if (!lastx) {
-                if (pxp >= 0) add(j, pxp, pym, -1.0);
-            } else {
-                d0 -= R0[pym];
-                d1 -= R1[pym];
-            }
-        }
-        // (x-, y-) corner
-        if (vxm && vym) add(j, pxm, pym, 1.0);
     }
-    k.Dr[(int64_t)yv * k.W + xv] = make_double2(d0, d1);
+    __builtin_nontemporal_store(d0, &k.Dr[(int64_t)yv * k.W + xv].x);
+    __builtin_nontemporal_store(d1, &k.Dr[(int64_t)yv * k.W + xv].y);
 }
 
-// (4) scalar gradients: per-block partials of sum g E, sum g (1 - Pbar), sum g Pbar over a
-// fixed pixel assignment, then one block adds them in a fixed order.
-__global__ void __launch_bounds__(kBlock) scalar_partial_kernel(BwdK k) {
-    const int s = k.p.n_scales;
-    const int64_t n = (int64_t)k.H * k.W, ps = n;
-    const float *E = k.R + (int64_t)(2 * s) * ps, *Pb = k.R + (int64_t)(2 * s + 1) * ps;
-    Sum3 acc{0.0, 0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        const int64_t y = i / k.W, x = i % k.W;
-        const double gx = (double)k.g[y * k.ld_g + x];
-        const double pb = (double)Pb[i];
-        acc.a = __builtin_fma(gx, (double)E[i], acc.a);
-        acc.b = __builtin_fma(gx, 1.0 - pb, acc.b);
-        acc.c = __builtin_fma(gx, pb, acc.c);
-    }
-    const Sum3 r = block_sum3(acc);
-    if (threadIdx.x == 0) {
-        k.part[3 * blockIdx.x] = r.a;
-        k.part[3 * blockIdx.x + 1] = r.b;
-        k.part[3 * blockIdx.x + 2] = r.c;
-    }
-}
-
+// (4) scalar gradients: one block adds the per-block partials of (1) in a fixed order.
 __global__ void __launch_bounds__(kBlock) scalar_finalize_kernel(const double *part, int nparts,
                                                                  double *out) {
     Sum3 acc{0.0, 0.0, 0.0};
@@ -332,11 +318,12 @@ BwdPlan make_bwd_plan(int H, int W, int n_scales, const int *ry, bool with_resid
     };
     const size_t hw = (size_t)H * W;
     b.resid = with_resid ? take((2 * (size_t)n_scales + 2) * hw * sizeof(float)) : 0;
+    b.Rp = take(2 * (size_t)n_scales * tiles_x * (size_t)H * sizeof(double));
     b.Rb = take(2 * (size_t)n_scales * H * sizeof(double));
     b.Cp = take(2 * (size_t)n_scales * b.nchunks * (size_t)W * sizeof(double));
     b.Cb = take(2 * (size_t)n_scales * W * sizeof(double));
     b.Dr = take(hw * sizeof(double2));
-    b.part = take((size_t)kScalarBlocks * 3 * sizeof(double));
+    b.part = take((size_t)tiles_x * b.nchunks * 3 * sizeof(double));
     b.scan_plan = make_scan_plan(H, W, kF64, 0, scan_tune_default(H, W));
     b.scan = take(b.scan_plan.total);
     b.total = off;
@@ -355,6 +342,7 @@ hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, voi
     k.g = a.g;
     k.ld_g = a.ld_g;
     k.R = a.resid;
+    k.Rp = reinterpret_cast<double *>(w + plan.Rp);
     k.Rb = reinterpret_cast<double *>(w + plan.Rb);
     k.Cp = reinterpret_cast<double *>(w + plan.Cp);
     k.Cb = reinterpret_cast<double *>(w + plan.Cb);
@@ -365,25 +353,20 @@ hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, voi
     k.teeth = plan.teeth;
     k.nchunks = plan.nchunks;
     const int S = a.p.n_scales;
-    hipLaunchKernelGGL(border_rows_kernel, dim3(a.H), dim3(kBlock), 0, s, k);
+    const unsigned nbs = (unsigned)(k.tiles_x * plan.nchunks);
+    hipLaunchKernelGGL(border_scalar_kernel, dim3(nbs), dim3(kBlock), 0, s, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned ncol = (unsigned)((a.W + kWave - 1) / kWave);
-    hipLaunchKernelGGL(border_cols_kernel, dim3(ncol * plan.nchunks), dim3(kBlock), 0, s, k);
+    const unsigned nred = (unsigned)(((int64_t)2 * S * (a.H + a.W) + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(border_reduce_kernel, dim3(nred), dim3(kBlock), 0, s, k);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const unsigned nred = (unsigned)(((int64_t)2 * S * a.W + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(border_cols_reduce_kernel, dim3(nred), dim3(kBlock), 0, s, k);
+    hipLaunchKernelGGL(scalar_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k.part, (int)nbs,
+                       a.grad_params);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(deposit_kernel, dim3((unsigned)plan.nblocks), dim3(kBlock), 0, s, k);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    e = launch_suffix_adjoint(k.Dr, a.W, a.v, a.ld_v, a.H, a.W, a.grad_v, a.ld_gv,
-                              plan.scan_plan, w + plan.scan, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(scalar_partial_kernel, dim3(kScalarBlocks), dim3(kBlock), 0, s, k);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(scalar_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k.part,
-                       kScalarBlocks, a.grad_params);
-    return hipGetLastError();
+    return launch_suffix_adjoint(k.Dr, a.W, a.v, a.ld_v, a.H, a.W, a.grad_v, a.ld_gv,
+                                 plan.scan_plan, w + plan.scan, s);
 }
 
 }  // namespace tmo

@@ -10,6 +10,26 @@ namespace tmo {
 
 constexpr int kWave = 64;
 
+// Global-address-space view of a pointer.  Pointers that a kernel reads from a descriptor in
+// memory (the batched launches) are generic to the compiler, which then emits flat loads
+// and stores with 64-bit lane addresses; through this view it emits global memory
+// instructions, including the scalar-base + 32-bit-offset form.
+// (The host compilation pass of a .hip file parses device code but has no such address
+// space; there the view is the plain pointer.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TM_GLOBAL __attribute__((address_space(1)))
+#else
+#define TM_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ const TM_GLOBAL T *gptr(const T *p) {
+    return (const TM_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ TM_GLOBAL T *gptr(T *p) {
+    return (TM_GLOBAL T *)p;
+}
+
 // ------------------------------------------------------------------ DPP moves (GFX9)
 // dpp_ctrl encodings: row_shr:n = 0x110 + n, wave_shr:1 = 0x138, row_bcast:15 = 0x142,
 // row_bcast:31 = 0x143.  Lanes whose source is outside the row/wave, or that row_mask /
@@ -168,6 +188,11 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1
 // Workgroups are dispatched to the 8 XCDs round-robin by block index.  Remap so that each
 // XCD receives one contiguous range of tiles, keeping neighbouring tiles (which share
 // table rows) in one XCD's L2.  The map is a bijection on [0, nblocks).
+// Index of the calling wave inside its block, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
     constexpr uint32_t kXcd = 8;
     uint32_t q = nblocks / kXcd, r = nblocks % kXcd;
@@ -185,8 +210,9 @@ __device__ __forceinline__ void comb_map(uint32_t b, int tiles_x, int p4, int te
     rg = (int)(r % (uint32_t)teeth) * p4 + (int)(r / (uint32_t)teeth);
 }
 
-// Batched launches walk one flattened list of work items spanning every image; the image
-// of item g is the last i with prefix[i] <= g (prefix has count+1 entries, prefix[0] = 0).
+// Batched launches walk one flattened list of work items spanning a range of images; the
+// image of item g is the last i with prefix[i] <= g (prefix has count+1 entries and
+// prefix[0] <= g).
 __device__ __forceinline__ int find_image(const int64_t *prefix, int count, int64_t g) {
     int lo = 0, hi = count - 1;
     while (lo < hi) {

@@ -34,6 +34,8 @@ StatsK make_statsk(const float *rgb, int64_t ch_stride, int64_t ld_rgb, const fl
 // block per image (device arrays ks[count], part_prefix[count+1]).
 hipError_t launch_stats_batch(const StatsK *ks, const int64_t *part_prefix, int count,
                               unsigned grid, hipStream_t s);
+// Resident blocks per CU of the batched statistics kernel (at least 1).
+int stats_batch_occupancy();
 
 hipError_t launch_luminance(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int H, int W,
                             float *lum, int64_t ld_lum, hipStream_t s);
@@ -116,6 +118,9 @@ struct BatchScan {
     unsigned grid_tiles, grid_items;
 };
 hipError_t launch_tables_batch(const BatchScan &b, hipStream_t s);
+// Resident blocks per CU of the batched scan kernels of this precision and tiling (the
+// smallest over the three phases, at least 1).
+int scan_batch_occupancy(int prec, int vec, int chunk);
 // Items of stage 2 of one image (thread-level): nq*H + nq*W + nq*tiles_y.
 int64_t scan_stage2_items(const ScanK &k, bool sat);
 
@@ -158,7 +163,11 @@ int64_t query_blocks(const FwdK &k);
 // Fused query of a batch: one persistent launch (grid a multiple of 8) over every image's
 // tiles (device arrays ks[count], tile_prefix[count+1]).
 hipError_t launch_forward_batch(const FwdK *ks, const int64_t *tile_prefix, int count, int prec,
-                                unsigned grid, hipStream_t s);
+                                bool h32, unsigned grid, hipStream_t s);
+// Resident blocks per CU of the batched query kernel (at least 1).
+int forward_batch_occupancy(int prec, bool h32);
+// Every histogram byte offset of the query of k fits in 32 bits.
+bool hist_offsets_fit_32(const FwdK &k);
 FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int64_t ld_sat,
                 const float *offsets, const uint32_t *hist, int64_t ld_hist,
                 int64_t plane_stride, const float *edges, const QueryParams &p, float *out,
@@ -191,7 +200,7 @@ struct BwdResidArgs {
 struct BwdPlan {
     int64_t nblocks;
     int p4, teeth, nchunks;
-    size_t resid, Rb, Cp, Cb, Dr, part, scan, total;
+    size_t resid, Rp, Rb, Cp, Cb, Dr, part, scan, total;
     ScanPlan scan_plan;
 };
 // with_resid: also reserve the residual planes (the table-based backward rebuilds them).

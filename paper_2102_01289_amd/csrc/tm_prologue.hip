@@ -128,11 +128,12 @@ __global__ void __launch_bounds__(kBlock) lum_stats_kernel(StatsK k) {
     stats_part<FROM_RGB, STATS>(k, blockIdx.x, gridDim.x);
 }
 
-// Batched prologue: item g is part (g - prefix[i]) of image i.
+// Batched prologue over images [0, count) of ks: item g in [prefix[0], prefix[count]) is part
+// (g - prefix[i]) of image i.
 __global__ void __launch_bounds__(kBlock) lum_stats_batch(const StatsK *ks, const int64_t *prefix,
                                                           int count) {
     const int64_t total = prefix[count];
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    for (int64_t g = prefix[0] + blockIdx.x; g < total; g += gridDim.x) {
         const int i = find_image(prefix, count, g);
         stats_part<true, true>(ks[i], (int)(g - prefix[i]), ks[i].nparts);
         __syncthreads();
@@ -330,6 +331,12 @@ hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, con
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k);
     return hipGetLastError();
+}
+
+int stats_batch_occupancy() {
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lum_stats_batch, kBlock, 0) ==
+                   hipSuccess && n > 0 ? n : 1;
 }
 
 hipError_t launch_stats_batch(const StatsK *ks, const int64_t *part_prefix, int count,

@@ -21,25 +21,35 @@ constexpr int kRows = kQueryRows;   // a block covers 64 columns x 4 rows
 constexpr int kMaxS = 8;            // TM_MAX_SCALES
 
 
+// Table entry types per integral-image precision.
+template <int P> struct SatEntry { using T = float2; };     // {I1, I2}
+template <> struct SatEntry<kC32x2> { using T = float4; };  // {I1.hi, I1.lo, I2.hi, I2.lo}
+template <> struct SatEntry<kF64> { using T = double2; };
+
+// Load at a wave-uniform row base plus a per-lane unsigned 32-bit byte offset, the form
+// the global_load "saddr + voffset" addressing takes directly (no 64-bit lane arithmetic).
+template <typename T>
+__device__ __forceinline__ T load_at(const char *row, uint32_t off) {
+    return *reinterpret_cast<const TM_GLOBAL T *>(gptr(row) + off);
+}
+
 // Window mean m and variance var (Eq. 10 read as the population variance, not yet clamped)
 // from the four corner entries of the interleaved integral image and the reciprocal of the
 // window area.  The corner sums cancel heavily (large quadrant sums, small window sums), so
 // for the compensated and FP64 tables they are combined in FP64.
 template <int P>
-__device__ __forceinline__ void window_moments(const FwdK &k, int64_t oA, int64_t oB,
-                                               int64_t oC, int64_t oD, double inv_n, float mu1,
-                                               float mu2, double &m, double &var) {
+__device__ __forceinline__ void window_moments(const typename SatEntry<P>::T &A,
+                                               const typename SatEntry<P>::T &B,
+                                               const typename SatEntry<P>::T &C,
+                                               const typename SatEntry<P>::T &D, double inv_n,
+                                               float mu1, float mu2, double &m, double &var) {
     if constexpr (P == kF32) {
-        const float2 *t = static_cast<const float2 *>(k.sat);
-        const float2 A = t[oA], B = t[oB], C = t[oC], D = t[oD];
         const float inv = (float)inv_n;
         const float mf = ((A.x + C.x) - (B.x + D.x)) * inv;
         const float vf = __builtin_fmaf((A.y + C.y) - (B.y + D.y), inv, -(mf * mf));
         m = (double)mf;
         var = (double)vf;
     } else if constexpr (P == kC32x2) {
-        const float4 *t = static_cast<const float4 *>(k.sat);
-        const float4 A = t[oA], B = t[oB], C = t[oC], D = t[oD];
         // leading parts exactly in FP64; trailing parts (2^-24 smaller) summed in FP32
         const double h1 = ((double)A.x + (double)C.x) - ((double)B.x + (double)D.x);
         const double h2 = ((double)A.z + (double)C.z) - ((double)B.z + (double)D.z);
@@ -49,8 +59,6 @@ __device__ __forceinline__ void window_moments(const FwdK &k, int64_t oA, int64_
         const double e2 = __builtin_fma(h2 + (double)l2, inv_n, (double)mu2);
         var = __builtin_fma(-m, m, e2);
     } else {
-        const double2 *t = static_cast<const double2 *>(k.sat);
-        const double2 A = t[oA], B = t[oB], C = t[oC], D = t[oD];
         m = ((A.x + C.x) - (B.x + D.x)) * inv_n;
         var = __builtin_fma(-m, m, ((A.y + C.y) - (B.y + D.y)) * inv_n);
     }
@@ -66,24 +74,32 @@ __device__ __forceinline__ double recip_area(int N) {
 }
 
 // One 64 x 4 tile of one image.  sh_edges is the block's copy of the image's bin edges.
+// A wave covers 64 columns of one row, so every row index and row address is wave-uniform
+// (scalar registers) and the lanes only add their column offsets.  H32: every histogram
+// byte offset fits in 32 bits, so a lane's plane is folded into its 32-bit column offset.
 // RESID: also write the per-pixel residual planes the backward needs (their derivation is
-// in the backward's header): R1_j = -2 c_j m_j / N_j and R2_j = c_j / N_j with
-// c_j = (L_j - L)/D eps/(var_j + eps)^2 (zero where var_j was clamped or D = 0),
-// E = sum_j (L_j - L)/D (-var_j/(var_j + eps)^2) and Pbar = sum_j W_j P_j / D.
-template <int P, bool RESID>
+// in the backward's header): the pair {R1_j, R2_j} = {-2 c_j m_j / N_j, c_j / N_j} with
+// c_j = (L_j - L)/D eps/(var_j + eps)^2 (zero where var_j was clamped or D = 0), one
+// interleaved pair plane per field, then E = sum_j (L_j - L)/D (-var_j/(var_j + eps)^2) and
+// Pbar = sum_j W_j P_j / D.
+// Outputs and residual planes are written with streaming (non-temporal) stores so that
+// they do not evict table lines the neighbouring tiles still read.
+template <int P, bool RESID, bool H32>
 __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float *sh_edges) {
+    using ST = typename SatEntry<P>::T;
+    constexpr uint32_t ES = sizeof(ST);
     const int ne = k.p.n_bins - 1;
     __syncthreads();   // the previous tile of this block may still read sh_edges
-    for (int i = threadIdx.x; i < ne; i += kBlock) sh_edges[i] = k.edges[i];
+    for (int i = threadIdx.x; i < ne; i += kBlock) sh_edges[i] = gptr(k.edges)[i];
     __syncthreads();
 
     int tx, rg;
     comb_map(tile, k.tiles_x, k.p4, k.teeth, tx, rg);
     const int x = tx * kWave + lane_id();
-    const int y = rg * kRows + (int)(threadIdx.x / kWave);
-    if (x >= k.W || y >= k.H) return;
+    const int y = rg * kRows + wave_id();
+    if (y >= k.H || x >= k.W) return;
 
-    const float v = k.v[(int64_t)y * k.ld_v + x];
+    const float v = gptr(k.v)[(int64_t)y * k.ld_v + x];
     // bin b = #{edges <= v} (edges ascending)
     int lo = 0, hi = ne;
     while (lo < hi) {
@@ -91,12 +107,18 @@ __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float
         if (sh_edges[mid] <= v) lo = mid + 1; else hi = mid;
     }
     const int b = lo;
-    const uint32_t *plane = b > 0 ? k.hist + (int64_t)(b - 1) * k.plane_stride : nullptr;
+    // histogram addressing: the plane G_b of this pixel, entry (-1, -1) at byte 0 of a row
+    // base, lanes add their plane (H32) and column offsets
+    const int64_t hplane = (int64_t)(b > 0 ? b - 1 : 0) * k.plane_stride;
+    const uint32_t hplane_b = H32 ? (uint32_t)(hplane * 4) : 0u;
+    const uint32_t *hlane = H32 ? nullptr : k.hist + hplane;
+    const char *sat0 = static_cast<const char *>(k.sat) - (k.ld_sat + 1) * (int64_t)ES;
+    const char *hist0 = reinterpret_cast<const char *>(k.hist - (k.ld_hist + 1));
 
     const int s = k.p.n_scales;
     const float ldr = k.p.ld_max - k.p.ld_min;
-    const float mu1 = P == kC32x2 ? k.offsets[0] : 0.f;
-    const float mu2 = P == kC32x2 ? k.offsets[1] : 0.f;
+    const float mu1 = P == kC32x2 ? gptr(k.offsets)[0] : 0.f;
+    const float mu2 = P == kC32x2 ? gptr(k.offsets)[1] : 0.f;
     float num = 0.f, den = 0.f, lsum = 0.f, pn = 0.f, psum = 0.f;
     float vj[kMaxS], mj[kMaxS], lj[kMaxS], nj[kMaxS];
     bool clj[kMaxS];
@@ -105,21 +127,33 @@ __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float
         if (j < s) {
             const int rx = k.p.rx[j], ry = k.p.ry[j];
             const int xm = max(x - rx - 1, -1), xp = min(x + rx, k.W - 1);
-            const int ym = max(y - ry - 1, -1), yp = min(y + ry, k.H - 1);
+            const int ym = max(y - ry - 1, -1), yp = min(y + ry, k.H - 1);   // uniform
             const int N = (xp - xm) * (yp - ym);
             const double inv_n = recip_area(N);
+            const char *sm = sat0 + (int64_t)(ym + 1) * k.ld_sat * ES;
+            const char *sp = sat0 + (int64_t)(yp + 1) * k.ld_sat * ES;
+            const uint32_t oxm = (uint32_t)(xm + 1) * ES, oxp = (uint32_t)(xp + 1) * ES;
             double m, vr;
-            window_moments<P>(k, (int64_t)ym * k.ld_sat + xm, (int64_t)ym * k.ld_sat + xp,
-                              (int64_t)yp * k.ld_sat + xp, (int64_t)yp * k.ld_sat + xm, inv_n,
-                              mu1, mu2, m, vr);
+            window_moments<P>(load_at<ST>(sm, oxm), load_at<ST>(sm, oxp), load_at<ST>(sp, oxp),
+                              load_at<ST>(sp, oxm), inv_n, mu1, mu2, m, vr);
             // a one-pixel window has zero variance by definition (its rounding noise would
             // otherwise reach the gradient through the clamp)
             const bool clamped = !(vr > 0.0) || N == 1;
             const float var = clamped ? 0.f : (float)vr;
             uint32_t c = 0u;
-            if (plane) {
-                c = plane[(int64_t)yp * k.ld_hist + xp] + plane[(int64_t)ym * k.ld_hist + xm] -
-                    plane[(int64_t)ym * k.ld_hist + xp] - plane[(int64_t)yp * k.ld_hist + xm];
+            if (b > 0) {
+                if constexpr (H32) {
+                    const char *hm = hist0 + (int64_t)(ym + 1) * k.ld_hist * 4;
+                    const char *hp = hist0 + (int64_t)(yp + 1) * k.ld_hist * 4;
+                    const uint32_t hxm = hplane_b + (uint32_t)(xm + 1) * 4u;
+                    const uint32_t hxp = hplane_b + (uint32_t)(xp + 1) * 4u;
+                    c = load_at<uint32_t>(hp, hxp) + load_at<uint32_t>(hm, hxm) -
+                        load_at<uint32_t>(hm, hxp) - load_at<uint32_t>(hp, hxm);
+                } else {
+                    const TM_GLOBAL uint32_t *pm = gptr(hlane) + (int64_t)ym * k.ld_hist;
+                    const TM_GLOBAL uint32_t *pp = gptr(hlane) + (int64_t)yp * k.ld_hist;
+                    c = pp[xp] + pm[xm] - pm[xp] - pp[xm];
+                }
             }
             const float Pj = (float)c * (float)inv_n;
             const float Lj = __builtin_fmaf(ldr, Pj, k.p.ld_min);
@@ -139,10 +173,10 @@ __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float
         }
     }
     const float L = den > 0.f ? num / den : lsum / (float)s;
-    const int64_t pix = (int64_t)y * k.ld_out + x;
-    if (k.out) k.out[pix] = L;
+    if (k.out) __builtin_nontemporal_store(L, gptr(k.out) + (int64_t)y * k.ld_out + x);
     if (RESID) {
-        const int64_t o = (int64_t)y * k.W + x, ps = k.rstride;
+        TM_GLOBAL float *ro = gptr(k.resid) + (int64_t)y * k.W + x;
+        const int64_t ps = k.rstride;
         const float inv_d = den > 0.f ? 1.0f / den : 0.f;
         float E = 0.f;
 #pragma unroll
@@ -154,34 +188,40 @@ __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float
                 E = __builtin_fmaf(d, -vj[j] * r2, E);
                 const float c = clj[j] ? 0.f : d * k.p.eps * r2;
                 const float cn = c * nj[j];
-                k.resid[(int64_t)j * ps + o] = -2.0f * cn * mj[j];
-                k.resid[(int64_t)(s + j) * ps + o] = cn;
+                TM_GLOBAL float *pr = gptr(k.resid) + 2 * ((int64_t)j * ps + (int64_t)y * k.W + x);
+                __builtin_nontemporal_store(-2.0f * cn * mj[j], pr);
+                __builtin_nontemporal_store(cn, pr + 1);
             }
         }
-        k.resid[(int64_t)(2 * s) * ps + o] = E;
-        k.resid[(int64_t)(2 * s + 1) * ps + o] = den > 0.f ? pn / den : psum / (float)s;
+        __builtin_nontemporal_store(E, ro + (int64_t)(2 * s) * ps);
+        __builtin_nontemporal_store(den > 0.f ? pn / den : psum / (float)s,
+                                    ro + (int64_t)(2 * s + 1) * ps);
     }
 }
 
-template <int P, bool RESID>
+template <int P, bool RESID, bool H32>
 __global__ void __launch_bounds__(kBlock) forward_kernel(FwdK k) {
     __shared__ float sh_edges[256];
-    forward_tile<P, RESID>(k, xcd_tile(blockIdx.x, gridDim.x), sh_edges);
+    forward_tile<P, RESID, H32>(k, xcd_tile(blockIdx.x, gridDim.x), sh_edges);
 }
 
-// Batched query: a persistent grid whose blocks on XCD x (block % 8) walk the x-th eighth of
-// the flattened tile list, so each XCD's L2 sees one contiguous run of tiles.
-template <int P>
-__global__ void __launch_bounds__(kBlock) forward_batch(const FwdK *ks, const int64_t *prefix,
+// Batched query: a persistent grid that walks the images in order.  Each image's tile list
+// (in comb order) is cut into eight contiguous parts, part x for the blocks on XCD x (block %
+// 8), so all XCDs work on the same image at once -- its tables stay in the shared memory-side
+// cache -- and each XCD's L2 sees one contiguous run of that image's tiles, as in the
+// single-image launch.  No block waits for another: a block that finishes its share of an
+// image moves on to the next.
+template <int P, bool H32>
+__global__ void __launch_bounds__(kBlock) forward_batch(const FwdK *__restrict__ ks,
+                                                       const int64_t *__restrict__ prefix,
                                                        int count) {
     __shared__ float sh_edges[256];
-    const int64_t total = prefix[count];
-    const int64_t per = (total + 7) / 8;
-    const int64_t xcd = blockIdx.x % 8, nb = gridDim.x / 8;
-    const int64_t end = min(total, (xcd + 1) * per);
-    for (int64_t g = xcd * per + blockIdx.x / 8; g < end; g += nb) {
-        const int i = find_image(prefix, count, g);
-        forward_tile<P, false>(ks[i], (uint32_t)(g - prefix[i]), sh_edges);
+    const int64_t xcd = blockIdx.x % 8, nb = gridDim.x / 8, lb = blockIdx.x / 8;
+    for (int i = 0; i < count; ++i) {
+        const int64_t T = prefix[i + 1] - prefix[i];
+        const int64_t a = T * xcd / 8, b = T * (xcd + 1) / 8;
+        for (int64_t t = a + lb; t < b; t += nb)
+            forward_tile<P, false, H32>(ks[i], (uint32_t)t, sh_edges);
     }
 }
 
@@ -189,20 +229,42 @@ __global__ void __launch_bounds__(kBlock) forward_batch(const FwdK *ks, const in
 
 int64_t query_blocks(const FwdK &k) { return (int64_t)k.tiles_x * k.p4 * k.teeth; }
 
-hipError_t launch_forward_batch(const FwdK *ks, const int64_t *tile_prefix, int count, int prec,
-                                unsigned grid, hipStream_t s) {
+template <bool H32>
+hipError_t launch_fwd_batch(const FwdK *ks, const int64_t *tile_prefix, int count, int prec,
+                            unsigned grid, hipStream_t s) {
     switch (prec) {
         case kF32:
-            hipLaunchKernelGGL(forward_batch<kF32>, dim3(grid), dim3(kBlock), 0, s, ks, tile_prefix, count);
+            hipLaunchKernelGGL((forward_batch<kF32, H32>), dim3(grid), dim3(kBlock), 0, s, ks, tile_prefix, count);
             break;
         case kC32x2:
-            hipLaunchKernelGGL(forward_batch<kC32x2>, dim3(grid), dim3(kBlock), 0, s, ks, tile_prefix, count);
+            hipLaunchKernelGGL((forward_batch<kC32x2, H32>), dim3(grid), dim3(kBlock), 0, s, ks, tile_prefix, count);
             break;
         default:
-            hipLaunchKernelGGL(forward_batch<kF64>, dim3(grid), dim3(kBlock), 0, s, ks, tile_prefix, count);
+            hipLaunchKernelGGL((forward_batch<kF64, H32>), dim3(grid), dim3(kBlock), 0, s, ks, tile_prefix, count);
             break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_forward_batch(const FwdK *ks, const int64_t *tile_prefix, int count, int prec,
+                                bool h32, unsigned grid, hipStream_t s) {
+    return h32 ? launch_fwd_batch<true>(ks, tile_prefix, count, prec, grid, s)
+               : launch_fwd_batch<false>(ks, tile_prefix, count, prec, grid, s);
+}
+
+int forward_batch_occupancy(int prec, bool h32) {
+    int n = 0;
+    hipError_t e;
+    if (prec == kF32)
+        e = h32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, forward_batch<kF32, true>, kBlock, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, forward_batch<kF32, false>, kBlock, 0);
+    else if (prec == kC32x2)
+        e = h32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, forward_batch<kC32x2, true>, kBlock, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, forward_batch<kC32x2, false>, kBlock, 0);
+    else
+        e = h32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, forward_batch<kF64, true>, kBlock, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, forward_batch<kF64, false>, kBlock, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
 }
 
 void comb_params(int H, int rows, const int *ry, int n_scales, int *p4, int *teeth) {
@@ -245,21 +307,28 @@ FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int6
     return k;
 }
 
-template <bool RESID>
+template <bool RESID, bool H32>
 hipError_t launch_fwd(const FwdK &k, int prec, hipStream_t s) {
     const unsigned tiles = (unsigned)query_blocks(k);
     switch (prec) {
         case kF32:
-            hipLaunchKernelGGL((forward_kernel<kF32, RESID>), dim3(tiles), dim3(kBlock), 0, s, k);
+            hipLaunchKernelGGL((forward_kernel<kF32, RESID, H32>), dim3(tiles), dim3(kBlock), 0, s, k);
             break;
         case kC32x2:
-            hipLaunchKernelGGL((forward_kernel<kC32x2, RESID>), dim3(tiles), dim3(kBlock), 0, s, k);
+            hipLaunchKernelGGL((forward_kernel<kC32x2, RESID, H32>), dim3(tiles), dim3(kBlock), 0, s, k);
             break;
         default:
-            hipLaunchKernelGGL((forward_kernel<kF64, RESID>), dim3(tiles), dim3(kBlock), 0, s, k);
+            hipLaunchKernelGGL((forward_kernel<kF64, RESID, H32>), dim3(tiles), dim3(kBlock), 0, s, k);
             break;
     }
     return hipGetLastError();
+}
+
+// Largest histogram byte offset a lane forms relative to entry (-1, -1) of plane 0.
+bool hist_offsets_fit_32(const FwdK &k) {
+    if (!k.hist || k.p.n_bins < 2) return true;
+    const int64_t last = (int64_t)(k.p.n_bins - 2) * k.plane_stride + (int64_t)k.W + 1;
+    return last * 4 < ((int64_t)1 << 32);
 }
 
 hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void *sat,
@@ -271,7 +340,9 @@ hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void
                        p, out, ld_out);
     k.resid = resid;
     k.rstride = (int64_t)H * W;
-    return resid ? launch_fwd<true>(k, prec, s) : launch_fwd<false>(k, prec, s);
+    if (hist_offsets_fit_32(k))
+        return resid ? launch_fwd<true, true>(k, prec, s) : launch_fwd<false, true>(k, prec, s);
+    return resid ? launch_fwd<true, false>(k, prec, s) : launch_fwd<false, false>(k, prec, s);
 }
 
 }  // namespace tmo

@@ -53,11 +53,11 @@ struct Entry<kF64> {
 // Load the lane's VEC consecutive pixels of row y (zeros outside the image).
 template <int VEC>
 __device__ __forceinline__ void load_row(const ScanK &k, int y, int xl, float (&v)[VEC]) {
-    const float *row = k.v + (int64_t)y * k.ld_v;
+    const TM_GLOBAL float *row = gptr(k.v) + (int64_t)y * k.ld_v;
     if (k.vec_load && (VEC % 4 == 0) && xl + VEC <= k.W) {
 #pragma unroll
         for (int i = 0; i < VEC; i += 4) {
-            float4 t = *reinterpret_cast<const float4 *>(row + xl + i);
+            float4 t = *reinterpret_cast<const TM_GLOBAL float4 *>(row + xl + i);
             v[i] = t.x; v[i + 1] = t.y; v[i + 2] = t.z; v[i + 3] = t.w;
         }
     } else {
@@ -95,28 +95,73 @@ __device__ __forceinline__ uint32_t ind(float v, float lo, float hi, bool in) {
     return (in && v >= lo && v < hi) ? 1u : 0u;
 }
 
+// One row of scan input: the luminance in table mode; in adjoint mode the deposit pair of
+// the row and the luminance at the mirrored output pixels.  Tiles load row r+1 before they
+// process row r, so the loads of the next row are in flight during the row's wave scans and
+// stores.
+template <int VEC, bool ADJ>
+struct RowIn {
+    float v[VEC];
+    double2 d[ADJ ? VEC : 1];
+};
+
+template <int VEC, bool ADJ, bool OUT_V = ADJ>
+__device__ __forceinline__ void load_in(const ScanK &k, int y, int xl, RowIn<VEC, ADJ> &r) {
+    if constexpr (ADJ) {
+        const TM_GLOBAL double2 *row = gptr(k.dsrc) + (int64_t)y * k.ld_d;
+        const TM_GLOBAL float *vr = gptr(k.v) + (int64_t)(k.H - 1 - y) * k.ld_v;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const bool in = xl + i < k.W;
+            r.d[i] = in ? make_double2(row[xl + i].x, row[xl + i].y) : make_double2(0.0, 0.0);
+            if (OUT_V) r.v[i] = in ? vr[k.W - 1 - (xl + i)] : 0.f;
+        }
+    } else {
+        load_row<VEC>(k, y, xl, r.v);
+    }
+}
+
 // Per-pixel terms of the two scanned quantities: (v - mu1, v^2 - mu2) of the luminance in
 // table mode; the two FP64 deposit planes in adjoint mode.  Zero outside the image.
 template <int P, int VEC, bool ADJ>
-__device__ __forceinline__ void sat_terms(const ScanK &k, int y, int xl, const float (&v)[VEC],
+__device__ __forceinline__ void sat_terms(const ScanK &k, int xl, const RowIn<VEC, ADJ> &in,
                                           float mu1, float mu2, typename Acc<P>::T (&q1)[VEC],
                                           typename Acc<P>::T (&q2)[VEC]) {
     using A = Acc<P>;
     if constexpr (ADJ) {
-        const double2 *row = k.dsrc + (int64_t)y * k.ld_d;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
-            const double2 d = (xl + i < k.W) ? row[xl + i] : make_double2(0.0, 0.0);
-            q1[i] = d.x;
-            q2[i] = d.y;
+            q1[i] = in.d[i].x;
+            q2[i] = in.d[i].y;
         }
     } else {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
-            const bool in = xl + i < k.W;
-            q1[i] = in ? A::of_v(v[i], mu1) : A::zero();
-            q2[i] = in ? A::of_v2(v[i], mu2) : A::zero();
+            const bool ok = xl + i < k.W;
+            q1[i] = ok ? A::of_v(in.v[i], mu1) : A::zero();
+            q2[i] = ok ? A::of_v2(in.v[i], mu2) : A::zero();
         }
+    }
+}
+
+// Store a lane's VEC consecutive counts of one row: 16-byte stores inside the image (the
+// row pitch is a multiple of 64 entries and xl a multiple of VEC, so they are aligned),
+// element stores on the ragged last tile.
+template <int VEC>
+__device__ __forceinline__ void store_counts(TM_GLOBAL uint32_t *out, int xl, int W, bool full,
+                                             const uint32_t (&c)[VEC]) {
+    if (full && VEC % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < VEC; i += 4)
+            *reinterpret_cast<TM_GLOBAL uint4 *>(out + xl + i) =
+                make_uint4(c[i], c[i + 1], c[i + 2], c[i + 3]);
+    } else if (full) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) out[xl + i] = c[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i)
+            if (xl + i < W) out[xl + i] = c[i];
     }
 }
 
@@ -153,14 +198,17 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
             for (int i = 0; i < VEC; ++i) cc[c][i] = 0u;
         }
 
+        RowIn<VEC, ADJ> nxt;
+        if (rows > 0) load_in<VEC, ADJ, false>(k, y0, xl, nxt);
         for (int r = 0; r < rows; ++r) {
             const int y = y0 + r;
-            float v[VEC];
-            if (!ADJ) load_row<VEC>(k, y, xl, v);
+            const RowIn<VEC, ADJ> cur = nxt;
+            if (r + 1 < rows) load_in<VEC, ADJ, false>(k, y + 1, xl, nxt);
+            const float(&v)[VEC] = cur.v;
             if (do_sat) {
                 T s1 = A::zero(), s2 = A::zero();
                 T q1[VEC], q2[VEC];
-                sat_terms<P, VEC, ADJ>(k, y, xl, v, mu1, mu2, q1, q2);
+                sat_terms<P, VEC, ADJ>(k, xl, cur, mu1, mu2, q1, q2);
 #pragma unroll
                 for (int i = 0; i < VEC; ++i) {
                     c1[i] = A::add(c1[i], q1[i]);
@@ -173,7 +221,7 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
                 t1 = A::add(t1, s1);
                 t2 = A::add(t2, s2);
                 if (lane == 0) {
-                    T *rs = reinterpret_cast<T *>(k.rs_sat);
+                    TM_GLOBAL T *rs = reinterpret_cast<TM_GLOBAL T *>(gptr(k.rs_sat));
                     rs[(int64_t)y * k.tiles_x + tx] = s1;
                     rs[((int64_t)k.H + y) * k.tiles_x + tx] = s2;
                 }
@@ -199,9 +247,9 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
                     tc[c] += a;
                     if (c + 1 < CHUNK) tc[c + 1] += b;
                     if (lane == 0) {
-                        if (c < pe.np) k.rs_h[((int64_t)(p0 + c) * k.H + y) * k.tiles_x + tx] = a;
+                        if (c < pe.np) gptr(k.rs_h)[((int64_t)(p0 + c) * k.H + y) * k.tiles_x + tx] = a;
                         if (c + 1 < pe.np)
-                            k.rs_h[((int64_t)(p0 + c + 1) * k.H + y) * k.tiles_x + tx] = b;
+                            gptr(k.rs_h)[((int64_t)(p0 + c + 1) * k.H + y) * k.tiles_x + tx] = b;
                     }
                 }
             }
@@ -346,6 +394,7 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
     const int xl = x0 + lane * VEC;
     const int nchunks = HIST ? (k.n_planes + CHUNK - 1) / CHUNK : 0;
     const bool last_tx = tx == k.tiles_x - 1;
+    const bool full = x0 + TW <= k.W;   // tile-uniform: every lane's columns are in the image
 
     for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
         const bool do_sat = SAT && ch == 0;
@@ -375,16 +424,20 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
             }
         }
 
+        RowIn<VEC, ADJ> nxt;
+        if (rows > 0) load_in<VEC, ADJ>(k, y0, xl, nxt);
+#pragma unroll 2
         for (int r = 0; r < rows; ++r) {
             const int y = y0 + r;
-            float v[VEC];
-            if (!ADJ) load_row<VEC>(k, y, xl, v);
+            const RowIn<VEC, ADJ> cur = nxt;
+            if (r + 1 < rows) load_in<VEC, ADJ>(k, y + 1, xl, nxt);
+            const float(&v)[VEC] = cur.v;
             if (do_sat) {
-                const T *xc = reinterpret_cast<const T *>(k.xc_sat);
+                const TM_GLOBAL T *xc = reinterpret_cast<const TM_GLOBAL T *>(gptr(k.xc_sat));
                 const T xc1 = xc[(int64_t)y * k.tiles_x + tx];
                 const T xc2 = xc[((int64_t)k.H + y) * k.tiles_x + tx];
                 T p1[VEC], p2[VEC];
-                sat_terms<P, VEC, ADJ>(k, y, xl, v, mu1, mu2, p1, p2);
+                sat_terms<P, VEC, ADJ>(k, xl, cur, mu1, mu2, p1, p2);
 #pragma unroll
                 for (int i = 1; i < VEC; ++i) {
                     p1[i] = A::add(p1[i - 1], p1[i]);
@@ -400,18 +453,22 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
                 if constexpr (ADJ) {
                     // virtual (x', y) is pixel (W-1-x', H-1-y): dv = s1 + 2 v s2
                     const int yo = k.H - 1 - y;
-                    const float *vr = k.v + (int64_t)yo * k.ld_v;
-                    float *gr = k.gv + (int64_t)yo * k.ld_gv;
+                    TM_GLOBAL float *gr = gptr(k.gv) + (int64_t)yo * k.ld_gv;
 #pragma unroll
                     for (int i = 0; i < VEC; ++i) {
                         const int xo = k.W - 1 - (xl + i);
-                        if (xo >= 0) gr[xo] = (float)(c1[i] + 2.0 * (double)vr[xo] * c2[i]);
+                        if (xo >= 0) gr[xo] = (float)(c1[i] + 2.0 * (double)cur.v[i] * c2[i]);
                     }
                 } else {
-                    ET *out = reinterpret_cast<ET *>(k.sat) + (int64_t)y * k.ld_sat;
+                    TM_GLOBAL ET *out = reinterpret_cast<TM_GLOBAL ET *>(gptr(k.sat)) + (int64_t)y * k.ld_sat;
+                    if (full) {
 #pragma unroll
-                    for (int i = 0; i < VEC; ++i)
-                        if (xl + i < k.W) out[xl + i] = E::make(c1[i], c2[i]);
+                        for (int i = 0; i < VEC; ++i) out[xl + i] = E::make(c1[i], c2[i]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i)
+                            if (xl + i < k.W) out[xl + i] = E::make(c1[i], c2[i]);
+                    }
                 }
             }
             if (do_h) {
@@ -433,25 +490,21 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
                     {
                         const int64_t q = p0 + c;
                         if (c < pe.np) {
-                            const uint32_t xc = k.xc_h[(q * k.H + y) * k.tiles_x + tx];
-                            uint32_t *out = k.hist + q * k.plane_stride + (int64_t)y * k.ld_hist;
+                            const uint32_t xc = gptr(k.xc_h)[(q * k.H + y) * k.tiles_x + tx];
+                            TM_GLOBAL uint32_t *out = gptr(k.hist) + q * k.plane_stride + (int64_t)y * k.ld_hist;
 #pragma unroll
-                            for (int i = 0; i < VEC; ++i) {
-                                cc[c][i] += xc + exa + pa[i];
-                                if (xl + i < k.W) out[xl + i] = cc[c][i];
-                            }
+                            for (int i = 0; i < VEC; ++i) cc[c][i] += xc + exa + pa[i];
+                            store_counts<VEC>(out, xl, k.W, full, cc[c]);
                         }
                     }
                     if (c + 1 < CHUNK) {
                         const int64_t q = p0 + c + 1;
                         if (c + 1 < pe.np) {
-                            const uint32_t xc = k.xc_h[(q * k.H + y) * k.tiles_x + tx];
-                            uint32_t *out = k.hist + q * k.plane_stride + (int64_t)y * k.ld_hist;
+                            const uint32_t xc = gptr(k.xc_h)[(q * k.H + y) * k.tiles_x + tx];
+                            TM_GLOBAL uint32_t *out = gptr(k.hist) + q * k.plane_stride + (int64_t)y * k.ld_hist;
 #pragma unroll
-                            for (int i = 0; i < VEC; ++i) {
-                                cc[c + 1][i] += xc + exb + pb[i];
-                                if (xl + i < k.W) out[xl + i] = cc[c + 1][i];
-                            }
+                            for (int i = 0; i < VEC; ++i) cc[c + 1][i] += xc + exb + pb[i];
+                            store_counts<VEC>(out, xl, k.W, full, cc[c + 1]);
                         }
                     }
                 }
@@ -493,7 +546,7 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
 // ---------------------------------------------------------------- single-image kernels
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
 __global__ void __launch_bounds__(kBlock) scan_stage1(ScanK k) {
-    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int tile = blockIdx.x * kWavesPerBlock + wave_id();
     if (tile < k.tiles_x * k.tiles_y) stage1_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, tile);
 }
 
@@ -505,18 +558,20 @@ __global__ void __launch_bounds__(kBlock) scan_stage2(ScanK k, int64_t items) {
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
 __global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
-    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int tile = blockIdx.x * kWavesPerBlock + wave_id();
     if (tile < k.tiles_x * k.tiles_y) stage3_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, tile);
 }
 
 // ---------------------------------------------------------------- batched kernels
-// A persistent grid walks one flattened list of work items spanning every image.
+// A persistent grid walks one flattened list of work items spanning images [0, count) of ks;
+// prefix points at the first image's entry of the batch-wide prefix sums, so the walk covers
+// [prefix[0], prefix[count]).
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool THIRD>
 __global__ void __launch_bounds__(kBlock) scan_tiles_batch(const ScanK *ks, const int64_t *prefix,
                                                            int count) {
     const int64_t total = prefix[count];
     const int64_t step = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t g = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; g < total;
+    for (int64_t g = prefix[0] + (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); g < total;
          g += step) {
         const int i = __builtin_amdgcn_readfirstlane(find_image(prefix, count, g));
         const int tile = (int)(g - prefix[i]);
@@ -532,7 +587,8 @@ __global__ void __launch_bounds__(kBlock) scan_stage2_batch(const ScanK *ks, con
                                                             int count) {
     const int64_t total = prefix[count];
     const int64_t step = (int64_t)gridDim.x * kBlock;
-    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < total; g += step) {
+    for (int64_t g = prefix[0] + (int64_t)blockIdx.x * kBlock + threadIdx.x; g < total;
+         g += step) {
         const int i = find_image(prefix, count, g);
         stage2_item<P, SAT>(ks[i], g - prefix[i]);
     }
@@ -614,6 +670,34 @@ hipError_t batch_vec(const BatchScan &b, hipStream_t s) {
 size_t round_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
 
 }  // namespace
+
+template <int P, int VEC, int CHUNK>
+int occ3() {
+    int a = 0, b = 0, c = 0;
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &a, scan_tiles_batch<P, VEC, CHUNK, true, true, false>, kBlock, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &b, scan_tiles_batch<P, VEC, CHUNK, true, true, true>, kBlock, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, scan_stage2_batch<P, true>, kBlock, 0);
+    const int m = a < b ? (a < c ? a : c) : (b < c ? b : c);
+    return m > 0 ? m : 1;
+}
+
+template <int P, int VEC>
+int occ_chunk(int chunk) {
+    return chunk == 2 ? occ3<P, VEC, 2>() : chunk == 4 ? occ3<P, VEC, 4>() : occ3<P, VEC, 8>();
+}
+
+template <int P>
+int occ_vec(int vec, int chunk) {
+    return vec == 2 ? occ_chunk<P, 2>(chunk) : vec == 4 ? occ_chunk<P, 4>(chunk)
+                                                        : occ_chunk<P, 8>(chunk);
+}
+
+int scan_batch_occupancy(int prec, int vec, int chunk) {
+    return prec == kF32 ? occ_vec<kF32>(vec, chunk) : prec == kC32x2 ? occ_vec<kC32x2>(vec, chunk)
+                                                                     : occ_vec<kF64>(vec, chunk);
+}
 
 hipError_t launch_tables_batch(const BatchScan &b, hipStream_t s) {
     switch (b.prec) {

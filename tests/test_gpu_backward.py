@@ -133,3 +133,13 @@ def test_training_forward_and_residual_backward(prec):
     assert np.max(np.abs(R[11] - pbar)) <= 1e-4
     E = np.where(D > 0, ((Lj - Lr) / np.where(D > 0, D, 1) * (-varj / (varj + 0.1) ** 2)).sum(0), 0)
     assert np.max(np.abs(R[10] - E)) <= 1e-3 * (1 + np.max(np.abs(E)))
+    # pair planes: R2_j = c_j / N_j and R1_j / R2_j = -2 m_j with the oracle's window mean
+    pairs = tm.residual_pairs(m.resid, 5).cpu().numpy().astype(np.float64)
+    N = np.stack([oracle.box_filter(np.ones((H, W)), rx[j], ry[j]) for j in range(5)])
+    Dd = np.where(D > 0, D, 1)
+    c = np.where((D > 0) & (varj > 0), (Lj - Lr) / Dd * 0.1 / (varj + 0.1) ** 2, 0)
+    r2 = c / N
+    assert np.max(np.abs(pairs[..., 1] - r2)) <= 1e-3 * np.max(np.abs(r2)) + 1e-12
+    mj = np.stack([oracle.box_filter(lum.astype(np.float64), rx[j], ry[j]) for j in range(5)]) / N
+    r1 = -2 * r2 * mj
+    assert np.max(np.abs(pairs[..., 0] - r1)) <= 1e-3 * np.max(np.abs(r1)) + 1e-12

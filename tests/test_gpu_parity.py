@@ -64,15 +64,15 @@ def test_edges_degenerate_image():
 
 # --------------------------------------------------------------------------- a3
 TUNES = [None, (2, 1, 2), (8, 3, 8), (4, 16, 4), (2, 64, 8)]
+# every shape with the default tiling; the explicit tilings are swept on three shapes
+SHAPE_TUNES = [(H, W, 0) for H, W in SHAPES] + [
+    (H, W, ti) for H, W in [(256, 256), (37, 123), (65, 257)] for ti in range(1, len(TUNES))]
 
 
-@pytest.mark.parametrize("H,W", SHAPES)
+@pytest.mark.parametrize("H,W,ti", SHAPE_TUNES)
 @pytest.mark.parametrize("n", [2, 5, 64])
 @pytest.mark.parametrize("layout", ["cumulative", "per_bin"])
-@pytest.mark.parametrize("ti", range(len(TUNES)))
 def test_integral_histogram_bit_exact(H, W, n, layout, ti):
-    if ti and (H, W) not in [(256, 256), (37, 123), (65, 257)]:
-        pytest.skip("tunes are swept on three shapes")
     _, ref = _lum_dev(H, W, seed=3 * n + W)
     v = to_dev(ref)
     edges = to_dev(edges_ref(ref, n))
@@ -88,11 +88,8 @@ def test_integral_histogram_bit_exact(H, W, n, layout, ti):
 
 # --------------------------------------------------------------------------- a2
 @pytest.mark.parametrize("prec", ["f32", "c32x2", "f64"])
-@pytest.mark.parametrize("H,W", SHAPES)
-@pytest.mark.parametrize("ti", range(len(TUNES)))
+@pytest.mark.parametrize("H,W,ti", SHAPE_TUNES)
 def test_integral_image_within_bound(prec, H, W, ti):
-    if ti and (H, W) not in [(256, 256), (37, 123), (65, 257)]:
-        pytest.skip("tunes are swept on three shapes")
     _, ref = _lum_dev(H, W, seed=11 + W, lo=-3.0, hi=5.0)
     v = to_dev(ref)
     vd = ref.astype(np.float64)
