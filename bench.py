@@ -123,7 +123,9 @@ def bench_batch(args):
         print(f"bench: generated image {i + 1}/{len(shapes)} ({h}x{w})", file=sys.stderr,
               flush=True)
     mpx = sum(h * w for h, w in shapes) / 1e6
-    cands = [(4, 16, 4), (2, 16, 4), (8, 16, 4), (4, 8, 4), (4, 32, 4)]
+    # (0 = each image's own default for its shape)
+    cands = [(0, 0, 4), (0, 16, 4), (4, 0, 4), (2, 0, 4), (4, 16, 4), (2, 16, 4), (4, 8, 4),
+             (4, 32, 4)]
     t, _ = autotune.tune_batch(imgs, args.n_bins, args.n_scales, args.prec, reps=3,
                                use_cache=False, cands=cands)
     b = tm.Batch(imgs, args.n_bins, args.n_scales, args.eps, prec=args.prec, tune=t)
@@ -149,7 +151,7 @@ def bench_batch(args):
         _, H, W = rgb.shape
         mappers.append(tm.ToneMapper(H, W, tm.make_params(args.n_bins, args.n_scales,
                                                           eps=args.eps, H=H, W=W),
-                                     args.prec, tune=t, device=dev))
+                                     args.prec, tune=tm.image_tune(t, H, W), device=dev))
     per_ms = timed(lambda: [m.run(r) for m, r in zip(mappers, imgs)])
     line = {
         "metric": "aggregate megapixels/s, batched forward (HIP graph) vs per-image launches",

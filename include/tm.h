@@ -105,6 +105,11 @@ typedef struct {
 
 const char *tm_status_string(tm_status s);
 
+/* The scan tiling an H x W image gets when an entry point is passed tune = NULL (host
+ * function): 4 columns per lane from width 2048 up, else 2; 16 rows per tile, halved (not
+ * below 4) while the image has fewer than 2048 tiles; 4 planes per pass. */
+tm_status tm_default_tune(int32_t H, int32_t W, tm_tune *t);
+
 /* Radii of the receptive-field pyramid (Section II-C): the largest field is the image and
  * each next one is half as wide, rx[j] = W >> (j+1), ry[j] = H >> (j+1) for j < n_scales.
  * Host function; fills p->rx, p->ry only. */
@@ -274,13 +279,18 @@ size_t tm_batch_workspace_bytes(const tm_image_desc *descs, int32_t count, const
 
 /* Lay the batch out in ws and upload its descriptor tables on `stream` (asynchronously; the
  * object keeps the host copies alive).  descs is read during the call only.  tune: one scan
- * tiling for all images (NULL: 4 columns per lane, 16 rows, 4 planes per pass). */
+ * tiling for all images, except that tile_w_vec = 0 and tile_h = 0 give every image the
+ * library default for its own shape (NULL: {0, 0, 4}).  The images are processed in groups
+ * of equal columns per lane; outputs go to each descriptor's own buffer. */
 tm_status tm_batch_create(const tm_image_desc *descs, int32_t count, const tm_params *p,
                           tm_sat_prec prec, const tm_tune *tune, void *ws, size_t ws_bytes,
                           void *stream, tm_batch **batch);
 
-/* The forward of every image: one persistent launch per phase over all images (prologue
- * parts, per-image finalize, scan stages 1-3, fused query) -- 6 launches, no host sync. */
+/* The forward of every image.  The images are taken in consecutive groups whose integral
+ * tables together stay within 160 MiB (so that the fused query finds them still in the
+ * memory-side cache); for each group, one launch per phase covers all its images (prologue
+ * parts, per-image finalize, scan stages 1-3, fused query) -- 6 launches per group, no host
+ * sync. */
 tm_status tm_batch_forward(tm_batch *batch, void *stream);
 
 /* Record tm_batch_forward into a HIP graph (stream must not be the null stream; nothing is

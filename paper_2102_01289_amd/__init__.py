@@ -15,7 +15,8 @@ import torch
 from . import _capi
 
 __all__ = [
-    "TmError", "Table", "table_geometry", "paper_radii", "make_params", "tune",
+    "TmError", "Table", "table_geometry", "paper_radii", "make_params", "tune", "default_tune",
+    "image_tune",
     "tm_luminance", "tm_image_stats", "tm_prologue", "tm_integral_image",
     "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
@@ -101,6 +102,22 @@ def make_params(n_bins: int = 5, n_scales: int = 5, rx=None, ry=None, eps: float
 
 def tune(tile_w_vec: int, tile_h: int, bin_chunk: int) -> _capi.TmTune:
     return _capi.TmTune(tile_w_vec, tile_h, bin_chunk)
+
+
+def default_tune(H: int, W: int) -> _capi.TmTune:
+    """The scan tiling an H x W image gets by default (tm_default_tune)."""
+    t = _capi.TmTune()
+    _ck("tm_default_tune", _lib().tm_default_tune(H, W, ctypes.byref(t)))
+    return t
+
+
+def image_tune(t, H: int, W: int) -> _capi.TmTune:
+    """A batch tiling as one image of shape H x W uses it: 0 fields take the image's
+    default."""
+    d = default_tune(H, W)
+    if t is None:
+        return d
+    return _capi.TmTune(t.tile_w_vec or d.tile_w_vec, t.tile_h or d.tile_h, t.bin_chunk)
 
 
 # ------------------------------------------------------------------------ tables
@@ -435,7 +452,7 @@ def tonemap(rgb: torch.Tensor, n_bins: int = 5, n_scales: int = 5, eps: float = 
 # ------------------------------------------------------------------------ batches
 class Batch:
     """Forward of many images of uneven size: per-image buffers laid out in one workspace,
-    one persistent launch per phase over all images (tm_batch_forward), optionally recorded
+    one launch per phase over each group of images (tm_batch_forward), optionally recorded
     once into a HIP graph and replayed (tm_batch_capture / tm_batch_replay)."""
 
     def __init__(self, rgbs, n_bins: int = 5, n_scales: int = 5, eps: float = 0.1,

@@ -42,10 +42,15 @@ def _store(key: str, value) -> None:
     os.replace(tmp, path)
 
 
-def candidates(n_bins: int):
+def candidates(n_bins: int, batch: bool = False):
+    """Tilings to time: columns per lane x rows per tile x planes per pass.  For batches,
+    0 columns per lane or 0 rows per tile means each image takes the default for its own
+    shape."""
     planes = n_bins - 1
     chunks = [c for c in (2, 4, 8) if c <= max(planes, 2) or c == 4]
-    return [(v, th, c) for v in (2, 4, 8) for th in (4, 8, 16, 32) for c in chunks]
+    rows = (0, 4, 8, 16, 32) if batch else (4, 8, 16, 32)
+    vecs = (0, 2, 4, 8) if batch else (2, 4, 8)
+    return [(v, th, c) for v in vecs for th in rows for c in chunks]
 
 
 def _time(fn, reps: int, warmup: int = 2) -> float:
@@ -108,7 +113,7 @@ def tune_batch(rgbs, n_bins: int = 5, n_scales: int = 5, prec: str = "c32x2", re
         if hit:
             return tune(*hit[:3]), hit[3]
     best = None
-    for c in (cands or candidates(n_bins)):
+    for c in (cands or candidates(n_bins, batch=True)):
         b = Batch(rgbs, n_bins, n_scales, prec=prec, tune=tune(*c))
         ms = _time(b.forward, reps)
         b.close()

@@ -207,8 +207,11 @@ __global__ void __launch_bounds__(kBlock) border_reduce_kernel(BwdK k) {
 // virtual pixel (0, 0) forms cooperatively before use.  The four gathers of a field are
 // issued together, branch-free: a corner that does not exist reads a clamped in-image
 // address with weight 0 (such lanes share one cache line).  Rows are wave-uniform.
+// S: the number of fields, fixed at compile time so that the gathers of every field are
+// issued together (a loop with a run-time bound keeps one field's loads in flight at a time).
+template <int S>
 __global__ void __launch_bounds__(kBlock) deposit_kernel(BwdK k) {
-    const int s = k.p.n_scales;
+    constexpr int s = S;
     __shared__ double shK[2][kS];
     int tx, rg;
     comb_map(xcd_tile(blockIdx.x, gridDim.x), k.tiles_x, k.p4, k.teeth, tx, rg);
@@ -238,9 +241,29 @@ __global__ void __launch_bounds__(kBlock) deposit_kernel(BwdK k) {
     const int cx = k.W - 1 - xv, cy = k.H - 1 - yv;   // cy is wave-uniform
     const bool lastx = cx == k.W - 1, lasty = cy == k.H - 1;
     double d0 = 0.0, d1 = 0.0;
+    // gather phase: all loads of all fields first
+    float2 rv[S][4];
+    float gw[S][4];
 #pragma unroll
-    for (int j = 0; j < kS; ++j) {
-        if (j < s) {
+    for (int j = 0; j < S; ++j) {
+        const int rx = k.p.rx[j], ry = k.p.ry[j];
+        const int ax = max(cx - rx, 0), bx = min(cx + rx + 1, k.W - 1);
+        const int ay = max(cy - ry, 0), by = min(cy + ry + 1, k.H - 1);
+        const float2 *Rj = rpair(k, j);
+        const float2 *Ra = Rj + (int64_t)ay * k.W, *Rb_ = Rj + (int64_t)by * k.W;
+        const float *ga = k.g + (int64_t)ay * k.ld_g, *gb = k.g + (int64_t)by * k.ld_g;
+        rv[j][0] = Ra[ax];
+        rv[j][1] = Ra[bx];
+        rv[j][2] = Rb_[ax];
+        rv[j][3] = Rb_[bx];
+        gw[j][0] = ga[ax];
+        gw[j][1] = ga[bx];
+        gw[j][2] = gb[ax];
+        gw[j][3] = gb[bx];
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        {
             const int rx = k.p.rx[j], ry = k.p.ry[j];
             const int pxp = cx - rx;        // pixel whose x+ corner is cx (cx < W-1)
             const int pxm = cx + rx + 1;    // pixel whose x- corner is cx
@@ -248,13 +271,8 @@ __global__ void __launch_bounds__(kBlock) deposit_kernel(BwdK k) {
             const int pym = cy + ry + 1;
             const bool okxp = !lastx && pxp >= 0, okxm = pxm <= k.W - 1;
             const bool okyp = !lasty && pyp >= 0, okym = pym <= k.H - 1;
-            const int ax = max(pxp, 0), bx = min(pxm, k.W - 1);
-            const int ay = max(pyp, 0), by = min(pym, k.H - 1);
-            const float2 *Rj = rpair(k, j);
-            const float2 *Ra = Rj + (int64_t)ay * k.W, *Rb_ = Rj + (int64_t)by * k.W;
-            const float *ga = k.g + (int64_t)ay * k.ld_g, *gb = k.g + (int64_t)by * k.ld_g;
-            const float2 r_pp = Ra[ax], r_mp = Ra[bx], r_pm = Rb_[ax], r_mm = Rb_[bx];
-            const float g_pp = ga[ax], g_mp = ga[bx], g_pm = gb[ax], g_mm = gb[bx];
+            const float2 r_pp = rv[j][0], r_mp = rv[j][1], r_pm = rv[j][2], r_mm = rv[j][3];
+            const float g_pp = gw[j][0], g_mp = gw[j][1], g_pm = gw[j][2], g_mm = gw[j][3];
             const double w_pp = okxp && okyp ? (double)g_pp : 0.0;
             const double w_mp = okxm && okyp ? -(double)g_mp : 0.0;
             const double w_pm = okxp && okym ? -(double)g_pm : 0.0;
@@ -363,7 +381,16 @@ hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, voi
     hipLaunchKernelGGL(scalar_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k.part, (int)nbs,
                        a.grad_params);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(deposit_kernel, dim3((unsigned)plan.nblocks), dim3(kBlock), 0, s, k);
+    switch (S) {
+#define TM_DEPOSIT(n)                                                                           \
+    case n:                                                                                    \
+        hipLaunchKernelGGL(deposit_kernel<n>, dim3((unsigned)plan.nblocks), dim3(kBlock), 0, s, k); \
+        break;
+        TM_DEPOSIT(1) TM_DEPOSIT(2) TM_DEPOSIT(3) TM_DEPOSIT(4)
+        TM_DEPOSIT(5) TM_DEPOSIT(6) TM_DEPOSIT(7) TM_DEPOSIT(8)
+#undef TM_DEPOSIT
+        default: return hipErrorInvalidValue;
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_suffix_adjoint(k.Dr, a.W, a.v, a.ld_v, a.H, a.W, a.grad_v, a.ld_gv,
                                  plan.scan_plan, w + plan.scan, s);

@@ -1,5 +1,5 @@
-// tm_batch.cpp -- batched forward: many images of uneven size in persistent launches, one per
-// phase and image group, recordable as one HIP graph.
+// tm_batch.cpp -- batched forward: many images of uneven size, one launch per phase and image
+// group, recordable as one HIP graph.
 //
 // tm_batch_create lays every image's buffers out in the caller's workspace, builds the
 // per-image kernel descriptors (StatsK, ScanK, FwdK) and prefix sums of each phase's work
@@ -7,12 +7,15 @@
 // integral tables together stay within kGroupTableBytes: the fused query reads every table
 // entry twenty times (four corners, five fields), and it runs at about twice the speed when
 // the tables it reads were just written and still sit in the 256 MB memory-side cache.
-// tm_batch_forward then launches, group after group, six kernels whose persistent grids walk
-// the flattened work of the group's images (statistics, edges, three scan phases, query).
+// tm_batch_forward then launches, group after group, six kernels whose grids cover the
+// flattened work of the group's images (statistics, edges, three scan phases, query), one
+// work item per block (per wave for the scan tiles), so the hardware hands the items out in
+// order and the items in flight stay a compact window of the list.
 // Every image keeps exactly the reduction structure and scan tiling of a single-image call
 // with the same tiling, so batched outputs equal per-image outputs bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -28,14 +31,16 @@ struct tm_batch {
     std::vector<StatsK> sk;
     std::vector<ScanK> ck;
     std::vector<FwdK> fk;
+    std::vector<int> vec;   // columns per lane of the scan of descriptor k
     std::vector<int64_t> parts, tiles, items, qtiles;   // prefixes, count + 1 each
     StatsK *d_sk = nullptr;
     ScanK *d_ck = nullptr;
     FwdK *d_fk = nullptr;
     int64_t *d_parts = nullptr, *d_tiles = nullptr, *d_items = nullptr, *d_qtiles = nullptr;
     struct Group {
-        int i0, i1;                                  // images [i0, i1)
-        unsigned g_stats, g_tiles, g_items, g_query;   // persistent grid sizes
+        int i0, i1;                                  // descriptors [i0, i1)
+        int vec;                                     // their scans' columns per lane
+        unsigned g_stats, g_tiles, g_items, g_query;   // grid sizes
     };
     std::vector<Group> groups;
     bool h32 = true;   // every image's histogram offsets fit the 32-bit query addressing
@@ -85,8 +90,10 @@ tm_status check(const tm_image_desc *d, int32_t count, const tm_params *p, tm_sa
         p->n_scales > TM_MAX_SCALES)
         return TM_ERR_ARG;
     if (!(p->eps > 0.f) || !(p->ld_max > p->ld_min)) return TM_ERR_ARG;
-    t = tune ? ScanTune{tune->tile_w_vec, tune->tile_h, tune->bin_chunk} : ScanTune{4, 16, 4};
-    if (!scan_tune_valid(t)) return TM_ERR_ARG;
+    // tile_w_vec 0 / tile_h 0: every image takes the default for its own shape
+    t = tune ? ScanTune{tune->tile_w_vec, tune->tile_h, tune->bin_chunk} : ScanTune{0, 0, 4};
+    if (!scan_tune_valid(ScanTune{t.vec ? t.vec : 4, t.th ? t.th : 16, t.chunk}))
+        return TM_ERR_ARG;
     for (int i = 0; i < count; ++i) {
         const tm_image_desc &x = d[i];
         if (x.H < 1 || x.W < 1 || (int64_t)x.H * x.W >= ((int64_t)1 << 31)) return TM_ERR_SHAPE;
@@ -99,9 +106,28 @@ tm_status check(const tm_image_desc *d, int32_t count, const tm_params *p, tm_sa
     return TM_OK;
 }
 
-// Lays the batch out from `base` (nullptr: sizing only) and fills the host descriptors.
+// The scan tiling of one image: the batch's, with 0 fields taken from the image's default.
+ScanTune image_tiling(const ScanTune &t, int H, int W) {
+    const ScanTune def = scan_tune_default(H, W);
+    return ScanTune{t.vec ? t.vec : def.vec, t.th ? t.th : def.th, t.chunk};
+}
+
+// Processing order: the images sorted (stably) by columns per lane, so that a group of
+// consecutive images shares one compiled scan variant.
+std::vector<int> processing_order(const tm_image_desc *d, int32_t count, const ScanTune &t) {
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return image_tiling(t, d[a].H, d[a].W).vec < image_tiling(t, d[b].H, d[b].W).vec;
+    });
+    return order;
+}
+
+// Lays the batch out from `base` (nullptr: sizing only) and fills the host descriptors, in
+// processing order (descriptor k is image order[k]; bufs stay indexed by image).
 size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int prec,
               const ScanTune &t, char *base, tm_batch *b) {
+    const std::vector<int> order = processing_order(d, count, t);
     Carver c{base};
     const size_t o_sk = c.take(sizeof(StatsK) * count);
     const size_t o_ck = c.take(sizeof(ScanK) * count);
@@ -118,6 +144,7 @@ size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int pre
         b->sk.resize(count);
         b->ck.resize(count);
         b->fk.resize(count);
+        b->vec.resize(count);
         b->bufs.resize(count);
         b->parts.assign(count + 1, 0);
         b->tiles.assign(count + 1, 0);
@@ -125,7 +152,8 @@ size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int pre
         b->qtiles.assign(count + 1, 0);
     }
     for (int i = 0; i < count; ++i) {
-        const tm_image_desc &x = d[i];
+        const int img = order[i];
+        const tm_image_desc &x = d[img];
         const int H = x.H, W = x.W;
         int64_t ld, org, elems;
         tm_table_geometry(H, W, &ld, &org, &elems);
@@ -135,7 +163,8 @@ size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int pre
         const size_t o_part = c.take(sizeof(StatsPartial) * (size_t)stats_blocks(H, W));
         const size_t o_sat = c.take(entry_bytes(prec) * (size_t)elems);
         const size_t o_hist = c.take(4 * (size_t)elems * (size_t)(n > 1 ? n - 1 : 1));
-        const ScanPlan sp = make_scan_plan(H, W, prec, n - 1, t);
+        const ScanTune ti = image_tiling(t, H, W);
+        const ScanPlan sp = make_scan_plan(H, W, prec, n - 1, ti);
         const size_t o_scan = c.take(sp.total);
         if (!b) continue;
         float *lum = c.ptr<float>(o_lum);
@@ -144,7 +173,8 @@ size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int pre
         float *minmax = edges + 258;
         void *sat = c.ptr<char>(o_sat) + org * entry_bytes(prec);
         uint32_t *hist = c.ptr<uint32_t>(o_hist) + org;
-        b->bufs[i] = {lum, edges, offsets, ld_lum, sat, ld, hist, ld, elems};
+        b->bufs[img] = {lum, edges, offsets, ld_lum, sat, ld, hist, ld, elems};
+        b->vec[i] = ti.vec;
         b->sk[i] = make_statsk(x.rgb, x.ch_stride, x.ld_rgb, nullptr, 0, lum, ld_lum, H, W, n,
                                edges, offsets, minmax, c.ptr<StatsPartial>(o_part));
         ScanArgs a{};
@@ -222,34 +252,29 @@ tm_status tm_batch_create(const tm_image_desc *descs, int32_t count, const tm_pa
     b->prec = (int)prec;
     b->tune = t;
     layout(descs, count, p, (int)prec, t, static_cast<char *>(ws), b);
-    int cus = 256, dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess)
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     // Image groups (consecutive, tables within kGroupTableBytes, at least one image each)
-    // and their persistent grids: every block resident from the start (blocks per CU from
-    // the occupancy of each kernel), so the static interleaved work split stays balanced.
+    // and their grids: one work item per block (per wave for the scan tiles), handed out
+    // in order by the hardware, so the items in flight stay a compact window of the list.
     for (int i = 0; i < count; ++i) b->h32 = b->h32 && hist_offsets_fit_32(b->fk[i]);
-    const int64_t occ_s = stats_batch_occupancy(),
-                  occ_t = scan_batch_occupancy(b->prec, t.vec, t.chunk),
-                  occ_q = forward_batch_occupancy(b->prec, b->h32);
     const size_t per_entry = entry_bytes((int)prec) + 4 * (size_t)(p->n_bins > 1 ? p->n_bins - 1 : 0);
     for (int i0 = 0; i0 < count;) {
         int i1 = i0;
         size_t bytes = 0;
         while (i1 < count) {
-            const size_t bi = (size_t)b->bufs[i1].plane_stride * per_entry;
-            if (i1 > i0 && bytes + bi > kGroupTableBytes) break;
+            const size_t bi = (size_t)b->fk[i1].plane_stride * per_entry;
+            if (i1 > i0 && (bytes + bi > kGroupTableBytes || b->vec[i1] != b->vec[i0])) break;
             bytes += bi;
             ++i1;
         }
         tm_batch::Group g;
         g.i0 = i0;
         g.i1 = i1;
-        g.g_stats = clampu(b->parts[i1] - b->parts[i0], 1, occ_s * cus);
-        g.g_tiles = clampu((b->tiles[i1] - b->tiles[i0] + 3) / 4, 1, occ_t * cus);
-        g.g_items = clampu((b->items[i1] - b->items[i0] + 255) / 256, 1, occ_t * cus);
-        g.g_query = clampu((b->qtiles[i1] - b->qtiles[i0] + 7) / 8 * 8, 8,
-                           occ_q * cus / 8 * 8) / 8 * 8;
+        g.vec = b->vec[i0];
+        const int64_t kMaxGrid = ((int64_t)1 << 31) - 1;
+        g.g_stats = clampu(b->parts[i1] - b->parts[i0], 1, kMaxGrid);
+        g.g_tiles = clampu((b->tiles[i1] - b->tiles[i0] + 3) / 4, 1, kMaxGrid);
+        g.g_items = clampu((b->items[i1] - b->items[i0] + 255) / 256, 1, kMaxGrid);
+        g.g_query = clampu(b->qtiles[i1] - b->qtiles[i0], 1, kMaxGrid);   // one block per tile
         b->groups.push_back(g);
         i0 = i1;
     }
@@ -281,7 +306,7 @@ tm_status tm_batch_forward(tm_batch *b, void *stream) {
         hipError_t e = launch_stats_batch(b->d_sk + g.i0, b->d_parts + g.i0, n, g.g_stats, s);
         if (e != hipSuccess) return TM_ERR_HIP;
         BatchScan bs{b->d_ck + g.i0, b->d_tiles + g.i0, b->d_items + g.i0, n, b->prec,
-                     b->tune.vec, b->tune.chunk, g.g_tiles, g.g_items};
+                     g.vec, b->tune.chunk, g.g_tiles, g.g_items};
         e = launch_tables_batch(bs, s);
         if (e != hipSuccess) return TM_ERR_HIP;
         e = launch_forward_batch(b->d_fk + g.i0, b->d_qtiles + g.i0, n, b->prec, b->h32,

@@ -130,6 +130,16 @@ tm_status tm_paper_radii(int32_t H, int32_t W, tm_params *p) {
     return TM_OK;
 }
 
+tm_status tm_default_tune(int32_t H, int32_t W, tm_tune *t) {
+    if (!t) return TM_ERR_ARG;
+    TM_TRY(check_image(H, W));
+    const ScanTune d = scan_tune_default(H, W);
+    t->tile_w_vec = d.vec;
+    t->tile_h = d.th;
+    t->bin_chunk = d.chunk;
+    return TM_OK;
+}
+
 tm_status tm_table_geometry(int32_t H, int32_t W, int64_t *ld, int64_t *origin_offset,
                             int64_t *elems) {
     TM_TRY(check_image(H, W));

@@ -30,12 +30,10 @@ int stats_blocks(int H, int W);
 StatsK make_statsk(const float *rgb, int64_t ch_stride, int64_t ld_rgb, const float *lum_in,
                    int64_t ld_in, float *lum_out, int64_t ld_out, int H, int W, int n_bins,
                    float *edges, float *offsets, float *minmax, StatsPartial *partials);
-// Prologue of a batch: parts of every image in one persistent launch, then one finalize
+// Prologue of a batch: the parts of images [0, count) in one launch, then one finalize
 // block per image (device arrays ks[count], part_prefix[count+1]).
 hipError_t launch_stats_batch(const StatsK *ks, const int64_t *part_prefix, int count,
                               unsigned grid, hipStream_t s);
-// Resident blocks per CU of the batched statistics kernel (at least 1).
-int stats_batch_occupancy();
 
 hipError_t launch_luminance(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int H, int W,
                             float *lum, int64_t ld_lum, hipStream_t s);
@@ -109,8 +107,8 @@ struct ScanArgs {
 hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipStream_t s);
 ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws);
 
-// Integral image + cumulative histogram of a whole batch: three persistent launches over
-// flattened work lists (device arrays: ks[count], tile_prefix[count+1], item_prefix[count+1]).
+// Integral image + cumulative histogram of images [0, count): three launches over flattened
+// work lists (device arrays: ks[count], tile_prefix[count+1], item_prefix[count+1]).
 struct BatchScan {
     const ScanK *ks;
     const int64_t *tile_prefix, *item_prefix;
@@ -118,9 +116,7 @@ struct BatchScan {
     unsigned grid_tiles, grid_items;
 };
 hipError_t launch_tables_batch(const BatchScan &b, hipStream_t s);
-// Resident blocks per CU of the batched scan kernels of this precision and tiling (the
-// smallest over the three phases, at least 1).
-int scan_batch_occupancy(int prec, int vec, int chunk);
+
 // Items of stage 2 of one image (thread-level): nq*H + nq*W + nq*tiles_y.
 int64_t scan_stage2_items(const ScanK &k, bool sat);
 
@@ -160,12 +156,10 @@ struct FwdK {
 constexpr int kQueryRows = 4;   // a query block covers 64 columns x 4 rows
 // Blocks of one image's fused query (the comb schedule may include idle blocks).
 int64_t query_blocks(const FwdK &k);
-// Fused query of a batch: one persistent launch (grid a multiple of 8) over every image's
-// tiles (device arrays ks[count], tile_prefix[count+1]).
+// Fused query of a batch: one block per tile of images [0, count) (device arrays ks[count],
+// tile_prefix[count+1]; the grid is tile_prefix[count] - tile_prefix[0]).
 hipError_t launch_forward_batch(const FwdK *ks, const int64_t *tile_prefix, int count, int prec,
                                 bool h32, unsigned grid, hipStream_t s);
-// Resident blocks per CU of the batched query kernel (at least 1).
-int forward_batch_occupancy(int prec, bool h32);
 // Every histogram byte offset of the query of k fits in 32 bits.
 bool hist_offsets_fit_32(const FwdK &k);
 FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int64_t ld_sat,

@@ -130,11 +130,14 @@ __global__ void __launch_bounds__(kBlock) lum_stats_kernel(StatsK k) {
 
 // Batched prologue over images [0, count) of ks: item g in [prefix[0], prefix[count]) is part
 // (g - prefix[i]) of image i.
-__global__ void __launch_bounds__(kBlock) lum_stats_batch(const StatsK *ks, const int64_t *prefix,
+__global__ void __launch_bounds__(kBlock) lum_stats_batch(const StatsK *__restrict__ ks,
+                                                          const int64_t *__restrict__ prefix,
                                                           int count) {
     const int64_t total = prefix[count];
-    for (int64_t g = prefix[0] + blockIdx.x; g < total; g += gridDim.x) {
-        const int i = find_image(prefix, count, g);
+    int64_t g = prefix[0] + blockIdx.x;
+    int i = g < total ? find_image(prefix, count, g) : 0;   // advances with g
+    for (; g < total; g += gridDim.x) {
+        while (g >= prefix[i + 1]) ++i;
         stats_part<true, true>(ks[i], (int)(g - prefix[i]), ks[i].nparts);
         __syncthreads();
     }
@@ -266,7 +269,7 @@ __device__ void finalize_body(const StatsK &k) {
 
 __global__ void __launch_bounds__(kBlock) stats_finalize_kernel(StatsK k) { finalize_body(k); }
 
-__global__ void __launch_bounds__(kBlock) stats_finalize_batch(const StatsK *ks, int count) {
+__global__ void __launch_bounds__(kBlock) stats_finalize_batch(const StatsK *__restrict__ ks, int count) {
     for (int i = blockIdx.x; i < count; i += gridDim.x) {
         finalize_body(ks[i]);
         __syncthreads();
@@ -331,12 +334,6 @@ hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, con
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k);
     return hipGetLastError();
-}
-
-int stats_batch_occupancy() {
-    int n = 0;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lum_stats_batch, kBlock, 0) ==
-                   hipSuccess && n > 0 ? n : 1;
 }
 
 hipError_t launch_stats_batch(const StatsK *ks, const int64_t *part_prefix, int count,

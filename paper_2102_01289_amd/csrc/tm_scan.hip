@@ -563,17 +563,21 @@ __global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
 }
 
 // ---------------------------------------------------------------- batched kernels
-// A persistent grid walks one flattened list of work items spanning images [0, count) of ks;
-// prefix points at the first image's entry of the batch-wide prefix sums, so the walk covers
-// [prefix[0], prefix[count]).
+// A grid walks one flattened list of work items spanning images [0, count) of ks; prefix
+// points at the first image's entry of the batch-wide prefix sums, so the walk covers
+// [prefix[0], prefix[count]).  The batch launches one item per wave (one wave per item is
+// handed out in order by the hardware); the loop also serves smaller grids.
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool THIRD>
-__global__ void __launch_bounds__(kBlock) scan_tiles_batch(const ScanK *ks, const int64_t *prefix,
+__global__ void __launch_bounds__(kBlock) scan_tiles_batch(const ScanK *__restrict__ ks,
+                                                           const int64_t *__restrict__ prefix,
                                                            int count) {
     const int64_t total = prefix[count];
     const int64_t step = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t g = prefix[0] + (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); g < total;
-         g += step) {
-        const int i = __builtin_amdgcn_readfirstlane(find_image(prefix, count, g));
+    int64_t g = prefix[0] + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    // g only grows, so the image index only advances (no search per tile)
+    int i = g < total ? __builtin_amdgcn_readfirstlane(find_image(prefix, count, g)) : 0;
+    for (; g < total; g += step) {
+        while (g >= prefix[i + 1]) ++i;
         const int tile = (int)(g - prefix[i]);
         if (THIRD)
             stage3_tile<P, VEC, CHUNK, SAT, HIST, false>(ks[i], tile);
@@ -583,7 +587,8 @@ __global__ void __launch_bounds__(kBlock) scan_tiles_batch(const ScanK *ks, cons
 }
 
 template <int P, bool SAT>
-__global__ void __launch_bounds__(kBlock) scan_stage2_batch(const ScanK *ks, const int64_t *prefix,
+__global__ void __launch_bounds__(kBlock) scan_stage2_batch(const ScanK *__restrict__ ks,
+                                                           const int64_t *__restrict__ prefix,
                                                             int count) {
     const int64_t total = prefix[count];
     const int64_t step = (int64_t)gridDim.x * kBlock;
@@ -670,34 +675,6 @@ hipError_t batch_vec(const BatchScan &b, hipStream_t s) {
 size_t round_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
 
 }  // namespace
-
-template <int P, int VEC, int CHUNK>
-int occ3() {
-    int a = 0, b = 0, c = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &a, scan_tiles_batch<P, VEC, CHUNK, true, true, false>, kBlock, 0);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &b, scan_tiles_batch<P, VEC, CHUNK, true, true, true>, kBlock, 0);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, scan_stage2_batch<P, true>, kBlock, 0);
-    const int m = a < b ? (a < c ? a : c) : (b < c ? b : c);
-    return m > 0 ? m : 1;
-}
-
-template <int P, int VEC>
-int occ_chunk(int chunk) {
-    return chunk == 2 ? occ3<P, VEC, 2>() : chunk == 4 ? occ3<P, VEC, 4>() : occ3<P, VEC, 8>();
-}
-
-template <int P>
-int occ_vec(int vec, int chunk) {
-    return vec == 2 ? occ_chunk<P, 2>(chunk) : vec == 4 ? occ_chunk<P, 4>(chunk)
-                                                        : occ_chunk<P, 8>(chunk);
-}
-
-int scan_batch_occupancy(int prec, int vec, int chunk) {
-    return prec == kF32 ? occ_vec<kF32>(vec, chunk) : prec == kC32x2 ? occ_vec<kC32x2>(vec, chunk)
-                                                                     : occ_vec<kF64>(vec, chunk);
-}
 
 hipError_t launch_tables_batch(const BatchScan &b, hipStream_t s) {
     switch (b.prec) {

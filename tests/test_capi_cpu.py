@@ -127,3 +127,12 @@ def test_table_padded_view_layout_on_host():
         for y in range(H):
             for x in range(W):
                 assert pad[p, y + 1, x + 1] == 100 * p + 10 * y + x + 1
+
+
+def test_default_tune_matches_the_documented_rule():
+    from _bounds import tiling
+    for H, W in [(3000, 4000), (1080, 1920), (256, 256), (20, 4100), (1, 1), (4000, 360)]:
+        t = tm.default_tune(H, W)
+        assert (t.tile_w_vec, t.tile_h, t.bin_chunk) == (*tiling(H, W), 4)
+    t = tm.image_tune(tm.tune(0, 8, 2), 1080, 1920)
+    assert (t.tile_w_vec, t.tile_h, t.bin_chunk) == (2, 8, 2)

@@ -6,6 +6,7 @@ import torch
 
 import paper_2102_01289_amd as tm
 from paper_2102_01289_amd import autotune
+from _bounds import tiling
 from _cases import rgb_case, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -33,6 +34,25 @@ def test_batch_equals_per_image(prec, t):
         assert torch.equal(outs[i], ref), i
 
 
+@pytest.mark.parametrize("t", [(4, 0, 4), (0, 8, 2), (0, 0, 4), None])
+def test_batch_per_image_tiling(t):
+    # 0 fields (and the default tiling): each image scans with its own shape's default;
+    # the images are processed grouped by columns per lane, outputs stay in image order
+    imgs = _images(seed=11, shapes=SHAPES + [(40, 2500), (20, 4100)])
+    b = tm.Batch(imgs, 5, 5, tune=tm.tune(*t) if t else None)
+    outs = [o.clone() for o in b.forward()]
+    torch.cuda.synchronize()
+    tt = t or (0, 0, 4)
+    for i, rgb in enumerate(imgs):
+        _, H, W = rgb.shape
+        p = tm.make_params(5, 5, eps=0.1, H=H, W=W)
+        vec, th = tiling(H, W)
+        ref = tm.ToneMapper(H, W, p, "c32x2",
+                            tune=tm.tune(tt[0] or vec, tt[1] or th, tt[2])).run(rgb)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], ref), i
+
+
 def test_batch_other_parameters():
     imgs = _images(seed=5, shapes=[(50, 70), (33, 300), (200, 20)])
     b = tm.Batch(imgs, n_bins=64, n_scales=3, eps=0.05, ld_min=0.1, ld_max=0.9)
@@ -40,7 +60,8 @@ def test_batch_other_parameters():
     for i, rgb in enumerate(imgs):
         _, H, W = rgb.shape
         p = tm.make_params(64, 3, eps=0.05, ld_min=0.1, ld_max=0.9, H=H, W=W)
-        ref = tm.ToneMapper(H, W, p, "c32x2", tune=tm.tune(4, 16, 4)).run(rgb)
+        # the default batch tiling is each image's own default
+        ref = tm.ToneMapper(H, W, p, "c32x2").run(rgb)
         assert torch.equal(outs[i], ref)
 
 
@@ -74,8 +95,8 @@ def test_batch_graph_replays_match_eager():
 def test_autotune_picks_a_valid_tiling(tmp_path, monkeypatch):
     monkeypatch.setenv("TM355_TUNE_CACHE", str(tmp_path / "tune.json"))
     imgs = _images(seed=3, shapes=[(120, 500), (300, 200)])
-    t, ms = autotune.tune_batch(imgs, reps=2, cands=[(2, 8, 4), (4, 16, 4)])
-    assert (t.tile_w_vec, t.tile_h, t.bin_chunk) in [(2, 8, 4), (4, 16, 4)] and ms > 0
+    t, ms = autotune.tune_batch(imgs, reps=2, cands=[(2, 8, 4), (4, 16, 4), (4, 0, 4)])
+    assert (t.tile_w_vec, t.tile_h, t.bin_chunk) in [(2, 8, 4), (4, 16, 4), (4, 0, 4)] and ms > 0
     t2, _ = autotune.tune_image(imgs[0], reps=2)
     assert t2.tile_w_vec in (2, 4, 8)
     t3, _ = autotune.tune_image(imgs[0], reps=2)       # second call is served by the cache
