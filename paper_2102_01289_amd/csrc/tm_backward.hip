@@ -104,27 +104,39 @@ __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
     const int xc = min(x, k.W - 1);      // in-image address for the lanes past the edge
     const bool in = x < k.W;
     const int tile_end = min(ct * kWave + kWave, k.W);
-    for (int y = y0 + w; y < y1; y += kRows) {   // y is wave-uniform
+    // every load of a row in one phase; the next row of this wave is loaded before the
+    // current one is reduced
+    struct Row {
+        float g, e, p;
+        float2 r[kS];
+    };
+    auto load_row = [&](int y, Row &q) {
         const int64_t o = (int64_t)y * k.W + xc;
-        // load phase: every load of the row issued before any reduction
-        const float gf = k.g[(int64_t)y * k.ld_g + xc];
-        const float ef = E[o], pf = Pb[o];
-        float2 rr[kS];
+        q.g = k.g[(int64_t)y * k.ld_g + xc];
+        q.e = E[o];
+        q.p = Pb[o];
 #pragma unroll
         for (int j = 0; j < kS; ++j) {
-            rr[j] = make_float2(0.f, 0.f);
+            q.r[j] = make_float2(0.f, 0.f);
             // wave-uniform: does any field-j range sum need this tile row?
-            if (j < s && (tile_end > lox[j] || y >= loy[j])) rr[j] = rpair(k, j)[o];
+            if (j < s && (tile_end > lox[j] || y >= loy[j])) q.r[j] = rpair(k, j)[o];
         }
-        const double gx = in ? (double)gf : 0.0;
-        const double pb = (double)pf;
-        sacc.a = __builtin_fma(gx, (double)ef, sacc.a);
+    };
+    Row cur, nxt;
+    int y = y0 + w;   // wave-uniform
+    if (y < y1) load_row(y, cur);
+    for (; y < y1; y += kRows) {
+        const bool more = y + kRows < y1;
+        if (more) load_row(y + kRows, nxt);
+        const double gx = in ? (double)cur.g : 0.0;
+        const double pb = (double)cur.p;
+        sacc.a = __builtin_fma(gx, (double)cur.e, sacc.a);
         sacc.b = __builtin_fma(gx, 1.0 - pb, sacc.b);
         sacc.c = __builtin_fma(gx, pb, sacc.c);
 #pragma unroll
         for (int j = 0; j < kS; ++j) {
             if (j < s) {
-                const double a = gx * (double)rr[j].x, b = gx * (double)rr[j].y;
+                const double a = gx * (double)cur.r[j].x, b = gx * (double)cur.r[j].y;
                 if (y >= loy[j]) { cacc[0][j] += a; cacc[1][j] += b; }
                 double ra = 0.0, rb = 0.0;
                 if (tile_end > lox[j]) {   // block-uniform: the row range reaches this tile
@@ -138,6 +150,7 @@ __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
                 }
             }
         }
+        if (more) cur = nxt;
     }
     // column partials: the four waves' sums in a fixed order
     __shared__ double shc[kRows][kWave];
