@@ -198,6 +198,34 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
                              int64_t plane_stride, const float *edges, const tm_params *p,
                              float *out, int64_t ld_out, void *stream);
 
+/* Colour restoration (Sec. II-D, Eq. 12) fused into the forward: after L (the tone-mapped
+ * luminance of tm_tonemap_forward) each output channel is
+ *   c_out = (c_in / v)^saturation * L,   c = R, G, B,
+ * with v the input luminance (the image the tables were built from, normally Eq. 11 of the
+ * same rgb).  Readings: inputs are clamped at 0, and where v = 0 the ratio is taken as 1 (a
+ * neutral pixel).  The paper uses saturation = 0.6; any finite saturation >= 0 is accepted
+ * (0 gives a grey image of value L).  rgb / rgb_out: planar FP32, channel c at
+ * rgb + c*ch_stride, row pitch ld_rgb (ch_stride >= H*ld_rgb), caller-owned device memory.
+ * out (tone-mapped luminance, pitch ld_out) may be NULL. */
+tm_status tm_tonemap_forward_rgb(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                 const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                                 const float *offsets, const uint32_t *hist_cum,
+                                 int64_t ld_hist, int64_t plane_stride, const float *edges,
+                                 const tm_params *p, const float *rgb, int64_t ch_stride,
+                                 int64_t ld_rgb, float saturation, float *rgb_out,
+                                 int64_t ch_stride_out, int64_t ld_rgb_out, float *out,
+                                 int64_t ld_out, void *stream);
+
+/* The whole path RGB -> RGB on one image: prologue (Eq. 11, edges, offsets), integral image
+ * of precision prec and cumulative integral histogram (default tiling), fused query with
+ * colour restoration.  Every intermediate lives in ws (tm_tonemap_rgb_workspace_bytes). */
+size_t tm_tonemap_rgb_workspace_bytes(int32_t H, int32_t W, const tm_params *p,
+                                      tm_sat_prec prec);
+tm_status tm_tonemap_rgb(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                         int32_t W, const tm_params *p, tm_sat_prec prec, float saturation,
+                         float *rgb_out, int64_t ch_stride_out, int64_t ld_rgb_out, void *ws,
+                         size_t ws_bytes, void *stream);
+
 /* Number of FP32 residual planes a training forward writes: 2 * n_scales + 2 (0 if
  * n_scales is out of range). */
 int32_t tm_residual_planes(int32_t n_scales);

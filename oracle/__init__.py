@@ -9,7 +9,8 @@ Contents
     with integer arithmetic (Python's unbounded ints);
   * thin numpy wrappers around the plain C oracle (``tm_oracle.c``): luminance (Eq. 11),
     bins (Eq. 7), integral histogram (Eq. 8), integral images (Eq. 5), the forward method
-    (Eq. 1-4, 6, 9, 10) with integral tables or with direct window sums, the backward;
+    (Eq. 1-4, 6, 9, 10) with integral tables or with direct window sums, the backward,
+    colour restoration (Eq. 12);
   * ``paper_radii``: the receptive-field pyramid of Section II-C.
 The pure-Python brute force used to pin the C code lives in ``oracle.brute``.
 """
@@ -54,6 +55,8 @@ def lib() -> ctypes.CDLL:
         L.orc_backward.restype = I
         L.orc_box_filter.argtypes = [P, I64, I64, ctypes.c_int32, ctypes.c_int32, P]
         L.orc_box_filter.restype = I
+        L.orc_color_restore.argtypes = [P, P, P, I64, I64, D, P]
+        L.orc_color_restore.restype = None
         _LIB = L
     return _LIB
 
@@ -237,4 +240,16 @@ def box_filter(a, rx: int, ry: int):
     out = np.empty((H, W), dtype=np.float64)
     if lib().orc_box_filter(_ptr(a), H, W, int(rx), int(ry), _ptr(out)) != 0:
         raise MemoryError("oracle box_filter: allocation failed")
+    return out
+
+
+def color_restore(rgb, lum, L, sat: float = 0.6) -> np.ndarray:
+    """Eq. 12 (Section II-D): out_c = (c / v)^sat * L for c = R, G, B, in FP64 (planar
+    [3, H, W]); channels below 0 count as 0 and the ratio is 1 where v == 0."""
+    rgb = _c(rgb, np.float32)
+    lum = _c(lum, np.float32)
+    L = _c(L, np.float64)
+    H, W = lum.shape
+    out = np.empty((3, H, W), dtype=np.float64)
+    lib().orc_color_restore(_ptr(rgb), _ptr(lum), _ptr(L), H, W, float(sat), _ptr(out))
     return out

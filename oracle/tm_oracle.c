@@ -504,3 +504,22 @@ int orc_box_filter(const double *a, int64_t H, int64_t W, int32_t rx, int32_t ry
     free(sat);
     return 0;
 }
+
+/* ------------------------------------------------------------------ colour (Eq. 12) */
+/* Colour restoration (Section II-D, Eq. 12): every channel keeps its ratio to the input
+ * luminance, compressed by the exponent sat, and is scaled by the tone-mapped luminance:
+ *   out_c = (c / v)^sat * L,  c = R, G, B   (planar rgb, c at rgb + c*H*W).
+ * Readings: channel values below 0 count as 0; where v == 0 the ratio is 1.  FP64. */
+void orc_color_restore(const float *rgb, const float *v, const double *L, int64_t H,
+                       int64_t W, double sat, double *out)
+{
+    const int64_t np = H * W;
+    for (int c = 0; c < 3; ++c)
+        for (int64_t p = 0; p < np; ++p) {
+            double cin = (double)rgb[c * np + p];
+            if (cin < 0.0)
+                cin = 0.0;
+            const double ratio = v[p] > 0.0f ? cin / (double)v[p] : 1.0;
+            out[c * np + p] = pow(ratio, sat) * L[p];
+        }
+}

@@ -21,6 +21,7 @@ __all__ = [
     "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
     "residual_planes", "residual_pairs", "ToneMapper", "tonemap", "Batch",
+    "tm_tonemap_forward_rgb", "tonemap_rgb",
 ]
 
 
@@ -272,6 +273,54 @@ def tm_tonemap_forward(v, sat: Table, hist: Table | None, edges, params, offsets
     return out
 
 
+def _check_rgb(rgb, H=None, W=None):
+    if rgb.dtype != torch.float32 or rgb.dim() != 3 or rgb.shape[0] != 3 or \
+            rgb.stride(2) != 1 or not rgb.is_cuda:
+        raise ValueError("rgb must be a CUDA float32 planar [3, H, W] tensor with unit column "
+                         "stride")
+    if H is not None and tuple(rgb.shape[1:]) != (H, W):
+        raise ValueError(f"rgb is {tuple(rgb.shape[1:])}, expected {(H, W)}")
+
+
+def tm_tonemap_forward_rgb(v, sat: Table, hist: Table | None, edges, params, rgb,
+                           saturation: float = 0.6, offsets=None, rgb_out=None, out=None,
+                           stream=None):
+    """Fused query and colour restoration (Eq. 12): rgb_out [3, H, W] = (rgb / v)^saturation
+    * L; L is also written to `out` when given."""
+    H, W, ld = _img(v, "v")
+    _check_rgb(rgb, H, W)
+    if rgb_out is None:
+        rgb_out = torch.empty((3, H, W), dtype=torch.float32, device=v.device)
+    _check_rgb(rgb_out, H, W)
+    _ck("tm_tonemap_forward_rgb", _lib().tm_tonemap_forward_rgb(
+        _vp(v), ld, H, W, _vp(sat.ptr), sat.ld, _capi.SAT_PREC[sat.kind], _vp(offsets),
+        _vp(hist.ptr if hist else None), hist.ld if hist else 0,
+        hist.plane_stride if hist else 0, _vp(edges), ctypes.byref(params), _vp(rgb),
+        rgb.stride(0), rgb.stride(1), float(saturation), _vp(rgb_out), rgb_out.stride(0),
+        rgb_out.stride(1), _vp(out), out.stride(0) if out is not None else 0, _stream(stream)))
+    return rgb_out
+
+
+def tonemap_rgb(rgb: torch.Tensor, n_bins: int = 5, n_scales: int = 5, eps: float = 0.1,
+                prec: str = "c32x2", saturation: float = 0.6, ld_min: float = 0.0,
+                ld_max: float = 1.0, rgb_out=None, stream=None) -> torch.Tensor:
+    """The whole path RGB -> RGB on one planar image (tm_tonemap_rgb): Eq. 11 luminance and
+    bin edges, integral tables, fused query with colour restoration (Eq. 12)."""
+    _check_rgb(rgb)
+    _, H, W = rgb.shape
+    p = make_params(n_bins, n_scales, eps=eps, ld_min=ld_min, ld_max=ld_max, H=H, W=W)
+    if rgb_out is None:
+        rgb_out = torch.empty((3, H, W), dtype=torch.float32, device=rgb.device)
+    _check_rgb(rgb_out, H, W)
+    ws = _ws(_lib().tm_tonemap_rgb_workspace_bytes(H, W, ctypes.byref(p),
+                                                   _capi.SAT_PREC[prec]), rgb.device)
+    _ck("tm_tonemap_rgb", _lib().tm_tonemap_rgb(
+        _vp(rgb), rgb.stride(0), rgb.stride(1), H, W, ctypes.byref(p), _capi.SAT_PREC[prec],
+        float(saturation), _vp(rgb_out), rgb_out.stride(0), rgb_out.stride(1), _vp(ws),
+        ws.numel(), _stream(stream)))
+    return rgb_out
+
+
 def residual_planes(n_scales: int) -> int:
     return int(_lib().tm_residual_planes(n_scales))
 
@@ -392,6 +441,21 @@ class ToneMapper:
         self.tables(stream)
         self.query(stream)
         return self.out
+
+    def query_rgb(self, rgb, saturation: float = 0.6, stream=None) -> torch.Tensor:
+        """Fused query with colour restoration (Eq. 12) of rgb: returns rgb_out [3, H, W]
+        (L is also left in self.out)."""
+        if not hasattr(self, "rgb_out"):
+            self.rgb_out = torch.empty((3, self.H, self.W), dtype=torch.float32,
+                                       device=self.lum.device)
+        return tm_tonemap_forward_rgb(self.lum, self.sat, self.hist, self.edges, self.params,
+                                      rgb, saturation, self.offsets, self.rgb_out, self.out,
+                                      stream)
+
+    def run_rgb(self, rgb, saturation: float = 0.6, stream=None) -> torch.Tensor:
+        self.prologue(rgb, stream)
+        self.tables(stream)
+        return self.query_rgb(rgb, saturation, stream)
 
     def query_train(self, stream=None):
         """Fused query that also writes the backward's residual planes."""

@@ -61,6 +61,12 @@ SIGNATURES = {
     "tm_tonemap_forward": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
                                           I64, P, PP, P, I64, P]),
     "tm_backward_workspace_bytes": (SZ, [I32, I32, PP]),
+    "tm_tonemap_forward_rgb": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
+                                              I64, P, PP, P, I64, I64, F, P, I64, I64, P, I64,
+                                              P]),
+    "tm_tonemap_rgb_workspace_bytes": (SZ, [I32, I32, PP, ctypes.c_int]),
+    "tm_tonemap_rgb": (ctypes.c_int, [P, I64, I64, I32, I32, PP, ctypes.c_int, F, P, I64, I64, P,
+                                      SZ, P]),
     "tm_residual_planes": (I32, [I32]),
     "tm_tonemap_forward_train": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P,
                                                 I64, I64, P, PP, P, I64, P, P]),

@@ -303,6 +303,103 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
                                    (hipStream_t)stream));
 }
 
+tm_status tm_tonemap_forward_rgb(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                 const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                                 const float *offsets, const uint32_t *hist_cum,
+                                 int64_t ld_hist, int64_t plane_stride, const float *edges,
+                                 const tm_params *p, const float *rgb, int64_t ch_stride,
+                                 int64_t ld_rgb, float saturation, float *rgb_out,
+                                 int64_t ch_stride_out, int64_t ld_rgb_out, float *out,
+                                 int64_t ld_out, void *stream) {
+    TM_TRY(check_image(H, W));
+    TM_TRY(check_params(p));
+    if (!v || !rgb || !rgb_out || !valid_prec(prec)) return TM_ERR_ARG;
+    if (!(saturation >= 0.f) || !std::isfinite(saturation)) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_v));
+    TM_TRY(check_plane(H, W, ld_rgb));
+    TM_TRY(check_plane(H, W, ld_rgb_out));
+    if (ch_stride < (int64_t)H * ld_rgb || ch_stride_out < (int64_t)H * ld_rgb_out)
+        return TM_ERR_SHAPE;
+    if (out) TM_TRY(check_plane(H, W, ld_out));
+    TM_TRY(check_table(H, W, ld_sat, sat));
+    if (prec == TM_SAT_C32X2 && !offsets) return TM_ERR_ARG;
+    if (p->n_bins > 1) {
+        if (!edges) return TM_ERR_ARG;
+        TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
+    }
+    const QueryParams q = to_query(p);
+    return from_hip(launch_forward_rgb(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
+                                       ld_hist, plane_stride, edges, q, out, ld_out, rgb,
+                                       ch_stride, ld_rgb, rgb_out, ch_stride_out, ld_rgb_out,
+                                       saturation, (hipStream_t)stream));
+}
+
+// Buffers of the end-to-end RGB call, carved from its workspace (offsets in bytes).
+struct RgbPlan {
+    int64_t ld_lum, ld, org, elems;
+    size_t lum, edges, stats, sat, hist, scan, total;
+    size_t stats_bytes, scan_bytes;
+};
+
+static bool rgb_plan(int32_t H, int32_t W, const tm_params *p, tm_sat_prec prec, RgbPlan &r) {
+    if (check_image(H, W) != TM_OK || check_params(p) != TM_OK || !valid_prec(prec)) return false;
+    if (tm_table_geometry(H, W, &r.ld, &r.org, &r.elems) != TM_OK) return false;
+    r.ld_lum = ((int64_t)W + 63) / 64 * 64;
+    const size_t es = prec == TM_SAT_F32 ? 8 : 16;
+    const int planes = p->n_bins > 1 ? p->n_bins - 1 : 0;
+    r.stats_bytes = tm_image_stats_workspace_bytes(H, W);
+    r.scan_bytes = tm_tables_workspace_bytes(H, W, p->n_bins, prec, nullptr);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) / 256 * 256;
+        return o;
+    };
+    r.lum = take(sizeof(float) * (size_t)H * (size_t)r.ld_lum);
+    r.edges = take(sizeof(float) * 260);
+    r.stats = take(r.stats_bytes);
+    r.sat = take(es * (size_t)r.elems);
+    r.hist = take(4 * (size_t)r.elems * (size_t)(planes > 0 ? planes : 1));
+    r.scan = take(r.scan_bytes);
+    r.total = off;
+    return true;
+}
+
+size_t tm_tonemap_rgb_workspace_bytes(int32_t H, int32_t W, const tm_params *p,
+                                      tm_sat_prec prec) {
+    RgbPlan r;
+    return rgb_plan(H, W, p, prec, r) ? r.total : 0;
+}
+
+tm_status tm_tonemap_rgb(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                         int32_t W, const tm_params *p, tm_sat_prec prec, float saturation,
+                         float *rgb_out, int64_t ch_stride_out, int64_t ld_rgb_out, void *ws,
+                         size_t ws_bytes, void *stream) {
+    RgbPlan r;
+    if (!rgb_plan(H, W, p, prec, r)) {
+        TM_TRY(check_image(H, W));
+        TM_TRY(check_params(p));
+        return TM_ERR_ARG;
+    }
+    if (!rgb || !rgb_out) return TM_ERR_ARG;
+    TM_TRY(check_ws(ws, ws_bytes, r.total));
+    char *w = static_cast<char *>(ws);
+    float *lum = reinterpret_cast<float *>(w + r.lum);
+    float *edges = reinterpret_cast<float *>(w + r.edges);
+    float *offsets = edges + 256, *minmax = edges + 258;
+    const size_t es = prec == TM_SAT_F32 ? 8 : 16;
+    void *sat = w + r.sat + (size_t)r.org * es;
+    uint32_t *hist = p->n_bins > 1 ? reinterpret_cast<uint32_t *>(w + r.hist) + r.org : nullptr;
+    TM_TRY(tm_prologue(rgb, ch_stride, ld_rgb, H, W, p->n_bins, lum, r.ld_lum, edges, offsets,
+                       minmax, w + r.stats, r.stats_bytes, stream));
+    TM_TRY(tm_integral_tables(lum, r.ld_lum, H, W, prec, offsets, sat, r.ld, edges, p->n_bins,
+                              TM_HIST_CUMULATIVE, hist, r.ld, r.elems, nullptr, w + r.scan,
+                              r.scan_bytes, stream));
+    return tm_tonemap_forward_rgb(lum, r.ld_lum, H, W, sat, r.ld, prec, offsets, hist, r.ld,
+                                  r.elems, edges, p, rgb, ch_stride, ld_rgb, saturation, rgb_out,
+                                  ch_stride_out, ld_rgb_out, nullptr, 0, stream);
+}
+
 int32_t tm_residual_planes(int32_t n_scales) {
     return (n_scales < 1 || n_scales > TM_MAX_SCALES) ? 0 : 2 * n_scales + 2;
 }

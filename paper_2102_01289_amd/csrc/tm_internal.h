@@ -152,6 +152,12 @@ struct FwdK {
     int p4, teeth;      // comb schedule: period in 4-row groups, number of teeth
     float *resid;       // training forward: 2s + 2 residual planes of H*W (else null)
     int64_t rstride;
+    // colour restoration (Eq. 12), when rgb_out is not null: planar RGB in and out
+    const float *rgb;
+    int64_t rgb_cs, rgb_ld;
+    float *rgb_out;
+    int64_t out_cs, out_ld;
+    float saturation;
 };
 constexpr int kQueryRows = 4;   // a query block covers 64 columns x 4 rows
 // Blocks of one image's fused query (the comb schedule may include idle blocks).
@@ -166,6 +172,15 @@ FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int6
                 const float *offsets, const uint32_t *hist, int64_t ld_hist,
                 int64_t plane_stride, const float *edges, const QueryParams &p, float *out,
                 int64_t ld_out);
+// The fused query followed by colour restoration (Eq. 12): c_out = (c_in / v)^sat L for
+// c = R, G, B (the ratio taken as 1 where v = 0, inputs clamped at 0); out may be null.
+hipError_t launch_forward_rgb(const float *v, int64_t ld_v, int H, int W, const void *sat_tab,
+                              int64_t ld_sat, int prec, const float *offsets,
+                              const uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
+                              const float *edges, const QueryParams &p, float *out,
+                              int64_t ld_out, const float *rgb, int64_t rgb_cs, int64_t rgb_ld,
+                              float *rgb_out, int64_t out_cs, int64_t out_ld, float sat,
+                              hipStream_t s);
 hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void *sat,
                           int64_t ld_sat, int prec, const float *offsets, const uint32_t *hist,
                           int64_t ld_hist, int64_t plane_stride, const float *edges,

@@ -174,6 +174,17 @@ __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float
     }
     const float L = den > 0.f ? num / den : lsum / (float)s;
     if (k.out) __builtin_nontemporal_store(L, gptr(k.out) + (int64_t)y * k.ld_out + x);
+    if (k.rgb_out) {
+        // Eq. 12: each channel keeps its ratio to the input luminance, compressed by sat
+        const TM_GLOBAL float *ci = gptr(k.rgb) + (int64_t)y * k.rgb_ld + x;
+        TM_GLOBAL float *co = gptr(k.rgb_out) + (int64_t)y * k.out_ld + x;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float cin = fmaxf(ci[c * k.rgb_cs], 0.f);
+            const float r = v > 0.f ? cin / v : 1.f;
+            __builtin_nontemporal_store(powf(r, k.saturation) * L, co + c * k.out_cs);
+        }
+    }
     if (RESID) {
         TM_GLOBAL float *ro = gptr(k.resid) + (int64_t)y * k.W + x;
         const int64_t ps = k.rstride;
@@ -284,6 +295,11 @@ FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int6
     k.tiles_x = (W + kWave - 1) / kWave;
     k.resid = nullptr;
     k.rstride = 0;
+    k.rgb = nullptr;
+    k.rgb_cs = k.rgb_ld = 0;
+    k.rgb_out = nullptr;
+    k.out_cs = k.out_ld = 0;
+    k.saturation = 0.f;
     comb_params(H, kRows, p.ry, p.n_scales, &k.p4, &k.teeth);
     return k;
 }
@@ -310,6 +326,26 @@ bool hist_offsets_fit_32(const FwdK &k) {
     if (!k.hist || k.p.n_bins < 2) return true;
     const int64_t last = (int64_t)(k.p.n_bins - 2) * k.plane_stride + (int64_t)k.W + 1;
     return last * 4 < ((int64_t)1 << 32);
+}
+
+hipError_t launch_forward_rgb(const float *v, int64_t ld_v, int H, int W, const void *sat_tab,
+                              int64_t ld_sat, int prec, const float *offsets,
+                              const uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
+                              const float *edges, const QueryParams &p, float *out,
+                              int64_t ld_out, const float *rgb, int64_t rgb_cs, int64_t rgb_ld,
+                              float *rgb_out, int64_t out_cs, int64_t out_ld, float sat,
+                              hipStream_t s) {
+    FwdK k = make_fwdk(v, ld_v, H, W, sat_tab, ld_sat, offsets, hist, ld_hist, plane_stride,
+                       edges, p, out, ld_out);
+    k.rgb = rgb;
+    k.rgb_cs = rgb_cs;
+    k.rgb_ld = rgb_ld;
+    k.rgb_out = rgb_out;
+    k.out_cs = out_cs;
+    k.out_ld = out_ld;
+    k.saturation = sat;
+    return hist_offsets_fit_32(k) ? launch_fwd<false, true>(k, prec, s)
+                                  : launch_fwd<false, false>(k, prec, s);
 }
 
 hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void *sat,

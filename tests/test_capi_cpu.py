@@ -136,3 +136,23 @@ def test_default_tune_matches_the_documented_rule():
         assert (t.tile_w_vec, t.tile_h, t.bin_chunk) == (*tiling(H, W), 4)
     t = tm.image_tune(tm.tune(0, 8, 2), 1080, 1920)
     assert (t.tile_w_vec, t.tile_h, t.bin_chunk) == (2, 8, 2)
+
+
+def test_rgb_entry_argument_checks():
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    fake, null = P(1 << 20), P(0)
+    p = _params()
+    args = lambda sat, cs=100, rgb=fake: (fake, 10, 10, 10, fake, 64, 1, fake, fake, 64, 1 << 12,
+                                          fake, ctypes.byref(p), rgb, cs, 10, sat, fake, 100, 10,
+                                          null, 0, null)
+    for sat in (-0.1, float("nan"), float("inf")):
+        assert lib.tm_tonemap_forward_rgb(*args(sat)) == -1, sat
+    assert lib.tm_tonemap_forward_rgb(*args(0.6, rgb=null)) == -1
+    assert lib.tm_tonemap_forward_rgb(*args(0.6, cs=50)) == -2             # ch_stride < H*ld
+    H, W = 30, 40
+    pp = tm.make_params(5, 5, H=H, W=W)
+    need = lib.tm_tonemap_rgb_workspace_bytes(H, W, ctypes.byref(pp), 1)
+    assert need > 0 and lib.tm_tonemap_rgb_workspace_bytes(H, W, ctypes.byref(pp), 7) == 0
+    assert lib.tm_tonemap_rgb(fake, H * W, W, H, W, ctypes.byref(pp), 1, 0.6, fake, H * W, W,
+                              fake, need - 1, null) == -4

@@ -290,3 +290,51 @@ def test_backward_matches_central_differences(orc):
     d_eps = (np.sum(g * orc.forward(v, e, rx, ry, 0.1 + he))
              - np.sum(g * orc.forward(v, e, rx, ry, 0.1 - he))) / (2 * he)
     assert abs(d_eps - geps) <= 1e-6 * (1 + abs(geps))
+
+
+# ---------------------------------------------------------------- Eq. 12 colour restoration
+def _color_case(seed=3, H=7, W=9):
+    import oracle
+    rng = np.random.default_rng(seed)
+    rgb = rng.uniform(0.0, 3.0, (3, H, W)).astype(np.float32)
+    rgb[:, 0, 0] = 0.0                       # black pixel: v = 0, ratio taken as 1
+    rgb[:, 1, 1] = (2.0, -0.01, 1.0)         # a negative channel counts as 0
+    lum = oracle.luminance(rgb)
+    L = rng.uniform(0.0, 1.0, (H, W))
+    return rgb, lum, L
+
+
+def test_color_sat_one_is_the_plain_ratio(orc):
+    oracle = orc
+    # sat = 1: each channel is scaled by L / v
+    rgb, lum, L = _color_case()
+    out = oracle.color_restore(rgb, lum, L, 1.0)
+    c = np.maximum(rgb.astype(np.float64), 0.0)
+    v = lum.astype(np.float64)
+    want = np.where(v > 0, c / np.where(v > 0, v, 1.0), 1.0) * L
+    assert np.allclose(out, want, rtol=1e-15, atol=0)
+
+
+def test_color_sat_zero_is_grey(orc):
+    oracle = orc
+    rgb, lum, L = _color_case()
+    out = oracle.color_restore(rgb, lum, L, 0.0)
+    assert np.array_equal(out, np.broadcast_to(L, out.shape))
+
+
+def test_color_channel_ratios_and_exponent_law(orc):
+    oracle = orc
+    rgb, lum, L = _color_case(seed=8)
+    a, b = 0.35, 0.25
+    oa = oracle.color_restore(rgb, lum, L, a)
+    ob = oracle.color_restore(rgb, lum, L, b)
+    oab = oracle.color_restore(rgb, lum, L, a + b)
+    ok = (lum > 0) & (L > 0)
+    # (c/v)^(a+b) L = (c/v)^a L (c/v)^b L / L
+    assert np.allclose(oab[:, ok], (oa * ob)[:, ok] / L[ok], rtol=1e-13)
+    # channel ratios are the input ratios raised to sat (where both channels are positive)
+    c = rgb.astype(np.float64)
+    pos = ok & (c[0] > 0) & (c[2] > 0)
+    assert np.allclose(oa[0, pos] / oa[2, pos], (c[0, pos] / c[2, pos]) ** a, rtol=1e-13)
+    # the black pixel is neutral and the negative channel is zero
+    assert np.all(oa[:, 0, 0] == L[0, 0]) and oa[1, 1, 1] == 0.0
