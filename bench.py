@@ -48,10 +48,75 @@ def _parse():
                     help="after the timed loop, copy 1 GiB device-to-device once (a plain copy "
                          "kernel of known size, for calibrating HBM counters) and report its "
                          "bandwidth")
-    ap.add_argument("--workload", choices=["image", "batch", "precision"], default="image",
+    ap.add_argument("--workload", choices=["image", "batch", "precision", "sweep"],
+                    default="image",
                     help="image: one 4000x3000 image (default); batch: 64 images of uneven "
-                         "size, persistent launches replayed from a HIP graph")
+                         "size, launches replayed from a HIP graph; precision: output error "
+                         "per integral-image precision; sweep: the paper's Table IV grid "
+                         "(n, s in {3, 4, 5} at 480x640, 720x1280, 1080x1920) with a per-stage "
+                         "split")
     return ap.parse_args()
+
+
+# The paper's Table IV: whole tone-mapping time in ms on its phone GPU (an iPhone 6 Plus
+# through Metal), by bins n, fields s and resolution.  Context only: other hardware and an
+# unstated precision.
+PAPER_TABLE_IV_MS = {
+    (3, 3): (122.11, 303.79, 637.90), (3, 4): (145.82, 351.13, 788.27),
+    (3, 5): (166.91, 402.36, 865.69), (4, 3): (130.33, 284.74, 677.69),
+    (4, 4): (174.73, 359.80, 793.60), (4, 5): (175.14, 422.65, 920.95),
+    (5, 3): (139.69, 293.37, 869.33), (5, 4): (187.64, 355.05, 886.96),
+    (5, 5): (212.44, 432.90, 1016.26)}
+SWEEP_SHAPES = ((480, 640), (720, 1280), (1080, 1920))
+
+
+def bench_sweep(args):
+    """Forward time of one image over the Table IV grid, with the per-stage split (prologue,
+    tables, query; the paper's Fig. 7 splits its own time the same way) and each stage's
+    algorithmic bytes over its time."""
+    import torch
+
+    import paper_2102_01289_amd as tm
+    from synth import gen_wdr
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for k, (H, W) in enumerate(SWEEP_SHAPES):
+        rgb = torch.from_numpy(gen_wdr(H, W, 32, -2.0, 4.0, 202 + k).rgb).to(dev)
+        for (n, s), paper in PAPER_TABLE_IV_MS.items():
+            p = tm.make_params(n, s, eps=0.1, H=H, W=W)
+            m = tm.ToneMapper(H, W, p, args.prec, device=dev)
+            m.run(rgb)
+            stage = {}
+            for name, fn in (("prologue", lambda: m.prologue(rgb)), ("tables", m.tables),
+                             ("query", m.query)):
+                for _ in range(args.warmup):
+                    fn()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(args.steps):
+                    fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                stage[name] = a.elapsed_time(b) / args.steps
+            ms = sum(stage.values())
+            sat_b = {"f32": 8, "c32x2": 16, "f64": 16}[args.prec]
+            bytes_px = {"prologue": 16, "tables": 4 + sat_b + 4 * (n - 1),
+                        "query": query_bytes_per_px(args.prec, n)}
+            rows.append({
+                "height": H, "width": W, "n_bins": n, "n_scales": s,
+                "ms": round(ms, 4), "mp_s": round(H * W / (ms * 1e-3) / 1e6, 1),
+                "stage_ms": {k2: round(v, 4) for k2, v in stage.items()},
+                "stage_share": {k2: round(v / ms, 3) for k2, v in stage.items()},
+                "stage_algorithmic_gb_s": {k2: round(bytes_px[k2] * H * W / (v * 1e-3) / 1e9, 1)
+                                           for k2, v in stage.items()},
+                "paper_ms_iphone6plus": paper[k],
+                "speedup_vs_paper_context": round(paper[k] / ms, 1)})
+            print(f"sweep: {H}x{W} n={n} s={s}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "forward ms and MP/s over the Table IV grid (n, s, resolution)",
+                      "data": "synthetic", "sat_precision": args.prec, "steps": args.steps,
+                      "rows": rows}), flush=True)
 
 
 def bench_precision(args):
@@ -255,6 +320,9 @@ def main():
         return
     if args.workload == "precision":
         bench_precision(args)
+        return
+    if args.workload == "sweep":
+        bench_sweep(args)
         return
 
     import numpy as np

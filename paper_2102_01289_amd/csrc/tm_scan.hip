@@ -285,12 +285,27 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
 }
 
 // ================================================================ stage 2
-// Exclusive prefix of n values at stride `stride`, the loads issued 8 at a time so that the
-// scan's add chain does not serialise the memory latency.
+// Exclusive prefix of n values at stride `stride`, the loads issued 32 at a time so that
+// the scan's add chain does not serialise the memory latency (a column chain of a 1080-row
+// image with 4-row tiles is 270 values; stage 2 runs far fewer threads than the GPU holds,
+// so its time is the number of load round trips in the longest chain).  src and dst do not
+// overlap.
 template <class A, class T>
-__device__ __forceinline__ void excl_scan(const T *src, T *dst, int n, int64_t stride) {
+__device__ __forceinline__ void excl_scan(const T *__restrict__ src, T *__restrict__ dst, int n,
+                                          int64_t stride) {
+    constexpr int kB = 32;
     T run = A::zero();
     int t = 0;
+    for (; t + kB <= n; t += kB) {
+        T a[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) a[u] = src[(int64_t)(t + u) * stride];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            dst[(int64_t)(t + u) * stride] = run;
+            run = A::add(run, a[u]);
+        }
+    }
     for (; t + 8 <= n; t += 8) {
         T a[8];
 #pragma unroll
@@ -405,6 +420,9 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
         PlaneEdges<CHUNK> pe;
         if (do_h) pe = chunk_edges<CHUNK>(k, p0);
 
+        // the tile's first row is requested before the carries, so both loads are in flight
+        RowIn<VEC, ADJ> nxt;
+        if (rows > 0) load_in<VEC, ADJ>(k, y0, xl, nxt);
         T c1[VEC], c2[VEC];
         uint32_t cc[CHUNK][VEC];
         if (do_sat) {
@@ -424,8 +442,6 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
             }
         }
 
-        RowIn<VEC, ADJ> nxt;
-        if (rows > 0) load_in<VEC, ADJ>(k, y0, xl, nxt);
 #pragma unroll 2
         for (int r = 0; r < rows; ++r) {
             const int y = y0 + r;
