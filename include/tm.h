@@ -198,6 +198,17 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
                              int64_t plane_stride, const float *edges, const tm_params *p,
                              float *out, int64_t ld_out, void *stream);
 
+/* The forward of tm_tonemap_forward that also writes, for every field j, its tone value
+ * L_j (Eq. 2) and its weight W_j (Eq. 4), the maps Fig. 3 shows: maps holds 2 * n_scales
+ * planes of H*W FP32 (pitch W, plane stride H*W), L_j at plane j and W_j at plane
+ * n_scales + j; caller-owned. */
+tm_status tm_tonemap_forward_maps(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                  const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                                  const float *offsets, const uint32_t *hist_cum,
+                                  int64_t ld_hist, int64_t plane_stride, const float *edges,
+                                  const tm_params *p, float *out, int64_t ld_out, float *maps,
+                                  void *stream);
+
 /* Colour restoration (Sec. II-D, Eq. 12) fused into the forward: after L (the tone-mapped
  * luminance of tm_tonemap_forward) each output channel is
  *   c_out = (c_in / v)^saturation * L,   c = R, G, B,

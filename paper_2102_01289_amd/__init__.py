@@ -21,7 +21,7 @@ __all__ = [
     "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
     "residual_planes", "residual_pairs", "ToneMapper", "tonemap", "Batch",
-    "tm_tonemap_forward_rgb", "tonemap_rgb",
+    "tm_tonemap_forward_rgb", "tonemap_rgb", "tm_tonemap_forward_maps",
 ]
 
 
@@ -273,6 +273,26 @@ def tm_tonemap_forward(v, sat: Table, hist: Table | None, edges, params, offsets
     return out
 
 
+def tm_tonemap_forward_maps(v, sat: Table, hist: Table | None, edges, params, offsets=None,
+                            out=None, maps=None, stream=None):
+    """Forward plus the per-field maps of Fig. 3: (L [H, W], maps [2s, H, W]) with the tone
+    values L_j (Eq. 2) in maps[:s] and the weights W_j (Eq. 4) in maps[s:]."""
+    H, W, ld = _img(v, "v")
+    s = params.n_scales
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=v.device)
+    if maps is None:
+        maps = torch.empty((2 * s, H, W), dtype=torch.float32, device=v.device)
+    if tuple(maps.shape) != (2 * s, H, W) or not maps.is_contiguous():
+        raise ValueError(f"maps must be a contiguous [{2 * s}, {H}, {W}] tensor")
+    _ck("tm_tonemap_forward_maps", _lib().tm_tonemap_forward_maps(
+        _vp(v), ld, H, W, _vp(sat.ptr), sat.ld, _capi.SAT_PREC[sat.kind], _vp(offsets),
+        _vp(hist.ptr if hist else None), hist.ld if hist else 0,
+        hist.plane_stride if hist else 0, _vp(edges), ctypes.byref(params), _vp(out),
+        out.stride(0), _vp(maps), _stream(stream)))
+    return out, maps
+
+
 def _check_rgb(rgb, H=None, W=None):
     if rgb.dtype != torch.float32 or rgb.dim() != 3 or rgb.shape[0] != 3 or \
             rgb.stride(2) != 1 or not rgb.is_cuda:
@@ -441,6 +461,12 @@ class ToneMapper:
         self.tables(stream)
         self.query(stream)
         return self.out
+
+    def query_maps(self, stream=None):
+        """Fused query that also writes the per-field tone values and weights (Fig. 3):
+        (L, maps [2s, H, W])."""
+        return tm_tonemap_forward_maps(self.lum, self.sat, self.hist, self.edges, self.params,
+                                       self.offsets, self.out, None, stream)
 
     def query_rgb(self, rgb, saturation: float = 0.6, stream=None) -> torch.Tensor:
         """Fused query with colour restoration (Eq. 12) of rgb: returns rgb_out [3, H, W]

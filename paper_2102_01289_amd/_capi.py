@@ -61,6 +61,8 @@ SIGNATURES = {
     "tm_tonemap_forward": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
                                           I64, P, PP, P, I64, P]),
     "tm_backward_workspace_bytes": (SZ, [I32, I32, PP]),
+    "tm_tonemap_forward_maps": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
+                                               I64, P, PP, P, I64, P, P]),
     "tm_tonemap_forward_rgb": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
                                               I64, P, PP, P, I64, I64, F, P, I64, I64, P, I64,
                                               P]),

@@ -303,6 +303,30 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
                                    (hipStream_t)stream));
 }
 
+tm_status tm_tonemap_forward_maps(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                  const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                                  const float *offsets, const uint32_t *hist_cum,
+                                  int64_t ld_hist, int64_t plane_stride, const float *edges,
+                                  const tm_params *p, float *out, int64_t ld_out, float *maps,
+                                  void *stream) {
+    TM_TRY(check_image(H, W));
+    TM_TRY(check_params(p));
+    if (!v || !out || !maps || !valid_prec(prec)) return TM_ERR_ARG;
+    if (!aligned(maps, 4)) return TM_ERR_ALIGN;
+    TM_TRY(check_plane(H, W, ld_v));
+    TM_TRY(check_plane(H, W, ld_out));
+    TM_TRY(check_table(H, W, ld_sat, sat));
+    if (prec == TM_SAT_C32X2 && !offsets) return TM_ERR_ARG;
+    if (p->n_bins > 1) {
+        if (!edges) return TM_ERR_ARG;
+        TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
+    }
+    const QueryParams q = to_query(p);
+    return from_hip(launch_forward_maps(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
+                                        ld_hist, plane_stride, edges, q, out, ld_out, maps,
+                                        (hipStream_t)stream));
+}
+
 tm_status tm_tonemap_forward_rgb(const float *v, int64_t ld_v, int32_t H, int32_t W,
                                  const void *sat, int64_t ld_sat, tm_sat_prec prec,
                                  const float *offsets, const uint32_t *hist_cum,

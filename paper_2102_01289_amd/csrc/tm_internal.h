@@ -158,6 +158,9 @@ struct FwdK {
     float *rgb_out;
     int64_t out_cs, out_ld;
     float saturation;
+    // per-field maps (Fig. 3), when not null: L_j at plane j, W_j at plane s + j (pitch W)
+    float *maps;
+    int64_t mstride;
 };
 constexpr int kQueryRows = 4;   // a query block covers 64 columns x 4 rows
 // Blocks of one image's fused query (the comb schedule may include idle blocks).
@@ -172,6 +175,13 @@ FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int6
                 const float *offsets, const uint32_t *hist, int64_t ld_hist,
                 int64_t plane_stride, const float *edges, const QueryParams &p, float *out,
                 int64_t ld_out);
+// The fused query that also writes the per-field tone values L_j (Eq. 2) and weights W_j
+// (Eq. 4): maps holds 2s planes of H*W (plane stride H*W, pitch W).
+hipError_t launch_forward_maps(const float *v, int64_t ld_v, int H, int W, const void *sat,
+                               int64_t ld_sat, int prec, const float *offsets,
+                               const uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
+                               const float *edges, const QueryParams &p, float *out,
+                               int64_t ld_out, float *maps, hipStream_t s);
 // The fused query followed by colour restoration (Eq. 12): c_out = (c_in / v)^sat L for
 // c = R, G, B (the ratio taken as 1 where v = 0, inputs clamped at 0); out may be null.
 hipError_t launch_forward_rgb(const float *v, int64_t ld_v, int H, int W, const void *sat_tab,

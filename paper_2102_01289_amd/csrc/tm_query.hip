@@ -157,7 +157,14 @@ __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float
             }
             const float Pj = (float)c * (float)inv_n;
             const float Lj = __builtin_fmaf(ldr, Pj, k.p.ld_min);
-            const float Wj = var * __builtin_amdgcn_rcpf(var + k.p.eps);
+            // Eq. 4 with the hardware reciprocal, held in [0, 1] (the reciprocal's last-bit
+            // error could otherwise lift W_j of a very large variance one ulp above 1)
+            const float Wj = fminf(var * __builtin_amdgcn_rcpf(var + k.p.eps), 1.f);
+            if (k.maps) {
+                TM_GLOBAL float *mp = gptr(k.maps) + (int64_t)y * k.W + x;
+                __builtin_nontemporal_store(Lj, mp + (int64_t)j * k.mstride);
+                __builtin_nontemporal_store(Wj, mp + (int64_t)(s + j) * k.mstride);
+            }
             num = __builtin_fmaf(Wj, Lj, num);
             den += Wj;
             lsum += Lj;
@@ -300,6 +307,8 @@ FwdK make_fwdk(const float *v, int64_t ld_v, int H, int W, const void *sat, int6
     k.rgb_out = nullptr;
     k.out_cs = k.out_ld = 0;
     k.saturation = 0.f;
+    k.maps = nullptr;
+    k.mstride = 0;
     comb_params(H, kRows, p.ry, p.n_scales, &k.p4, &k.teeth);
     return k;
 }
@@ -326,6 +335,19 @@ bool hist_offsets_fit_32(const FwdK &k) {
     if (!k.hist || k.p.n_bins < 2) return true;
     const int64_t last = (int64_t)(k.p.n_bins - 2) * k.plane_stride + (int64_t)k.W + 1;
     return last * 4 < ((int64_t)1 << 32);
+}
+
+hipError_t launch_forward_maps(const float *v, int64_t ld_v, int H, int W, const void *sat,
+                               int64_t ld_sat, int prec, const float *offsets,
+                               const uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
+                               const float *edges, const QueryParams &p, float *out,
+                               int64_t ld_out, float *maps, hipStream_t s) {
+    FwdK k = make_fwdk(v, ld_v, H, W, sat, ld_sat, offsets, hist, ld_hist, plane_stride, edges,
+                       p, out, ld_out);
+    k.maps = maps;
+    k.mstride = (int64_t)H * W;
+    return hist_offsets_fit_32(k) ? launch_fwd<false, true>(k, prec, s)
+                                  : launch_fwd<false, false>(k, prec, s);
 }
 
 hipError_t launch_forward_rgb(const float *v, int64_t ld_v, int H, int W, const void *sat_tab,

@@ -240,3 +240,26 @@ def test_mirror_equivariance():
     _, L = _run_forward(rgb, p, "f64")
     _, Lf = _run_forward(rgb[:, :, ::-1].copy(), p, "f64")
     assert np.max(np.abs(Lf[:, ::-1] - L)) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["c32x2", "f64"])
+@pytest.mark.parametrize("H,W", [(256, 256), (37, 123), (1, 300)])
+def test_per_field_maps(prec, H, W):
+    # Fig. 3: the per-field tone values L_j (Eq. 2) and weights W_j (Eq. 4)
+    rgb = rgb_case(H, W, 8, -2.0, 4.0, seed=H + W)
+    lum = lum_ref(rgb)
+    e = edges_ref(lum, 5)
+    rx, ry = oracle.paper_radii(H, W, 5)
+    p = tm.make_params(5, 5, eps=0.1, H=H, W=W)
+    m = tm.ToneMapper(H, W, p, prec)
+    L_plain = m.run(to_dev(rgb)).clone()
+    L, maps = m.query_maps()
+    torch.cuda.synchronize()
+    assert torch.equal(L, L_plain)                    # the maps change no output bit
+    Lref, Lj, Wj, varj = oracle.forward(lum, e, rx, ry, 0.1, per_scale=True)
+    mp = maps.cpu().numpy().astype(np.float64)
+    # tone values: exact counts over the exact area, one FP32 division and one FMA
+    assert np.max(np.abs(mp[:5] - Lj)) <= 2e-7
+    # weights: W_j = var/(var + eps) moves by eps/(var + eps)^2 times the variance error
+    assert np.max(np.abs(mp[5:] - Wj)) <= 1e-4
+    assert np.all((mp[5:] >= 0) & (mp[5:] <= 1))
