@@ -50,11 +50,15 @@ struct Entry<kF64> {
     __device__ static T zero() { return make_double2(0.0, 0.0); }
 };
 
-// Load the lane's VEC consecutive pixels of row y (zeros outside the image).
+// Load the lane's VEC consecutive pixels of row y (zeros outside the image).  wide: the
+// whole tile lies inside the image and its rows are 16-byte aligned.  The choice is
+// tile-uniform, so the two forms are separate paths rather than one masked sequence (where
+// the element loads would have to wait for the vector load into the same registers).
 template <int VEC>
-__device__ __forceinline__ void load_row(const ScanK &k, int y, int xl, float (&v)[VEC]) {
+__device__ __forceinline__ void load_row(const ScanK &k, int y, int xl, bool wide,
+                                         float (&v)[VEC]) {
     const TM_GLOBAL float *row = gptr(k.v) + (int64_t)y * k.ld_v;
-    if (k.vec_load && (VEC % 4 == 0) && xl + VEC <= k.W) {
+    if ((VEC % 4 == 0) && wide) {
 #pragma unroll
         for (int i = 0; i < VEC; i += 4) {
             float4 t = *reinterpret_cast<const TM_GLOBAL float4 *>(row + xl + i);
@@ -106,7 +110,8 @@ struct RowIn {
 };
 
 template <int VEC, bool ADJ, bool OUT_V = ADJ>
-__device__ __forceinline__ void load_in(const ScanK &k, int y, int xl, RowIn<VEC, ADJ> &r) {
+__device__ __forceinline__ void load_in(const ScanK &k, int y, int xl, bool wide,
+                                        RowIn<VEC, ADJ> &r) {
     if constexpr (ADJ) {
         const TM_GLOBAL double2 *row = gptr(k.dsrc) + (int64_t)y * k.ld_d;
         const TM_GLOBAL float *vr = gptr(k.v) + (int64_t)(k.H - 1 - y) * k.ld_v;
@@ -117,7 +122,7 @@ __device__ __forceinline__ void load_in(const ScanK &k, int y, int xl, RowIn<VEC
             if (OUT_V) r.v[i] = in ? vr[k.W - 1 - (xl + i)] : 0.f;
         }
     } else {
-        load_row<VEC>(k, y, xl, r.v);
+        load_row<VEC>(k, y, xl, wide, r.v);
     }
 }
 
@@ -166,10 +171,28 @@ __device__ __forceinline__ void store_counts(TM_GLOBAL uint32_t *out, int xl, in
 }
 
 // ================================================================ stage 1
+// Rows are processed in groups of G; the loads of the next group are issued before the
+// current group is processed, so a tile waits for memory once per group rather than once per
+// row (the wave scans and stores of a row do not depend on the next rows).  The adjoint's rows
+// are 64 bytes per lane, so it keeps two in flight.
+template <int VEC, bool ADJ, bool THIRD>
+__host__ __device__ constexpr int row_group() {
+    return ADJ ? 2 : (VEC >= 8 || THIRD ? 4 : 8);
+}
+
+template <int G, int VEC, bool ADJ, bool OUT_V>
+__device__ __forceinline__ void load_group(const ScanK &k, int y, int n, int xl, bool wide,
+                                           RowIn<VEC, ADJ> (&b)[G]) {
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+        if (u < n) load_in<VEC, ADJ, OUT_V>(k, y + u, xl, wide, b[u]);
+}
+
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
 __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
     using A = Acc<P>;
     using T = typename A::T;
+    constexpr int G = row_group<VEC, ADJ, false>();
     const int ty = tile / k.tiles_x, tx = tile % k.tiles_x;
     const int lane = lane_id();
     const int TW = kWave * VEC;
@@ -177,6 +200,7 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
     const int rows = min(k.th, k.H - y0);
     const int xl = x0 + lane * VEC;
     const int nchunks = HIST ? (k.n_planes + CHUNK - 1) / CHUNK : 0;
+    const bool wide = k.vec_load && x0 + TW <= k.W;
 
     for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
         const bool do_sat = SAT && ch == 0;
@@ -198,59 +222,79 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
             for (int i = 0; i < VEC; ++i) cc[c][i] = 0u;
         }
 
-        RowIn<VEC, ADJ> nxt;
-        if (rows > 0) load_in<VEC, ADJ, false>(k, y0, xl, nxt);
-        for (int r = 0; r < rows; ++r) {
-            const int y = y0 + r;
-            const RowIn<VEC, ADJ> cur = nxt;
-            if (r + 1 < rows) load_in<VEC, ADJ, false>(k, y + 1, xl, nxt);
-            const float(&v)[VEC] = cur.v;
-            if (do_sat) {
-                T s1 = A::zero(), s2 = A::zero();
-                T q1[VEC], q2[VEC];
-                sat_terms<P, VEC, ADJ>(k, xl, cur, mu1, mu2, q1, q2);
+        RowIn<VEC, ADJ> nb[G];
+        load_group<G, VEC, ADJ, false>(k, y0, rows, xl, wide, nb);
+        for (int r0 = 0; r0 < rows; r0 += G) {
+            const int n = min(G, rows - r0);
+            RowIn<VEC, ADJ> cb[G];
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    c1[i] = A::add(c1[i], q1[i]);
-                    c2[i] = A::add(c2[i], q2[i]);
-                    s1 = A::add(s1, q1[i]);
-                    s2 = A::add(s2, q2[i]);
-                }
-                s1 = wave_sum<A>(s1);
-                s2 = wave_sum<A>(s2);
-                t1 = A::add(t1, s1);
-                t2 = A::add(t2, s2);
-                if (lane == 0) {
-                    TM_GLOBAL T *rs = reinterpret_cast<TM_GLOBAL T *>(gptr(k.rs_sat));
-                    rs[(int64_t)y * k.tiles_x + tx] = s1;
-                    rs[((int64_t)k.H + y) * k.tiles_x + tx] = s2;
-                }
-            }
-            if (do_h) {
-                uint32_t lc[CHUNK];
+            for (int u = 0; u < G; ++u) cb[u] = nb[u];
+            if (r0 + G < rows)
+                load_group<G, VEC, ADJ, false>(k, y0 + r0 + G, rows - r0 - G, xl, wide, nb);
+            // lane u keeps the totals of the group's row u; they are stored after the group
+            T k1 = A::zero(), k2 = A::zero();
+            uint32_t kh[CHUNK];
 #pragma unroll
-                for (int c = 0; c < CHUNK; ++c) {
-                    lc[c] = 0u;
+            for (int c = 0; c < CHUNK; ++c) kh[c] = 0u;
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                if (u >= n) break;
+                const float(&v)[VEC] = cb[u].v;
+                if (do_sat) {
+                    T s1 = A::zero(), s2 = A::zero();
+                    T q1[VEC], q2[VEC];
+                    sat_terms<P, VEC, ADJ>(k, xl, cb[u], mu1, mu2, q1, q2);
 #pragma unroll
                     for (int i = 0; i < VEC; ++i) {
-                        const uint32_t b = ind(v[i], pe.lo[c], pe.hi[c], xl + i < k.W);
-                        cc[c][i] += b;
-                        lc[c] += b;
+                        c1[i] = A::add(c1[i], q1[i]);
+                        c2[i] = A::add(c2[i], q2[i]);
+                        s1 = A::add(s1, q1[i]);
+                        s2 = A::add(s2, q2[i]);
+                    }
+                    s1 = wave_sum<A>(s1);
+                    s2 = wave_sum<A>(s2);
+                    t1 = A::add(t1, s1);
+                    t2 = A::add(t2, s2);
+                    if (lane == u) { k1 = s1; k2 = s2; }
+                }
+                if (do_h) {
+                    uint32_t lc[CHUNK];
+#pragma unroll
+                    for (int c = 0; c < CHUNK; ++c) {
+                        lc[c] = 0u;
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) {
+                            const uint32_t b = ind(v[i], pe.lo[c], pe.hi[c], xl + i < k.W);
+                            cc[c][i] += b;
+                            lc[c] += b;
+                        }
+                    }
+                    // row totals <= 64*VEC < 2^16: two planes per 32-bit lane value
+#pragma unroll
+                    for (int c = 0; c < CHUNK; c += 2) {
+                        const uint32_t pk = lc[c] | (c + 1 < CHUNK ? lc[c + 1] << 16 : 0u);
+                        const uint32_t s = wave_sum<AddU32>(pk);
+                        const uint32_t a = s & 0xffffu, b = s >> 16;
+                        tc[c] += a;
+                        if (c + 1 < CHUNK) tc[c + 1] += b;
+                        if (lane == u) {
+                            kh[c] = a;
+                            if (c + 1 < CHUNK) kh[c + 1] = b;
+                        }
                     }
                 }
-                // row totals <= 64*VEC < 2^16: two planes per 32-bit lane value
+            }
+            if (lane < n) {
+                const int64_t y = y0 + r0 + lane;
+                if (do_sat) {
+                    TM_GLOBAL T *rs = reinterpret_cast<TM_GLOBAL T *>(gptr(k.rs_sat));
+                    rs[y * k.tiles_x + tx] = k1;
+                    rs[((int64_t)k.H + y) * k.tiles_x + tx] = k2;
+                }
+                if (do_h) {
 #pragma unroll
-                for (int c = 0; c < CHUNK; c += 2) {
-                    const uint32_t pk = lc[c] | (c + 1 < CHUNK ? lc[c + 1] << 16 : 0u);
-                    const uint32_t s = wave_sum<AddU32>(pk);
-                    const uint32_t a = s & 0xffffu, b = s >> 16;
-                    tc[c] += a;
-                    if (c + 1 < CHUNK) tc[c + 1] += b;
-                    if (lane == 0) {
-                        if (c < pe.np) gptr(k.rs_h)[((int64_t)(p0 + c) * k.H + y) * k.tiles_x + tx] = a;
-                        if (c + 1 < pe.np)
-                            gptr(k.rs_h)[((int64_t)(p0 + c + 1) * k.H + y) * k.tiles_x + tx] = b;
-                    }
+                    for (int c = 0; c < CHUNK; ++c)
+                        if (c < pe.np) gptr(k.rs_h)[((int64_t)(p0 + c) * k.H + y) * k.tiles_x + tx] = kh[c];
                 }
             }
         }
@@ -375,24 +419,95 @@ __device__ __forceinline__ void stage2_item(const ScanK &k, int64_t idx) {
 }
 
 // ================================================================ stage 3
-// Column carry at the top of the tile for the lane's VEC columns:
-//   sum_{ty'<ty} TTE[ty'][tx] + inclusive prefix over the tile of CSE[ty][.].
-template <class A, int VEC, class T>
-__device__ __forceinline__ void top_carry(const T *tte, const T *cse, int ty, int tx, int tiles_x,
-                                          int W, int xl, T (&col)[VEC]) {
-    T acc = A::zero();
-    for (int t = lane_id(); t < ty; t += kWave) acc = A::add(acc, tte[(int64_t)t * tiles_x + tx]);
-    const T above = wave_sum<A>(acc);
+// Column carries at the top of the tile for the lane's VEC columns, for every quantity of
+// the pass:  sum_{ty'<ty} TTE[ty'][tx] + inclusive prefix over the tile of CSE[ty][.].
+// All loads are issued before the first sum (one memory round trip per 256 tile rows above,
+// not one per quantity and 64 rows); each lane sums the rows t = lane (mod 64) in ascending
+// order, then the wave adds the lanes' sums.
+// col = (sum over the wave of above_lane) + (sum of e over the lanes to the left) +
+// (inclusive prefix of the lane's own e).
+template <class O, int VEC, class T>
+__device__ __forceinline__ void carry_finish(T above_lane, const T (&e)[VEC], T (&col)[VEC]) {
+    const T above = wave_sum<O>(above_lane);
     T p[VEC];
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-        T c = (xl + i < W) ? cse[xl + i] : A::zero();
-        p[i] = i ? A::add(p[i - 1], c) : c;
-    }
-    T ex = wave_shr1(wave_inclusive<A>(p[VEC - 1]));
-    T base = A::add(above, ex);
+    for (int i = 0; i < VEC; ++i) p[i] = i ? O::add(p[i - 1], e[i]) : e[i];
+    const T ex = wave_shr1(wave_inclusive<O>(p[VEC - 1]));
+    const T base = O::add(above, ex);
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) col[i] = A::add(base, p[i]);
+    for (int i = 0; i < VEC; ++i) col[i] = O::add(base, p[i]);
+}
+
+template <class A, int VEC, int CHUNK, class T>
+__device__ __forceinline__ void tile_carries(const ScanK &k, bool do_sat, bool do_h, int p0,
+                                             int np, int ty, int tx, int xl, T (&c1)[VEC],
+                                             T (&c2)[VEC], uint32_t (&cc)[CHUNK][VEC]) {
+    const int lane = lane_id();
+    const int64_t ntt = (int64_t)k.tiles_y * k.tiles_x;
+    const T *tte = reinterpret_cast<const T *>(k.tte_sat);
+    const T *cse = reinterpret_cast<const T *>(k.cse_sat);
+    // the tile row's column sums above it
+    T e1[VEC], e2[VEC];
+    uint32_t eh[CHUNK][VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+        const bool in = xl + i < k.W;
+        e1[i] = A::zero();
+        e2[i] = A::zero();
+        if (do_sat && in) {
+            const T a = cse[(int64_t)ty * k.W + xl + i];
+            const T b = cse[((int64_t)k.tiles_y + ty) * k.W + xl + i];
+            e1[i] = a;
+            e2[i] = b;
+        }
+#pragma unroll
+        for (int c = 0; c < CHUNK; ++c)
+            eh[c][i] = (do_h && in && c < np)
+                           ? k.cse_h[((int64_t)(p0 + c) * k.tiles_y + ty) * k.W + xl + i]
+                           : 0u;
+    }
+    // the tiles above, in this tile column
+    T a1 = A::zero(), a2 = A::zero();
+    uint32_t ah[CHUNK];
+#pragma unroll
+    for (int c = 0; c < CHUNK; ++c) ah[c] = 0u;
+    for (int t0 = 0; t0 < ty; t0 += 4 * kWave) {
+        T l1[4], l2[4];
+        uint32_t lh[4][CHUNK];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * kWave + lane;
+            const int64_t o = (int64_t)t * k.tiles_x + tx;
+            l1[u] = A::zero();
+            l2[u] = A::zero();
+            if (do_sat && t < ty) {
+                const T a = tte[o];
+                const T b = tte[ntt + o];
+                l1[u] = a;
+                l2[u] = b;
+            }
+#pragma unroll
+            for (int c = 0; c < CHUNK; ++c)
+                lh[u][c] = (do_h && t < ty && c < np) ? k.tte_h[(int64_t)(p0 + c) * ntt + o] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (t0 + u * kWave + lane < ty) {
+                a1 = A::add(a1, l1[u]);
+                a2 = A::add(a2, l2[u]);
+#pragma unroll
+                for (int c = 0; c < CHUNK; ++c) ah[c] += lh[u][c];
+            }
+        }
+    }
+    if (do_sat) {
+        carry_finish<A, VEC>(a1, e1, c1);
+        carry_finish<A, VEC>(a2, e2, c2);
+    }
+    if (do_h) {
+#pragma unroll
+        for (int c = 0; c < CHUNK; ++c) carry_finish<AddU32, VEC>(ah[c], eh[c], cc[c]);
+    }
 }
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
@@ -420,104 +535,121 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
         PlaneEdges<CHUNK> pe;
         if (do_h) pe = chunk_edges<CHUNK>(k, p0);
 
-        // the tile's first row is requested before the carries, so both loads are in flight
-        RowIn<VEC, ADJ> nxt;
-        if (rows > 0) load_in<VEC, ADJ>(k, y0, xl, nxt);
-        T c1[VEC], c2[VEC];
-        uint32_t cc[CHUNK][VEC];
-        if (do_sat) {
-            const T *tte = reinterpret_cast<const T *>(k.tte_sat);
-            const T *cse = reinterpret_cast<const T *>(k.cse_sat);
-            top_carry<A, VEC>(tte, cse + (int64_t)ty * k.W, ty, tx, k.tiles_x, k.W, xl, c1);
-            top_carry<A, VEC>(tte + (int64_t)k.tiles_y * k.tiles_x,
-                              cse + ((int64_t)k.tiles_y + ty) * k.W, ty, tx, k.tiles_x, k.W, xl, c2);
-        }
-        if (do_h) {
-#pragma unroll
-            for (int c = 0; c < CHUNK; ++c) {
-                const int64_t q = c < pe.np ? p0 + c : p0;
-                top_carry<AddU32, VEC>(k.tte_h + q * k.tiles_y * k.tiles_x,
-                                       k.cse_h + (q * k.tiles_y + ty) * k.W, ty, tx, k.tiles_x,
-                                       k.W, xl, cc[c]);
-            }
-        }
-
-#pragma unroll 2
-        for (int r = 0; r < rows; ++r) {
-            const int y = y0 + r;
-            const RowIn<VEC, ADJ> cur = nxt;
-            if (r + 1 < rows) load_in<VEC, ADJ>(k, y + 1, xl, nxt);
-            const float(&v)[VEC] = cur.v;
+        // the tile's first rows (and their row carries) are requested before the column
+        // carries, so both are in flight together; lane u holds the row carries of the
+        // group's row u
+        constexpr int G = row_group<VEC, ADJ, true>();
+        RowIn<VEC, ADJ> nb[G];
+        T nx1 = A::zero(), nx2 = A::zero();
+        uint32_t nxh[CHUNK];
+        auto load_rows = [&](int r0) {
+            const int n = rows - r0;
+            load_group<G, VEC, ADJ, ADJ>(k, y0 + r0, n, xl, full && k.vec_load, nb);
+            const int64_t y = y0 + r0 + lane;
             if (do_sat) {
                 const TM_GLOBAL T *xc = reinterpret_cast<const TM_GLOBAL T *>(gptr(k.xc_sat));
-                const T xc1 = xc[(int64_t)y * k.tiles_x + tx];
-                const T xc2 = xc[((int64_t)k.H + y) * k.tiles_x + tx];
-                T p1[VEC], p2[VEC];
-                sat_terms<P, VEC, ADJ>(k, xl, cur, mu1, mu2, p1, p2);
-#pragma unroll
-                for (int i = 1; i < VEC; ++i) {
-                    p1[i] = A::add(p1[i - 1], p1[i]);
-                    p2[i] = A::add(p2[i - 1], p2[i]);
-                }
-                const T b1 = A::add(xc1, wave_shr1(wave_inclusive<A>(p1[VEC - 1])));
-                const T b2 = A::add(xc2, wave_shr1(wave_inclusive<A>(p2[VEC - 1])));
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    c1[i] = A::add(c1[i], A::add(b1, p1[i]));
-                    c2[i] = A::add(c2[i], A::add(b2, p2[i]));
-                }
-                if constexpr (ADJ) {
-                    // virtual (x', y) is pixel (W-1-x', H-1-y): dv = s1 + 2 v s2
-                    const int yo = k.H - 1 - y;
-                    TM_GLOBAL float *gr = gptr(k.gv) + (int64_t)yo * k.ld_gv;
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) {
-                        const int xo = k.W - 1 - (xl + i);
-                        if (xo >= 0) gr[xo] = (float)(c1[i] + 2.0 * (double)cur.v[i] * c2[i]);
-                    }
-                } else {
-                    TM_GLOBAL ET *out = reinterpret_cast<TM_GLOBAL ET *>(gptr(k.sat)) + (int64_t)y * k.ld_sat;
-                    if (full) {
-#pragma unroll
-                        for (int i = 0; i < VEC; ++i) out[xl + i] = E::make(c1[i], c2[i]);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < VEC; ++i)
-                            if (xl + i < k.W) out[xl + i] = E::make(c1[i], c2[i]);
-                    }
+                nx1 = A::zero();
+                nx2 = A::zero();
+                if (lane < n) {
+                    const T a = xc[y * k.tiles_x + tx];
+                    const T b = xc[((int64_t)k.H + y) * k.tiles_x + tx];
+                    nx1 = a;
+                    nx2 = b;
                 }
             }
             if (do_h) {
 #pragma unroll
-                for (int c = 0; c < CHUNK; c += 2) {
-                    uint32_t pa[VEC], pb[VEC];
+                for (int c = 0; c < CHUNK; ++c)
+                    nxh[c] = (lane < n && c < pe.np)
+                                 ? gptr(k.xc_h)[((int64_t)(p0 + c) * k.H + y) * k.tiles_x + tx]
+                                 : 0u;
+            }
+        };
+        if (rows > 0) load_rows(0);
+        T c1[VEC], c2[VEC];
+        uint32_t cc[CHUNK][VEC];
+        tile_carries<A, VEC, CHUNK>(k, do_sat, do_h, p0, do_h ? pe.np : 0, ty, tx, xl, c1, c2, cc);
+
+        for (int r0 = 0; r0 < rows; r0 += G) {
+            const int n = min(G, rows - r0);
+            RowIn<VEC, ADJ> cb[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) cb[u] = nb[u];
+            const T gx1 = nx1, gx2 = nx2;
+            uint32_t gxh[CHUNK];
+#pragma unroll
+            for (int c = 0; c < CHUNK; ++c) gxh[c] = nxh[c];
+            if (r0 + G < rows) load_rows(r0 + G);
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                if (u >= n) break;
+                const int y = y0 + r0 + u;
+                const RowIn<VEC, ADJ> &cur = cb[u];
+                const float(&v)[VEC] = cur.v;
+                if (do_sat) {
+                    const T xc1 = readlane(gx1, u);
+                    const T xc2 = readlane(gx2, u);
+                    T p1[VEC], p2[VEC];
+                    sat_terms<P, VEC, ADJ>(k, xl, cur, mu1, mu2, p1, p2);
+#pragma unroll
+                    for (int i = 1; i < VEC; ++i) {
+                        p1[i] = A::add(p1[i - 1], p1[i]);
+                        p2[i] = A::add(p2[i - 1], p2[i]);
+                    }
+                    const T b1 = A::add(xc1, wave_shr1(wave_inclusive<A>(p1[VEC - 1])));
+                    const T b2 = A::add(xc2, wave_shr1(wave_inclusive<A>(p2[VEC - 1])));
 #pragma unroll
                     for (int i = 0; i < VEC; ++i) {
-                        const bool in = xl + i < k.W;
-                        const uint32_t a = ind(v[i], pe.lo[c], pe.hi[c], in);
-                        const uint32_t b = (c + 1 < CHUNK) ? ind(v[i], pe.lo[c + 1], pe.hi[c + 1], in) : 0u;
-                        pa[i] = i ? pa[i - 1] + a : a;
-                        pb[i] = i ? pb[i - 1] + b : b;
+                        c1[i] = A::add(c1[i], A::add(b1, p1[i]));
+                        c2[i] = A::add(c2[i], A::add(b2, p2[i]));
                     }
-                    // lane-exclusive prefix of both planes packed in 16-bit halves (<= 64*VEC)
-                    const uint32_t pk = pa[VEC - 1] | (pb[VEC - 1] << 16);
-                    const uint32_t ex = wave_shr1(wave_inclusive<AddU32>(pk));
-                    const uint32_t exa = ex & 0xffffu, exb = ex >> 16;
-                    {
-                        const int64_t q = p0 + c;
+                    if constexpr (ADJ) {
+                        // virtual (x', y) is pixel (W-1-x', H-1-y): dv = s1 + 2 v s2
+                        const int yo = k.H - 1 - y;
+                        TM_GLOBAL float *gr = gptr(k.gv) + (int64_t)yo * k.ld_gv;
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) {
+                            const int xo = k.W - 1 - (xl + i);
+                            if (xo >= 0) gr[xo] = (float)(c1[i] + 2.0 * (double)cur.v[i] * c2[i]);
+                        }
+                    } else {
+                        TM_GLOBAL ET *out = reinterpret_cast<TM_GLOBAL ET *>(gptr(k.sat)) + (int64_t)y * k.ld_sat;
+                        if (full) {
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i) out[xl + i] = E::make(c1[i], c2[i]);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i)
+                                if (xl + i < k.W) out[xl + i] = E::make(c1[i], c2[i]);
+                        }
+                    }
+                }
+                if (do_h) {
+#pragma unroll
+                    for (int c = 0; c < CHUNK; c += 2) {
+                        uint32_t pa[VEC], pb[VEC];
+#pragma unroll
+                        for (int i = 0; i < VEC; ++i) {
+                            const bool in = xl + i < k.W;
+                            const uint32_t a = ind(v[i], pe.lo[c], pe.hi[c], in);
+                            const uint32_t b = (c + 1 < CHUNK) ? ind(v[i], pe.lo[c + 1], pe.hi[c + 1], in) : 0u;
+                            pa[i] = i ? pa[i - 1] + a : a;
+                            pb[i] = i ? pb[i - 1] + b : b;
+                        }
+                        // lane-exclusive prefix of both planes packed in 16-bit halves (<= 64*VEC)
+                        const uint32_t pk = pa[VEC - 1] | (pb[VEC - 1] << 16);
+                        const uint32_t ex = wave_shr1(wave_inclusive<AddU32>(pk));
+                        const uint32_t exa = ex & 0xffffu, exb = ex >> 16;
                         if (c < pe.np) {
-                            const uint32_t xc = gptr(k.xc_h)[(q * k.H + y) * k.tiles_x + tx];
-                            TM_GLOBAL uint32_t *out = gptr(k.hist) + q * k.plane_stride + (int64_t)y * k.ld_hist;
+                            const uint32_t xc = readlane(gxh[c], u);
+                            TM_GLOBAL uint32_t *out = gptr(k.hist) + (int64_t)(p0 + c) * k.plane_stride + (int64_t)y * k.ld_hist;
 #pragma unroll
                             for (int i = 0; i < VEC; ++i) cc[c][i] += xc + exa + pa[i];
                             store_counts<VEC>(out, xl, k.W, full, cc[c]);
                         }
-                    }
-                    if (c + 1 < CHUNK) {
-                        const int64_t q = p0 + c + 1;
-                        if (c + 1 < pe.np) {
-                            const uint32_t xc = gptr(k.xc_h)[(q * k.H + y) * k.tiles_x + tx];
-                            TM_GLOBAL uint32_t *out = gptr(k.hist) + q * k.plane_stride + (int64_t)y * k.ld_hist;
+                        if (c + 1 < CHUNK && c + 1 < pe.np) {
+                            const uint32_t xc = readlane(gxh[c + 1], u);
+                            TM_GLOBAL uint32_t *out = gptr(k.hist) + (int64_t)(p0 + c + 1) * k.plane_stride + (int64_t)y * k.ld_hist;
 #pragma unroll
                             for (int i = 0; i < VEC; ++i) cc[c + 1][i] += xc + exb + pb[i];
                             store_counts<VEC>(out, xl, k.W, full, cc[c + 1]);
