@@ -170,6 +170,33 @@ __device__ __forceinline__ void store_counts(TM_GLOBAL uint32_t *out, int xl, in
     }
 }
 
+// LDS accesses of one wave happen in issue order; this keeps the compiler from moving the
+// staging writes and reads of a row across each other.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Store a lane's VEC consecutive integral-image entries of one full-width row.  A lane owns
+// VEC consecutive columns, so a direct store instruction would write every VEC-th entry; the
+// row is staged through the wave's LDS slice instead and written back so that each store
+// instruction covers 64 consecutive entries.
+template <int VEC, typename ET>
+__device__ __forceinline__ void store_entries_full(TM_GLOBAL ET *out, int x0, int lane,
+                                                   const ET (&e)[VEC], ET *st) {
+    if constexpr (VEC == 1) {
+        out[x0 + lane] = e[0];
+    } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) st[lane * VEC + i] = e[i];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) out[x0 + i * kWave + lane] = st[i * kWave + lane];
+        wave_lds_sync();
+    }
+}
+
 // ================================================================ stage 1
 // Rows are processed in groups of G; the loads of the next group are issued before the
 // current group is processed, so a tile waits for memory once per group rather than once per
@@ -525,6 +552,8 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
     const int nchunks = HIST ? (k.n_planes + CHUNK - 1) / CHUNK : 0;
     const bool last_tx = tx == k.tiles_x - 1;
     const bool full = x0 + TW <= k.W;   // tile-uniform: every lane's columns are in the image
+    // each wave's staging slice for the entry stores of one row
+    __shared__ ET sh_stage[(ADJ || !SAT) ? 1 : kWavesPerBlock * kWave * VEC];
 
     for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
         const bool do_sat = SAT && ch == 0;
@@ -615,8 +644,11 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
                     } else {
                         TM_GLOBAL ET *out = reinterpret_cast<TM_GLOBAL ET *>(gptr(k.sat)) + (int64_t)y * k.ld_sat;
                         if (full) {
+                            ET e[VEC];
 #pragma unroll
-                            for (int i = 0; i < VEC; ++i) out[xl + i] = E::make(c1[i], c2[i]);
+                            for (int i = 0; i < VEC; ++i) e[i] = E::make(c1[i], c2[i]);
+                            store_entries_full<VEC, ET>(out, x0, lane, e,
+                                                        sh_stage + wave_id() * (kWave * VEC));
                         } else {
 #pragma unroll
                             for (int i = 0; i < VEC; ++i)
@@ -692,10 +724,27 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
 }
 
 // ---------------------------------------------------------------- single-image kernels
+// When one launch builds both the integral image and the histogram planes, every tile is
+// two work items on neighbouring waves of one block: its integral image and its planes.
+// Each wave then holds the state of one kind of table only (fewer registers, more waves in
+// flight), and the second read of the tile's luminance rows is served by the cache.
+constexpr bool kSplitItems = true;
+
+template <bool SAT, bool HIST>
+__host__ __device__ constexpr int items_per_tile() {
+    return (kSplitItems && SAT && HIST) ? 2 : 1;
+}
+
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
 __global__ void __launch_bounds__(kBlock) scan_stage1(ScanK k) {
-    const int tile = blockIdx.x * kWavesPerBlock + wave_id();
-    if (tile < k.tiles_x * k.tiles_y) stage1_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, tile);
+    const int item = blockIdx.x * kWavesPerBlock + wave_id();
+    if (item >= k.tiles_x * k.tiles_y * items_per_tile<SAT, HIST>()) return;
+    if constexpr (items_per_tile<SAT, HIST>() == 2) {
+        if (item & 1) stage1_tile<P, VEC, CHUNK, false, true, ADJ>(k, item >> 1);
+        else stage1_tile<P, VEC, CHUNK, true, false, ADJ>(k, item >> 1);
+    } else {
+        stage1_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, item);
+    }
 }
 
 template <int P, bool SAT>
@@ -706,8 +755,14 @@ __global__ void __launch_bounds__(kBlock) scan_stage2(ScanK k, int64_t items) {
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
 __global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
-    const int tile = blockIdx.x * kWavesPerBlock + wave_id();
-    if (tile < k.tiles_x * k.tiles_y) stage3_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, tile);
+    const int item = blockIdx.x * kWavesPerBlock + wave_id();
+    if (item >= k.tiles_x * k.tiles_y * items_per_tile<SAT, HIST>()) return;
+    if constexpr (items_per_tile<SAT, HIST>() == 2) {
+        if (item & 1) stage3_tile<P, VEC, CHUNK, false, true, ADJ>(k, item >> 1);
+        else stage3_tile<P, VEC, CHUNK, true, false, ADJ>(k, item >> 1);
+    } else {
+        stage3_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, item);
+    }
 }
 
 // ---------------------------------------------------------------- batched kernels
@@ -749,14 +804,14 @@ __global__ void __launch_bounds__(kBlock) scan_stage2_batch(const ScanK *__restr
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ = false>
 hipError_t run3(const ScanK &k, hipStream_t s) {
-    const int tiles = k.tiles_x * k.tiles_y;
-    const int grid = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int items = k.tiles_x * k.tiles_y * items_per_tile<SAT, HIST>();
+    const int grid = (items + kWavesPerBlock - 1) / kWavesPerBlock;
     hipLaunchKernelGGL((scan_stage1<P, VEC, CHUNK, SAT, HIST, ADJ>), dim3(grid), dim3(kBlock), 0, s, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t items = scan_stage2_items(k, SAT);
-    hipLaunchKernelGGL((scan_stage2<P, SAT>), dim3((unsigned)((items + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, s, k, items);
+    const int64_t items2 = scan_stage2_items(k, SAT);
+    hipLaunchKernelGGL((scan_stage2<P, SAT>), dim3((unsigned)((items2 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, k, items2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((scan_stage3<P, VEC, CHUNK, SAT, HIST, ADJ>), dim3(grid), dim3(kBlock), 0, s, k);
