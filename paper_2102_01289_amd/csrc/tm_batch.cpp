@@ -202,7 +202,8 @@ size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int pre
         b->fk[i] = make_fwdk(lum, ld_lum, H, W, sat, ld, offsets, n > 1 ? hist : nullptr, ld,
                              elems, edges, qi, x.out, x.ld_out);
         b->parts[i + 1] = b->parts[i] + b->sk[i].nparts;
-        b->tiles[i + 1] = b->tiles[i] + (int64_t)sp.tiles_x * sp.tiles_y;
+        // scan work items: each tile is built as kFusedScanItems items
+        b->tiles[i + 1] = b->tiles[i] + (int64_t)kFusedScanItems * sp.tiles_x * sp.tiles_y;
         b->items[i + 1] = b->items[i] + scan_stage2_items(b->ck[i], true);
         b->qtiles[i + 1] = b->qtiles[i] + query_blocks(b->fk[i]);
     }

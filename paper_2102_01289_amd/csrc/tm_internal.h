@@ -109,6 +109,12 @@ ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws);
 
 // Integral image + cumulative histogram of images [0, count): three launches over flattened
 // work lists (device arrays: ks[count], tile_prefix[count+1], item_prefix[count+1]).
+// Work items per scan tile when one launch builds both the integral image and the histogram
+// planes: the tile's integral image and its planes go to neighbouring waves of one block, so
+// each wave holds the state of one kind of table only (fewer registers, more waves in
+// flight) and the second read of the tile's luminance rows is served by the cache.
+constexpr int kFusedScanItems = 2;
+
 struct BatchScan {
     const ScanK *ks;
     const int64_t *tile_prefix, *item_prefix;

@@ -109,12 +109,26 @@ struct RowIn {
     double2 d[ADJ ? VEC : 1];
 };
 
+// wide: table mode, the tile's columns are all in the image and its rows 16-byte aligned;
+// adjoint mode, the tile's columns are all in the image.  A wide adjoint row is loaded
+// entry-major (load i of lane l reads entry i*64 + l, so each load instruction covers 64
+// consecutive entries) and put into the scan's lane-major order by adj_lane_major.
 template <int VEC, bool ADJ, bool OUT_V = ADJ>
 __device__ __forceinline__ void load_in(const ScanK &k, int y, int xl, bool wide,
                                         RowIn<VEC, ADJ> &r) {
     if constexpr (ADJ) {
         const TM_GLOBAL double2 *row = gptr(k.dsrc) + (int64_t)y * k.ld_d;
         const TM_GLOBAL float *vr = gptr(k.v) + (int64_t)(k.H - 1 - y) * k.ld_v;
+        if (wide) {
+            const int lane = lane_id();
+            const int xe = xl - lane * VEC + lane;   // entry of load 0
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+                r.d[i] = row[xe + i * kWave];
+                if (OUT_V) r.v[i] = vr[k.W - 1 - (xe + i * kWave)];
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             const bool in = xl + i < k.W;
@@ -123,6 +137,35 @@ __device__ __forceinline__ void load_in(const ScanK &k, int y, int xl, bool wide
         }
     } else {
         load_row<VEC>(k, y, xl, wide, r.v);
+    }
+}
+
+// LDS accesses of one wave happen in issue order; this keeps the compiler from moving the
+// staging writes and reads of a row across each other.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Entry-major row (element i of lane l is entry i*64 + l) to lane-major (element i of lane l
+// is entry l*VEC + i), through the wave's LDS slice st of 64*VEC pairs.
+template <int VEC, bool OUT_V>
+__device__ __forceinline__ void adj_lane_major(RowIn<VEC, true> &r, double2 *st, int lane) {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) st[i * kWave + lane] = r.d[i];
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) r.d[i] = st[lane * VEC + i];
+    wave_lds_sync();
+    if constexpr (OUT_V) {
+        float *sv = reinterpret_cast<float *>(st);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) sv[i * kWave + lane] = r.v[i];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) r.v[i] = sv[lane * VEC + i];
+        wave_lds_sync();
     }
 }
 
@@ -168,14 +211,6 @@ __device__ __forceinline__ void store_counts(TM_GLOBAL uint32_t *out, int xl, in
         for (int i = 0; i < VEC; ++i)
             if (xl + i < W) out[xl + i] = c[i];
     }
-}
-
-// LDS accesses of one wave happen in issue order; this keeps the compiler from moving the
-// staging writes and reads of a row across each other.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Store a lane's VEC consecutive integral-image entries of one full-width row.  A lane owns
@@ -227,7 +262,9 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
     const int rows = min(k.th, k.H - y0);
     const int xl = x0 + lane * VEC;
     const int nchunks = HIST ? (k.n_planes + CHUNK - 1) / CHUNK : 0;
-    const bool wide = k.vec_load && x0 + TW <= k.W;
+    const bool full = x0 + TW <= k.W;   // tile-uniform
+    const bool wide = ADJ ? full : (k.vec_load && full);
+    __shared__ double2 sh_adj[ADJ ? kWavesPerBlock * kWave * VEC : 1];
 
     for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
         const bool do_sat = SAT && ch == 0;
@@ -266,6 +303,8 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
 #pragma unroll
             for (int u = 0; u < G; ++u) {
                 if (u >= n) break;
+                if constexpr (ADJ)
+                    if (wide) adj_lane_major<VEC, false>(cb[u], sh_adj + wave_id() * (kWave * VEC), lane);
                 const float(&v)[VEC] = cb[u].v;
                 if (do_sat) {
                     T s1 = A::zero(), s2 = A::zero();
@@ -554,6 +593,7 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
     const bool full = x0 + TW <= k.W;   // tile-uniform: every lane's columns are in the image
     // each wave's staging slice for the entry stores of one row
     __shared__ ET sh_stage[(ADJ || !SAT) ? 1 : kWavesPerBlock * kWave * VEC];
+    __shared__ double2 sh_adj[ADJ ? kWavesPerBlock * kWave * VEC : 1];
 
     for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
         const bool do_sat = SAT && ch == 0;
@@ -573,7 +613,7 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
         uint32_t nxh[CHUNK];
         auto load_rows = [&](int r0) {
             const int n = rows - r0;
-            load_group<G, VEC, ADJ, ADJ>(k, y0 + r0, n, xl, full && k.vec_load, nb);
+            load_group<G, VEC, ADJ, ADJ>(k, y0 + r0, n, xl, ADJ ? full : (full && k.vec_load), nb);
             const int64_t y = y0 + r0 + lane;
             if (do_sat) {
                 const TM_GLOBAL T *xc = reinterpret_cast<const TM_GLOBAL T *>(gptr(k.xc_sat));
@@ -613,6 +653,8 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
             for (int u = 0; u < G; ++u) {
                 if (u >= n) break;
                 const int y = y0 + r0 + u;
+                if constexpr (ADJ)
+                    if (full) adj_lane_major<VEC, true>(cb[u], sh_adj + wave_id() * (kWave * VEC), lane);
                 const RowIn<VEC, ADJ> &cur = cb[u];
                 const float(&v)[VEC] = cur.v;
                 if (do_sat) {
@@ -636,10 +678,23 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
                         // virtual (x', y) is pixel (W-1-x', H-1-y): dv = s1 + 2 v s2
                         const int yo = k.H - 1 - y;
                         TM_GLOBAL float *gr = gptr(k.gv) + (int64_t)yo * k.ld_gv;
+                        if (full) {
+                            // staged so that each store covers 64 consecutive outputs
+                            float *sv = reinterpret_cast<float *>(sh_adj + wave_id() * (kWave * VEC));
 #pragma unroll
-                        for (int i = 0; i < VEC; ++i) {
-                            const int xo = k.W - 1 - (xl + i);
-                            if (xo >= 0) gr[xo] = (float)(c1[i] + 2.0 * (double)cur.v[i] * c2[i]);
+                            for (int i = 0; i < VEC; ++i)
+                                sv[lane * VEC + i] = (float)(c1[i] + 2.0 * (double)cur.v[i] * c2[i]);
+                            wave_lds_sync();
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i)
+                                gr[k.W - 1 - (x0 + i * kWave + lane)] = sv[i * kWave + lane];
+                            wave_lds_sync();
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < VEC; ++i) {
+                                const int xo = k.W - 1 - (xl + i);
+                                if (xo >= 0) gr[xo] = (float)(c1[i] + 2.0 * (double)cur.v[i] * c2[i]);
+                            }
                         }
                     } else {
                         TM_GLOBAL ET *out = reinterpret_cast<TM_GLOBAL ET *>(gptr(k.sat)) + (int64_t)y * k.ld_sat;
@@ -724,15 +779,11 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
 }
 
 // ---------------------------------------------------------------- single-image kernels
-// When one launch builds both the integral image and the histogram planes, every tile is
-// two work items on neighbouring waves of one block: its integral image and its planes.
-// Each wave then holds the state of one kind of table only (fewer registers, more waves in
-// flight), and the second read of the tile's luminance rows is served by the cache.
-constexpr bool kSplitItems = true;
-
+// A launch that builds both the integral image and the histogram planes runs every tile as
+// kFusedScanItems work items (its integral image on an even wave, its planes on the next).
 template <bool SAT, bool HIST>
 __host__ __device__ constexpr int items_per_tile() {
-    return (kSplitItems && SAT && HIST) ? 2 : 1;
+    return (SAT && HIST) ? kFusedScanItems : 1;
 }
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
@@ -781,11 +832,20 @@ __global__ void __launch_bounds__(kBlock) scan_tiles_batch(const ScanK *__restri
     int i = g < total ? __builtin_amdgcn_readfirstlane(find_image(prefix, count, g)) : 0;
     for (; g < total; g += step) {
         while (g >= prefix[i + 1]) ++i;
-        const int tile = (int)(g - prefix[i]);
-        if (THIRD)
-            stage3_tile<P, VEC, CHUNK, SAT, HIST, false>(ks[i], tile);
-        else
-            stage1_tile<P, VEC, CHUNK, SAT, HIST, false>(ks[i], tile);
+        const int item = (int)(g - prefix[i]);
+        if constexpr (items_per_tile<SAT, HIST>() == 2) {
+            const int tile = item >> 1;
+            if (item & 1) {
+                if (THIRD) stage3_tile<P, VEC, CHUNK, false, true, false>(ks[i], tile);
+                else stage1_tile<P, VEC, CHUNK, false, true, false>(ks[i], tile);
+            } else {
+                if (THIRD) stage3_tile<P, VEC, CHUNK, true, false, false>(ks[i], tile);
+                else stage1_tile<P, VEC, CHUNK, true, false, false>(ks[i], tile);
+            }
+        } else {
+            if (THIRD) stage3_tile<P, VEC, CHUNK, SAT, HIST, false>(ks[i], item);
+            else stage1_tile<P, VEC, CHUNK, SAT, HIST, false>(ks[i], item);
+        }
     }
 }
 
