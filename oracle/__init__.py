@@ -9,8 +9,9 @@ Contents
     with integer arithmetic (Python's unbounded ints);
   * thin numpy wrappers around the plain C oracle (``tm_oracle.c``): luminance (Eq. 11),
     bins (Eq. 7), integral histogram (Eq. 8), integral images (Eq. 5), the forward method
-    (Eq. 1-4, 6, 9, 10) with integral tables or with direct window sums, the backward,
-    colour restoration (Eq. 12);
+    (Eq. 1-4, 6, 9, 10) with integral tables or with direct window sums -- with Eq. 10's
+    variance taken of the luminance or, as a variant, of its natural logarithm -- the
+    backward, colour restoration (Eq. 12);
   * ``paper_radii``: the receptive-field pyramid of Section II-C.
 The pure-Python brute force used to pin the C code lives in ``oracle.brute``.
 """
@@ -47,9 +48,9 @@ def lib() -> ctypes.CDLL:
         L.orc_bins.argtypes = [P, I64, P, I, P]
         L.orc_integral_histogram.argtypes = [P, I64, I64, I, I, P]
         L.orc_integral_image.argtypes = [P, I64, I64, I, P, P]
-        L.orc_forward.argtypes = [P, I64, I64, P, I, I, P, P, D, D, D, P, P, P, P]
+        L.orc_forward.argtypes = [P, I64, I64, P, I, I, P, P, D, D, D, I, P, P, P, P]
         L.orc_forward.restype = I
-        L.orc_forward_direct.argtypes = [P, I64, I64, P, I, I, P, P, D, D, D, P, I64, P]
+        L.orc_forward_direct.argtypes = [P, I64, I64, P, I, I, P, P, D, D, D, I, P, I64, P]
         L.orc_forward_direct.restype = I
         L.orc_backward.argtypes = [P, I64, I64, P, I, I, P, P, D, D, D, P, P, P]
         L.orc_backward.restype = I
@@ -179,9 +180,21 @@ def _radii(rx, ry):
     return rx, ry
 
 
-def forward(v, edges, rx, ry, eps=0.1, ldmin=0.0, ldmax=1.0, per_scale=False):
+VAR_DOMAINS = ("linear", "log")
+
+
+def _var_log(var_domain: str) -> int:
+    if var_domain not in VAR_DOMAINS:
+        raise ValueError(f"var_domain must be one of {VAR_DOMAINS}")
+    return int(var_domain == "log")
+
+
+def forward(v, edges, rx, ry, eps=0.1, ldmin=0.0, ldmax=1.0, per_scale=False,
+            var_domain="linear"):
     """Tone-mapped luminance L (float64 [H, W]) by Eq. 1-10 with integral tables.
-    With per_scale=True also returns (L_j, W_j, var_j), each float64 [s, H, W]."""
+    With per_scale=True also returns (L_j, W_j, var_j), each float64 [s, H, W].
+    var_domain="log": Eq. 10's window variance is that of l = ln(max(v, FLT_MIN)), in FP64,
+    instead of v itself (the bins still come from v)."""
     v = _c(v, np.float32)
     edges = _c(edges, np.float32)
     rx, ry = _radii(rx, ry)
@@ -192,13 +205,13 @@ def forward(v, edges, rx, ry, eps=0.1, ldmin=0.0, ldmax=1.0, per_scale=False):
     ptrs = [_ptr(e) for e in extra] if extra else [None, None, None]
     rc = lib().orc_forward(_ptr(v), H, W, _ptr(edges) if edges.size else None,
                            edges.size + 1, s, _ptr(rx), _ptr(ry), float(eps), float(ldmin),
-                           float(ldmax), _ptr(L), *ptrs)
+                           float(ldmax), _var_log(var_domain), _ptr(L), *ptrs)
     if rc != 0:
         raise MemoryError("oracle forward: allocation failed")
     return (L, *extra) if per_scale else L
 
 
-def forward_direct(v, edges, rx, ry, pix, eps=0.1, ldmin=0.0, ldmax=1.0):
+def forward_direct(v, edges, rx, ry, pix, eps=0.1, ldmin=0.0, ldmax=1.0, var_domain="linear"):
     """L at the flat pixel indices pix, with window histograms and sums taken directly."""
     v = _c(v, np.float32)
     edges = _c(edges, np.float32)
@@ -208,7 +221,8 @@ def forward_direct(v, edges, rx, ry, pix, eps=0.1, ldmin=0.0, ldmax=1.0):
     L = np.empty(pix.size, dtype=np.float64)
     rc = lib().orc_forward_direct(_ptr(v), H, W, _ptr(edges) if edges.size else None,
                                   edges.size + 1, rx.size, _ptr(rx), _ptr(ry), float(eps),
-                                  float(ldmin), float(ldmax), _ptr(pix), pix.size, _ptr(L))
+                                  float(ldmin), float(ldmax), _var_log(var_domain), _ptr(pix),
+                                  pix.size, _ptr(L))
     if rc != 0:
         raise MemoryError("oracle forward_direct: allocation failed")
     return L

@@ -7,6 +7,7 @@ going through any edge table.  Nothing here shares code with ``tm_oracle.c``.
 """
 from __future__ import annotations
 
+import math
 from fractions import Fraction
 
 import numpy as np
@@ -75,12 +76,18 @@ def window(x, y, W, H, rx, ry):
 
 
 def forward(v: np.ndarray, n: int, rx, ry, eps=0.1, ldmin=0.0, ldmax=1.0,
-            per_scale=False):
-    """Exact L (as Fractions, returned as float64) for a tiny float32 image v [H, W]."""
+            per_scale=False, var_domain="linear"):
+    """Exact L (as Fractions, returned as float64) for a tiny float32 image v [H, W].
+    var_domain="log": the window variance is taken of the FP64 natural logarithms
+    math.log(max(v, 2^-126)) (exact rational arithmetic from there on)."""
     H, W = v.shape
     vmin, vmax = float(v.min()), float(v.max())
     B = [[bin_of(v[y, x], vmin, vmax, n) for x in range(W)] for y in range(H)]
-    V = [[Fraction(float(v[y, x])) for x in range(W)] for y in range(H)]
+    if var_domain == "log":
+        V = [[Fraction(math.log(max(float(v[y, x]), float(FLT_MIN)))) for x in range(W)]
+             for y in range(H)]
+    else:
+        V = [[Fraction(float(v[y, x])) for x in range(W)] for y in range(H)]
     e = Fraction(float(eps))
     lo, hi = Fraction(float(ldmin)), Fraction(float(ldmax))
     s = len(rx)

@@ -16,6 +16,7 @@
  *   integral tables are (H+1) x (W+1): entry [y+1][x+1] holds the sum over x' <= x,
  *   y' <= y, and row 0 / column 0 are zero (the "x = -1" / "y = -1" corners).
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -292,8 +293,19 @@ static void tables_free(tables_t *t)
     memset(t, 0, sizeof(*t));
 }
 
+/* The image whose window variance Eq. 10 takes: the luminance itself (linear), or, with
+ * var_log set, its natural logarithm l = ln(max(v, FLT_MIN)) in FP64 (the log-domain
+ * alternative of Section II-A's "integral image of i and i^2"). */
+static double var_image_px(float v, int var_log)
+{
+    if (!var_log)
+        return (double)v;
+    const double m = (double)v > (double)FLT_MIN ? (double)v : (double)FLT_MIN;
+    return log(m);
+}
+
 static int tables_build(const float *v, int64_t H, int64_t W, const float *edges, int n,
-                        tables_t *t)
+                        int var_log, tables_t *t)
 {
     memset(t, 0, sizeof(*t));
     t->H = H; t->W = W; t->ld = W + 1; t->n = n;
@@ -310,11 +322,23 @@ static int tables_build(const float *v, int64_t H, int64_t W, const float *edges
     }
     orc_bins(v, H * W, edges, n, t->bins);
     orc_integral_histogram(t->bins, H, W, n, 0, t->hist);
-    orc_integral_image(v, H, W, 0, hi, lo);
-    for (int64_t i = 0; i < ps; ++i) { t->s1[i].hi = hi[i]; t->s1[i].lo = lo[i]; }
-    orc_integral_image(v, H, W, 1, hi, lo);
-    for (int64_t i = 0; i < ps; ++i) { t->s2[i].hi = hi[i]; t->s2[i].lo = lo[i]; }
+    if (!var_log) {
+        orc_integral_image(v, H, W, 0, hi, lo);
+        for (int64_t i = 0; i < ps; ++i) { t->s1[i].hi = hi[i]; t->s1[i].lo = lo[i]; }
+        orc_integral_image(v, H, W, 1, hi, lo);
+        for (int64_t i = 0; i < ps; ++i) { t->s2[i].hi = hi[i]; t->s2[i].lo = lo[i]; }
+        free(hi); free(lo);
+        return 0;
+    }
     free(hi); free(lo);
+    /* Eq. 5 of l and l^2, both in FP64, accumulated in double-double */
+    double *a = (double *)malloc((size_t)(H * W) * sizeof(double));
+    if (!a) { tables_free(t); return -1; }
+    for (int64_t i = 0; i < H * W; ++i) a[i] = var_image_px(v[i], 1);
+    sat_dd_f64(a, H, W, t->s1);
+    for (int64_t i = 0; i < H * W; ++i) a[i] = a[i] * a[i];
+    sat_dd_f64(a, H, W, t->s2);
+    free(a);
     return 0;
 }
 
@@ -340,14 +364,16 @@ static void pixel_scales(const tables_t *t, int64_t x, int64_t y, int s, const i
  * bins (Eq. 7), integral histogram (Eq. 8), integral images of v and v^2 (Eq. 5), then for
  * every pixel and every receptive field j: Eq. 9 histogram, Eq. 1 CDF, Eq. 2 tone value,
  * Eq. 6 sums, Eq. 10 variance, Eq. 4 weight; finally the Eq. 3 fusion.
+ * var_log: take Eq. 10's variance of l = ln(max(v, FLT_MIN)) instead of v (the bins are
+ * those of v either way).
  * Optional per-scale outputs (each s x H x W, nullable): Lj, Wj, varj.
  * Returns 0, or -1 if memory could not be allocated. */
 int orc_forward(const float *v, int64_t H, int64_t W, const float *edges, int n, int s,
                 const int32_t *rx, const int32_t *ry, double eps, double ldmin, double ldmax,
-                double *L, double *Lj, double *Wj, double *varj)
+                int var_log, double *L, double *Lj, double *Wj, double *varj)
 {
     tables_t t;
-    if (tables_build(v, H, W, edges, n, &t))
+    if (tables_build(v, H, W, edges, n, var_log, &t))
         return -1;
     scale_t sc[16];
     uint64_t *f = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
@@ -374,7 +400,7 @@ int orc_forward(const float *v, int64_t H, int64_t W, const float *edges, int n,
  * pix holds flat indices y*W + x. */
 int orc_forward_direct(const float *v, int64_t H, int64_t W, const float *edges, int n, int s,
                        const int32_t *rx, const int32_t *ry, double eps, double ldmin,
-                       double ldmax, const int64_t *pix, int64_t npix, double *L)
+                       double ldmax, int var_log, const int64_t *pix, int64_t npix, double *L)
 {
     uint64_t *f = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
     if (!f)
@@ -394,8 +420,9 @@ int orc_forward_direct(const float *v, int64_t H, int64_t W, const float *edges,
                     int32_t bb;
                     orc_bins(&vv, 1, edges, n, &bb);
                     f[bb] += 1;
-                    a1 = dd_add(a1, dd_from((double)vv));
-                    a2 = dd_add(a2, dd_from((double)vv * (double)vv));
+                    const double q = var_image_px(vv, var_log);
+                    a1 = dd_add(a1, dd_from(q));
+                    a2 = dd_add(a2, dd_from(q * q));
                 }
             double N = (double)((w.xp - w.xm) * (w.yp - w.ym));
             sc[j] = scale_terms(f, n, b, a1.hi + a1.lo, a2.hi + a2.lo, N, eps, ldmin, ldmax);
@@ -429,7 +456,7 @@ int orc_backward(const float *v, int64_t H, int64_t W, const float *edges, int n
                  const double *g, double *grad_v, double *grad_params)
 {
     tables_t t;
-    if (tables_build(v, H, W, edges, n, &t))
+    if (tables_build(v, H, W, edges, n, 0, &t))
         return -1;
     const int64_t np = H * W, ld = W + 1, ps = (H + 1) * (W + 1);
     double *A1 = (double *)malloc((size_t)s * (size_t)np * sizeof(double));

@@ -236,6 +236,66 @@ def test_power_of_two_covariance_is_bit_exact(orc):
         assert np.array_equal(L, Ls)
 
 
+# ------------------------------------------------------------- log-domain variance variant
+@pytest.mark.parametrize("H,W,n,rx,ry,seed", [
+    (5, 9, 3, [4, 2, 1], [2, 1, 0], 41),
+    (8, 8, 5, [4, 2, 1], [4, 2, 1], 42),
+    (6, 6, 64, [3, 1], [3, 1], 43),
+])
+def test_log_variance_matches_exact_brute_force(orc, H, W, n, rx, ry, seed):
+    v = _lum(orc, H, W, seed=seed, lo=-3, hi=5)
+    e = _edges(orc, v, n)
+    L, Ls, Ws, var = orc.forward(v, e, rx, ry, per_scale=True, var_domain="log")
+    Lb, Lsb, Wsb = brute.forward(v, n, rx, ry, per_scale=True, var_domain="log")
+    assert np.max(np.abs(L - Lb)) <= 1e-12
+    assert np.max(np.abs(Ls - Lsb)) <= 1e-15
+    assert np.max(np.abs(Ws - Wsb)) <= 1e-12
+    # the variant is a different method: the linear-domain weights differ
+    _, _, Wlin, _ = orc.forward(v, e, rx, ry, per_scale=True)
+    assert np.max(np.abs(Ws - Wlin)) > 1e-3
+
+
+def test_log_variance_equals_numpy_window_variance(orc):
+    # Eq. 10 of the log image, window by window with numpy (population variance)
+    v = _lum(orc, 11, 14, seed=44, lo=-3, hi=5)
+    rx, ry = [5, 2], [3, 1]
+    _, _, _, var = orc.forward(v, _edges(orc, v, 5), rx, ry, per_scale=True, var_domain="log")
+    lg = np.log(np.maximum(v.astype(np.float64), 2.0 ** -126))
+    for j in range(2):
+        for y in range(11):
+            for x in range(14):
+                win = lg[max(y - ry[j], 0):y + ry[j] + 1, max(x - rx[j], 0):x + rx[j] + 1]
+                assert abs(var[j, y, x] - max(np.var(win), 0.0)) <= 1e-12
+
+
+def test_log_variance_tables_equal_direct_windows(orc):
+    v = _lum(orc, 29, 41, K=6, seed=45, lo=-3, hi=5)
+    rx, ry = orc.paper_radii(29, 41, 5)
+    e = _edges(orc, v, 5)
+    L = orc.forward(v, e, rx, ry, var_domain="log")
+    Ld = orc.forward_direct(v, e, rx, ry, np.arange(v.size), var_domain="log")
+    assert np.max(np.abs(L.ravel() - Ld)) <= 1e-12
+
+
+def test_log_variance_is_scale_invariant(orc):
+    # scaling the luminance by 2^k moves the bin edges with it (the bins are unchanged)
+    # and shifts every log value by k ln 2, which leaves every window variance unchanged:
+    # the same eps gives the same L, while the linear variance needs eps * 4^k
+    v = _lum(orc, 16, 21, seed=46, lo=-3, hi=5)
+    rx, ry = orc.paper_radii(16, 21, 3)
+    L = orc.forward(v, _edges(orc, v, 5), rx, ry, 0.1, var_domain="log")
+    Llin = orc.forward(v, _edges(orc, v, 5), rx, ry, 0.1)
+    for k in (-3, 4):
+        vs = (v * np.float32(2.0 ** k)).astype(np.float32)
+        e = _edges(orc, vs, 5)
+        assert np.max(np.abs(orc.forward(vs, e, rx, ry, 0.1, var_domain="log") - L)) <= 1e-10
+        assert np.max(np.abs(orc.forward(vs, e, rx, ry, 0.1) - Llin)) > 1e-3
+    # a constant image has zero log variance: every L_j is min L_d
+    c = np.full((7, 9), 0.37, dtype=np.float32)
+    assert np.all(orc.forward(c, _edges(orc, c, 5), [3, 1], [3, 1], 0.1, 0.2, 0.9,
+                              var_domain="log") == 0.2)
+
+
 # ----------------------------------------------------------------------------- backward
 def test_box_filter_is_self_adjoint(orc):
     rng = np.random.default_rng(4)
