@@ -119,10 +119,30 @@ def bench_sweep(args):
                       "rows": rows}), flush=True)
 
 
+def _median_ms(fn, reps=10, warmup=2):
+    """Median over reps of one call of fn, timed with events on torch's current stream (the
+    stream the ToneMapper calls launch on)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return sorted(ts)[len(ts) // 2]
+
+
 def bench_precision(args):
     """Output error of each integral-image precision against the FP64 oracle on the whole
     image: the paper set at 4000x3000 (10^8:1) and the n = 64, radii {4, 16, 64} stress set
-    at 1920x1080."""
+    at 1920x1080; for the paper set also the log-domain variance variant against the
+    oracle's FP64 log-variance form.  Each variant's whole forward (prologue, tables, query)
+    is timed beside its error."""
     import numpy as np
     import torch
 
@@ -151,19 +171,29 @@ def bench_precision(args):
         case = {"workload": name, "n_bins": n, "radii_x": list(rx), "radii_y": list(ry),
                 "dynamic_range": float(lum.max() / lum.min()), "oracle_s": round(t_orc, 2),
                 "variants": {}}
-        for prec in ("f32", "c32x2", "f64"):
-            m = tm.ToneMapper(H, W, p, prec, device=dev)
-            L = m.run(torch.from_numpy(rgb).to(dev)).cpu().numpy().astype(np.float64)
+        refs = {"linear": ref}
+        variants = [(prec, "linear") for prec in ("f32", "c32x2", "f64")]
+        if radii is None:
+            refs["log"] = oracle.forward(lum, e, rx, ry, 0.1, var_domain="log")
+            variants += [(prec, "log") for prec in ("f32", "c32x2", "f64")]
+        x = torch.from_numpy(rgb).to(dev)
+        for prec, dom in variants:
+            m = tm.ToneMapper(H, W, p, prec, device=dev, variance=dom)
+            L = m.run(x).cpu().numpy().astype(np.float64)
             G = m.hist.padded()[..., 0].numpy().astype(np.uint64)
             exact = bool(np.array_equal(
                 G, oracle.integral_histogram(oracle.bins(lum, e), n, cumulative=True)))
-            err = np.abs(L - ref)
-            case["variants"][prec] = {
+            err = np.abs(L - refs[dom])
+            ms = _median_ms(lambda: m.run(x), reps=10)
+            key = prec if dom == "linear" else f"log_{prec}"
+            case["variants"][key] = {
                 "max_abs": float(err.max()), "p99_9": float(np.quantile(err, 0.999)),
                 "mean_abs": float(err.mean()), "frac_above_1_255": float(np.mean(err > 1 / 255)),
-                "histogram_bit_exact": exact}
+                "histogram_bit_exact": exact, "forward_ms": round(ms, 4),
+                "forward_mp_s": round(H * W / ms / 1e3, 1)}
             del m
-            print(f"bench: {name} {prec} max {err.max():.3e}", file=sys.stderr, flush=True)
+            print(f"bench: {name} {key} max {err.max():.3e} {ms:.3f} ms", file=sys.stderr,
+                  flush=True)
         out["cases"].append(case)
     print(json.dumps(out), flush=True)
 

@@ -151,6 +151,22 @@ tm_status tm_prologue(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32
                       int32_t W, int32_t n_bins, float *lum, int64_t ld_lum, float *edges,
                       float *offsets, float *minmax, void *ws, size_t ws_bytes, void *stream);
 
+/* Log-domain variance variant.  Section II-A builds the integral images "of i and i^2"
+ * (Eq. 5) for Eq. 10's window variance; the method is also defined with that variance taken
+ * of the logarithmic image l the bins are cut from.  This call writes
+ *   logv = ln(max(i, FLT_MIN))   (FP32, the device logf, within 2 ulp of the exact value)
+ * (H x W, pitch ld_log; must not overlap lum) and, in the same pass, the statistics of l:
+ * offsets[2] (device, nullable) = FP32-rounded means of l and l^2 (FP64 sums), the offsets a
+ * TM_SAT_C32X2 integral image of l needs, and minmax[2] (device, nullable) = {min l, max l}.
+ * The variant is then: tm_integral_image of logv with these offsets, the integral histogram
+ * of i as usual, and tm_tonemap_forward (or _maps, _rgb) given i itself (its bins decide
+ * Eq. 1) with the table and offsets of l; eps is then in units of l^2.  Forward only: the
+ * backward entry points take the variance of the image they are given.
+ * Deterministic.  Workspace: tm_image_stats_workspace_bytes. */
+tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t W, float *logv,
+                           int64_t ld_log, float *offsets, float *minmax, void *ws,
+                           size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------- stages a2, a3: tables */
 
 /* Integral images (Eq. 5) of v and v^2 in one interleaved table (entry type per

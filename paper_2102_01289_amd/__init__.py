@@ -190,6 +190,27 @@ def tm_image_stats(lum: torch.Tensor, n_bins: int, stream=None):
     return edges[:n_bins - 1], offsets, minmax
 
 
+def tm_log_luminance(lum: torch.Tensor, stream=None, out=None, offsets=None, minmax=None,
+                     ws=None):
+    """Log image l = ln(max(lum, FLT_MIN)) and its statistics: (l [H, W], offsets [2] =
+    FP32 means of l and l^2, minmax [2])."""
+    H, W, ld = _img(lum, "lum")
+    dev = lum.device
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    if offsets is None:
+        offsets = torch.empty(2, dtype=torch.float32, device=dev)
+    if minmax is None:
+        minmax = torch.empty(2, dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = _ws(_lib().tm_image_stats_workspace_bytes(H, W), dev)
+    _, _, ldo = _img(out, "out")
+    _ck("tm_log_luminance", _lib().tm_log_luminance(
+        _vp(lum), ld, H, W, _vp(out), ldo, _vp(offsets), _vp(minmax), _vp(ws), ws.numel(),
+        _stream(stream)))
+    return out, offsets, minmax
+
+
 def tm_prologue(rgb: torch.Tensor, n_bins: int, stream=None):
     """Eq. 11 and the image statistics in one pass: (lum, edges, offsets, minmax)."""
     _, H, W = rgb.shape
@@ -415,13 +436,22 @@ class Stage:
     out: torch.Tensor
 
 
+VARIANCE_DOMAINS = ("linear", "log")
+
+
 class ToneMapper:
     """Preallocated forward path for one image shape: prologue (Eq. 11 + statistics),
     integral tables (Eq. 5, 8), fused query (Eq. 1-4).  All buffers and workspaces are
-    allocated once so that run() only enqueues kernels (capturable in a HIP graph)."""
+    allocated once so that run() only enqueues kernels (capturable in a HIP graph).
+    variance="log": Eq. 10's window variance is that of the log image l = ln i (its
+    integral image is built from tm_log_luminance's plane; the bins still come from i);
+    forward only."""
 
     def __init__(self, H: int, W: int, params, prec: str = "c32x2", tune=None,
-                 device="cuda"):
+                 device="cuda", variance: str = "linear"):
+        if variance not in VARIANCE_DOMAINS:
+            raise ValueError(f"variance must be one of {VARIANCE_DOMAINS}")
+        self.variance = variance
         self.H, self.W, self.params, self.prec, self.tune = H, W, params, prec, tune
         n = params.n_bins
         dev = torch.device(device)
@@ -436,6 +466,13 @@ class ToneMapper:
         self.ws_tab = _ws(_lib().tm_tables_workspace_bytes(H, W, n, _capi.SAT_PREC[prec],
                                                             _tune_ref(tune)), dev)
         self.tune_ref = _tune_ref(tune)
+        # the integral image's offsets: those of the luminance, or of its log plane
+        self.sat_offsets = self.offsets
+        if variance == "log":
+            self.logv = torch.empty((H, W), dtype=torch.float32, device=dev)
+            self.log_offsets = torch.empty(2, dtype=torch.float32, device=dev)
+            self.log_minmax = torch.empty(2, dtype=torch.float32, device=dev)
+            self.sat_offsets = self.log_offsets
 
     def prologue(self, rgb, stream=None):
         _ck("tm_prologue", _lib().tm_prologue(
@@ -445,6 +482,19 @@ class ToneMapper:
 
     def tables(self, stream=None):
         h = self.hist
+        if self.variance == "log":
+            tm_log_luminance(self.lum, stream, self.logv, self.log_offsets, self.log_minmax,
+                             self.ws_stats)
+            _ck("tm_integral_image", _lib().tm_integral_image(
+                _vp(self.logv), self.logv.stride(0), self.H, self.W, _capi.SAT_PREC[self.prec],
+                _vp(self.log_offsets), _vp(self.sat.ptr), self.sat.ld, self.tune_ref,
+                _vp(self.ws_tab), self.ws_tab.numel(), _stream(stream)))
+            if h is not None:
+                _ck("tm_integral_histogram", _lib().tm_integral_histogram(
+                    _vp(self.lum), self.lum.stride(0), self.H, self.W, _vp(self.edges),
+                    self.params.n_bins, 1, _vp(h.ptr), h.ld, h.plane_stride, self.tune_ref,
+                    _vp(self.ws_tab), self.ws_tab.numel(), _stream(stream)))
+            return
         _ck("tm_integral_tables", _lib().tm_integral_tables(
             _vp(self.lum), self.lum.stride(0), self.H, self.W, _capi.SAT_PREC[self.prec],
             _vp(self.offsets), _vp(self.sat.ptr), self.sat.ld, _vp(self.edges),
@@ -454,7 +504,7 @@ class ToneMapper:
 
     def query(self, stream=None):
         tm_tonemap_forward(self.lum, self.sat, self.hist, self.edges, self.params,
-                           self.offsets, self.out, stream)
+                           self.sat_offsets, self.out, stream)
 
     def run(self, rgb, stream=None) -> torch.Tensor:
         self.prologue(rgb, stream)
@@ -466,7 +516,7 @@ class ToneMapper:
         """Fused query that also writes the per-field tone values and weights (Fig. 3):
         (L, maps [2s, H, W])."""
         return tm_tonemap_forward_maps(self.lum, self.sat, self.hist, self.edges, self.params,
-                                       self.offsets, self.out, None, stream)
+                                       self.sat_offsets, self.out, None, stream)
 
     def query_rgb(self, rgb, saturation: float = 0.6, stream=None) -> torch.Tensor:
         """Fused query with colour restoration (Eq. 12) of rgb: returns rgb_out [3, H, W]
@@ -475,7 +525,7 @@ class ToneMapper:
             self.rgb_out = torch.empty((3, self.H, self.W), dtype=torch.float32,
                                        device=self.lum.device)
         return tm_tonemap_forward_rgb(self.lum, self.sat, self.hist, self.edges, self.params,
-                                      rgb, saturation, self.offsets, self.rgb_out, self.out,
+                                      rgb, saturation, self.sat_offsets, self.rgb_out, self.out,
                                       stream)
 
     def run_rgb(self, rgb, saturation: float = 0.6, stream=None) -> torch.Tensor:
@@ -483,8 +533,13 @@ class ToneMapper:
         self.tables(stream)
         return self.query_rgb(rgb, saturation, stream)
 
+    def _linear_only(self, what):
+        if self.variance != "linear":
+            raise ValueError(f"{what}: the log-domain variance variant has a forward only")
+
     def query_train(self, stream=None):
         """Fused query that also writes the backward's residual planes."""
+        self._linear_only("query_train")
         if not hasattr(self, "resid"):
             self.resid = torch.empty((residual_planes(self.params.n_scales), self.H, self.W),
                                      dtype=torch.float32, device=self.lum.device)
@@ -505,6 +560,7 @@ class ToneMapper:
 
     def backward_resid(self, grad_out: torch.Tensor, stream=None):
         """Adjoint from the residual planes of the last run_train: (grad_lum, grad_params)."""
+        self._linear_only("backward_resid")
         self._bwd_buffers()
         if not hasattr(self, "ws_bwd_resid"):
             self.ws_bwd_resid = _ws(_lib().tm_backward_resid_workspace_bytes(
@@ -514,6 +570,7 @@ class ToneMapper:
 
     def backward(self, grad_out: torch.Tensor, stream=None):
         """Adjoint of the last forward from its tables: (grad_lum, grad_params)."""
+        self._linear_only("backward")
         self._bwd_buffers()
         if not hasattr(self, "ws_bwd"):
             self.ws_bwd = _ws(_lib().tm_backward_workspace_bytes(self.H, self.W,

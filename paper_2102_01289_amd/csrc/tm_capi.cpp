@@ -198,6 +198,18 @@ tm_status tm_prologue(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32
                                  (hipStream_t)stream));
 }
 
+tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t W, float *logv,
+                           int64_t ld_log, float *offsets, float *minmax, void *ws,
+                           size_t ws_bytes, void *stream) {
+    TM_TRY(check_image(H, W));
+    if (!lum || !logv) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_lum));
+    TM_TRY(check_plane(H, W, ld_log));
+    TM_TRY(check_ws(ws, ws_bytes, tm_image_stats_workspace_bytes(H, W)));
+    return from_hip(launch_log_stats(lum, ld_lum, logv, ld_log, H, W, offsets, minmax,
+                                     static_cast<StatsPartial *>(ws), (hipStream_t)stream));
+}
+
 // ------------------------------------------------------------------ a2, a3
 size_t tm_tables_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_sat_prec prec,
                                  const tm_tune *tune) {

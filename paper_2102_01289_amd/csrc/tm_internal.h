@@ -42,6 +42,10 @@ hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, con
                         int64_t ld_lum_in, float *lum_out, int64_t ld_lum_out, int H, int W,
                         int n_bins, float *edges, float *offsets, float *minmax,
                         StatsPartial *partials, hipStream_t s);
+// logv = ln(max(lum, FLT_MIN)) and the statistics (offsets, minmax) of logv.
+hipError_t launch_log_stats(const float *lum, int64_t ld_lum, float *logv, int64_t ld_log, int H,
+                            int W, float *offsets, float *minmax, StatsPartial *partials,
+                            hipStream_t s);
 
 // ---------------------------------------------------------------- scans (a2, a3)
 struct ScanTune {

@@ -60,7 +60,9 @@ __device__ Stat block_reduce(Stat st) {
 
 // One reduction part of one image: row segments part, part + nparts, ... (so the partials,
 // and hence the statistics, do not depend on how parts are scheduled).
-template <bool FROM_RGB, bool STATS>
+// LOG (luminance input only): the pass writes l = ln(max(v, FLT_MIN)) to lum_out and the
+// statistics are those of l.
+template <bool FROM_RGB, bool STATS, bool LOG = false>
 __device__ void stats_part(const StatsK &k, int part, int nparts) {
     Stat st{INFINITY, -INFINITY, 0.0, 0.0};
     const int H = k.H, W = k.W;
@@ -103,6 +105,16 @@ __device__ void stats_part(const StatsK &k, int part, int nparts) {
             } else {
                 for (int i = 0; i < 4; ++i) v[i] = (x + i < W) ? L[i] : 0.f;
             }
+            if (LOG) {
+                for (int i = 0; i < 4; ++i) v[i] = logf(fmaxf(v[i], FLT_MIN));
+                float *o = k.lum_out + (int64_t)y * k.ld_out + x;
+                if (full && k.vec_out) {
+                    *reinterpret_cast<float4 *>(o) = make_float4(v[0], v[1], v[2], v[3]);
+                } else {
+                    for (int i = 0; i < 4; ++i)
+                        if (x + i < W) o[i] = v[i];
+                }
+            }
         }
         if (STATS) {
             for (int i = 0; i < 4; ++i)
@@ -123,9 +135,9 @@ __device__ void stats_part(const StatsK &k, int part, int nparts) {
     }
 }
 
-template <bool FROM_RGB, bool STATS>
+template <bool FROM_RGB, bool STATS, bool LOG = false>
 __global__ void __launch_bounds__(kBlock) lum_stats_kernel(StatsK k) {
-    stats_part<FROM_RGB, STATS>(k, blockIdx.x, gridDim.x);
+    stats_part<FROM_RGB, STATS, LOG>(k, blockIdx.x, gridDim.x);
 }
 
 // Batched prologue over images [0, count) of ks: item g in [prefix[0], prefix[count]) is part
@@ -330,6 +342,19 @@ hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, con
         hipLaunchKernelGGL((lum_stats_kernel<true, true>), dim3(k.nparts), dim3(kBlock), 0, s, k);
     else
         hipLaunchKernelGGL((lum_stats_kernel<false, true>), dim3(k.nparts), dim3(kBlock), 0, s, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_log_stats(const float *lum, int64_t ld_lum, float *logv, int64_t ld_log, int H,
+                            int W, float *offsets, float *minmax, StatsPartial *partials,
+                            hipStream_t s) {
+    StatsK k = make_statsk(nullptr, 0, 0, lum, ld_lum, logv, ld_log, H, W, 1, nullptr, offsets,
+                           minmax, partials);
+    hipLaunchKernelGGL((lum_stats_kernel<false, true, true>), dim3(k.nparts), dim3(kBlock), 0, s,
+                       k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k);

@@ -9,6 +9,10 @@ so the entry's error is at most depth * u * sum |q| over the quadrant, with u = 
 (FP32), 2^-44 (compensated FP32 pairs: TwoSum of the leading parts plus the trailing parts)
 or 2^-53 (FP64).  For TM_SAT_C32X2, q = v - mu1 (and v^2 - mu2), |q| <= v + mu1.
 
+Log-domain variance variant.  The device's log plane is FP32 logf, within 2 ulp of the
+exact logarithm; the oracle's is FP64.  That input difference enters the window sums as
+|dS1| <= sum |dl| and |dS2| <= sum (2 |l| |dl| + dl^2) over the window.
+
 Fused output.  A perturbation d_j of the window variance of field j moves
 L = sum W_j L_j / D (D = sum W_j, W_j = var_j/(var_j + eps)) by
     dL = sum_j (L_j - L)/D * eps/(var_j + eps)^2 * d_j        (first order),
@@ -43,7 +47,7 @@ def sat_depth(H, W, vec, th):
 
 def abs_tables(lum, prec, mu1=0.0, mu2=0.0):
     """Quadrant sums of |q| for q = v and q = v^2 (upper bounds for C32X2), shape (H+1, W+1)."""
-    v = lum.astype(np.float64)
+    v = np.abs(lum.astype(np.float64))
     H, W = v.shape
     a1 = np.zeros((H + 1, W + 1))
     a2 = np.zeros((H + 1, W + 1))
@@ -75,11 +79,23 @@ def corners(H, W, rx, ry):
     return xm, xp, ym, yp, N
 
 
+def _box_table(a):
+    t = np.zeros((a.shape[0] + 1, a.shape[1] + 1))
+    t[1:, 1:] = np.cumsum(np.cumsum(a, 0), 1)
+    return t
+
+
 def forward_bound(lum, Lref, Lj, Wj, varj, S1j, rx, ry, eps, prec, vec, th, mu1=0.0,
-                  mu2=0.0):
-    """Per-pixel bound on |L_gpu - L_oracle| (see module docstring)."""
+                  mu2=0.0, input_err=None):
+    """Per-pixel bound on |L_gpu - L_oracle| (see module docstring).  lum is the image whose
+    window variance is taken.  input_err = (d1, d2): per-pixel bounds on how far the device's
+    terms q = v and q = v^2 may lie from the oracle's (when the two do not start from the
+    same values), added to the table bounds through window sums."""
     H, W = lum.shape
     e1, e2 = entry_bound(lum, prec, vec, th, mu1, mu2)
+    b1 = b2 = None
+    if input_err is not None:
+        b1, b2 = _box_table(input_err[0]), _box_table(input_err[1])
     D = Wj.sum(axis=0)
     out = np.zeros((H, W))
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -87,6 +103,9 @@ def forward_bound(lum, Lref, Lj, Wj, varj, S1j, rx, ry, eps, prec, vec, th, mu1=
             xm, xp, ym, yp, N = corners(H, W, rx[j], ry[j])
             c1 = e1[ym, xm] + e1[ym, xp] + e1[yp, xm] + e1[yp, xp]
             c2 = e2[ym, xm] + e2[ym, xp] + e2[yp, xm] + e2[yp, xp]
+            if b1 is not None:
+                c1 = c1 + (b1[yp, xp] - b1[ym, xp] - b1[yp, xm] + b1[ym, xm])
+                c2 = c2 + (b2[yp, xp] - b2[ym, xp] - b2[yp, xm] + b2[ym, xm])
             dvar = (c2 + 2.0 * np.abs(S1j[j] / N) * c1) / N
             sens = np.abs(Lj[j] - Lref) / D * eps / (varj[j] + eps) ** 2
             # with every weight near zero the first-order term is not a bound: count the whole
