@@ -4,5 +4,7 @@ This module only draws inputs.  It holds none of the tone-mapping arithmetic, so
 HIP path and the CPU oracle can be fed from it without sharing any of the method's code.
 """
 from .wdr import WdrImage, gen_wdr, gen_batch_shapes, gen_upstream_grad, WORKLOADS
+from .exposures import exposure_times, gen_exposure_stack, gen_sample_pixels
 
-__all__ = ["WdrImage", "gen_wdr", "gen_batch_shapes", "gen_upstream_grad", "WORKLOADS"]
+__all__ = ["WdrImage", "gen_wdr", "gen_batch_shapes", "gen_upstream_grad", "WORKLOADS",
+           "exposure_times", "gen_exposure_stack", "gen_sample_pixels"]
