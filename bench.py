@@ -48,7 +48,7 @@ def _parse():
                     help="after the timed loop, copy 1 GiB device-to-device once (a plain copy "
                          "kernel of known size, for calibrating HBM counters) and report its "
                          "bandwidth")
-    ap.add_argument("--workload", choices=["image", "batch", "precision", "sweep"],
+    ap.add_argument("--workload", choices=["image", "batch", "precision", "sweep", "hdr"],
                     default="image",
                     help="image: one 4000x3000 image (default); batch: 64 images of uneven "
                          "size, launches replayed from a HIP graph; precision: output error "
@@ -195,6 +195,67 @@ def bench_precision(args):
             print(f"bench: {name} {key} max {err.max():.3e} {ms:.3f} ms", file=sys.stderr,
                   flush=True)
         out["cases"].append(case)
+    print(json.dumps(out), flush=True)
+
+
+def bench_hdr(args):
+    """The multi-exposure front end at 4000x3000: four 8-bit exposures of the 12 MP workload's
+    radiance (seeded camera model), response recovery from 200 sampled pixels, the radiance
+    merge (HBM-bound: P*3 B in, 12 B out per pixel) and the chain exposures -> tone-mapped
+    RGB (merge, prologue, tables, fused query with colour restoration).  The oracle's merge
+    is timed on the host beside it."""
+    import numpy as np
+    import torch
+
+    import paper_2102_01289_amd as tm
+    from oracle import hdr
+    from synth import WORKLOADS, exposure_times, gen_exposure_stack, gen_sample_pixels, gen_wdr
+
+    c = WORKLOADS["wdr_4000x3000"]
+    H, W, P = c["H"], c["W"], 4
+    img = gen_wdr(H, W, c["K"], c["lo"], c["hi"], c["seed"])
+    times = exposure_times(P)
+    stack = gen_exposure_stack(img.rgb, times, seed=c["seed"] + 1000)
+    del img
+    print("bench: exposure stack generated", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    st = torch.from_numpy(stack).to(dev)
+    t = torch.from_numpy(np.log(times).astype(np.float32)).to(dev)
+    idx = torch.from_numpy(gen_sample_pixels(H, W, 200, seed=c["seed"] + 2000)).to(dev)
+    g = torch.empty((3, 256), dtype=torch.float32, device=dev)
+    ws = torch.empty(tm._lib().tm_hdr_response_workspace_bytes(), dtype=torch.uint8, device=dev)
+    E = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    resp_ms = _median_ms(lambda: tm.tm_hdr_response(st, t, idx, 100.0, g=g, ws=ws), reps=5)
+    merge_ms = _median_ms(lambda: tm.tm_hdr_merge(st, t, g, out=E), reps=args.steps)
+    p = tm.make_params(args.n_bins, args.n_scales, eps=args.eps, H=H, W=W)
+    m = tm.ToneMapper(H, W, p, args.prec, device=dev)
+
+    def chain():
+        tm.tm_hdr_merge(st, t, g, out=E)
+        m.run_rgb(E)
+
+    chain_ms = _median_ms(chain, reps=args.steps)
+    algo = (3 * P + 12) * H * W
+    # the oracle's merge of the same stack with the device's response, on the host
+    g_host = g.cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    hdr.merge(stack, g_host, np.log(times))
+    orc_s = time.perf_counter() - t0
+    out = {"metric": "megapixels/s, exposure merge (Debevec-Malik) and exposures -> "
+                     "tone-mapped RGB", "value": round(H * W / merge_ms / 1e3, 1),
+           "unit": "megapixels/s", "n_gpus": 1, "steps": args.steps,
+           "higher_is_better": True, "data": "synthetic", "dtype": "u8->f32",
+           "config": {"workload": "wdr_4000x3000_exposures4", "height": H, "width": W,
+                      "exposures": P, "exposure_ratio": 16, "samples": 200, "lambda": 100.0},
+           "merge_ms": round(merge_ms, 4), "response_ms": round(resp_ms, 3),
+           "chain_ms": round(chain_ms, 4), "chain_mp_s": round(H * W / chain_ms / 1e3, 1),
+           "roofline": {"bound": "hbm", "kernel": "hdr_merge_kernel",
+                        "achieved": round(algo / merge_ms / 1e6, 1), "peak": 8000.0,
+                        "unit": "GB/s", "frac": round(algo / merge_ms / 1e6 / 8000.0, 4),
+                        "algorithmic_bytes_per_launch": algo},
+           "cpu_baseline": {"value": round(H * W / orc_s / 1e6, 2), "unit": "megapixels/s",
+                            "cores": 1, "kind": "oracle",
+                            "sample": f"numpy merge of the full stack, {orc_s:.1f} s"}}
     print(json.dumps(out), flush=True)
 
 
@@ -353,6 +414,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args)
+        return
+    if args.workload == "hdr":
+        bench_hdr(args)
         return
 
     import numpy as np

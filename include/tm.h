@@ -309,6 +309,46 @@ tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W
                               float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
                               size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- multi-exposure input */
+
+/* The step before the method in the paper's application (Section III): the WDR image is
+ * recovered from several 8-bit exposures with the method of Debevec and Malik.  For 8-bit
+ * values z, pixel i and exposure j of time dt_j, the inverse log camera response
+ * g(z) = ln f^-1(z) obeys g(Z_ij) = ln E_i + ln dt_j; values are trusted by the hat weight
+ * w(z) = z (z <= 127), 255 - z (z >= 128).
+ *
+ * Exposure stacks: uint8, exposure j, channel c (R, G, B) of pixel (x, y) at
+ * stack[j*exp_stride + c*ch_stride + y*ld + x], with ld >= W, ch_stride >= H*ld,
+ * exp_stride >= 3*ch_stride; 1 <= P <= TM_HDR_MAX_EXPOSURES.  log_dt: device float[P], the
+ * natural logs of the exposure times.  g: device float[3][256], one inverse log response
+ * per channel. */
+#define TM_HDR_MAX_EXPOSURES 16
+#define TM_HDR_MAX_SAMPLE_VALUES 32768
+
+/* Response recovery: per channel, g minimising
+ *   sum_ij [w(Z_ij)(g(Z_ij) - ln E_i - ln dt_j)]^2 + lambda sum_{z=1..254} [w(z) g''(z)]^2,
+ * g''(z) = g(z-1) - 2 g(z) + g(z+1), with g(128) = 0, over the n_samples pixels whose flat
+ * indices y*W + x are in samples (device int32[n_samples]; an index outside the image makes
+ * that sample count for nothing).  n_samples * P <= TM_HDR_MAX_SAMPLE_VALUES, lambda >= 0.
+ * Solved in FP64 on the device (the per-sample ln E_i eliminated in closed form, then a
+ * Cholesky factorisation); g is written as FP32.  If the samples leave the system singular
+ * (too few distinct values) the channel's g is NaN.  Deterministic.
+ * Workspace: tm_hdr_response_workspace_bytes(). */
+size_t tm_hdr_response_workspace_bytes(void);
+tm_status tm_hdr_response(const uint8_t *stack, int64_t exp_stride, int64_t ch_stride,
+                          int64_t ld, int32_t P, int32_t H, int32_t W, const int32_t *samples,
+                          int32_t n_samples, const float *log_dt, float lambda, float *g,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Radiance map: per pixel and channel, ln E = sum_j w(Z_j)(g(Z_j) - ln dt_j) / sum_j w(Z_j)
+ * (where every weight is 0, i.e. each value is 0 or 255, the unweighted mean of
+ * g(Z_j) - ln dt_j), written as E = exp(ln E) in FP32 to the planar image rgb (channel c at
+ * rgb + c*ch_stride_out, pitch ld_out), ready for tm_prologue / tm_tonemap_rgb.  No
+ * workspace. */
+tm_status tm_hdr_merge(const uint8_t *stack, int64_t exp_stride, int64_t ch_stride, int64_t ld,
+                       int32_t P, int32_t H, int32_t W, const float *log_dt, const float *g,
+                       float *rgb, int64_t ch_stride_out, int64_t ld_out, void *stream);
+
 /* ---------------------------------------------------------------- batched forward */
 
 /* One image of a batch.  The method (Section II) is applied to each image independently,

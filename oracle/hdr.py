@@ -31,9 +31,9 @@ def weight(z) -> np.ndarray:
     return np.where(z <= 127, z, 255 - z).astype(np.float64)
 
 
-def response(Z, log_dt, lam: float, return_lnE: bool = False):
-    """Inverse log response g[256] (float64, g[128] = 0) from samples Z [N, P] (uint8)
-    and log exposure times log_dt [P]; with return_lnE also the samples' ln E [N]."""
+def system(Z, log_dt, lam: float):
+    """The least-squares system (A, b) of the response: columns g(0..255) without g(128),
+    then ln E_0..ln E_{N-1}; one row per sample value, then one per smoothness term."""
     Z = np.asarray(Z, dtype=np.int64)
     t = np.asarray(log_dt, dtype=np.float64)
     N, P = Z.shape
@@ -62,6 +62,14 @@ def response(Z, log_dt, lam: float, return_lnE: bool = False):
             if z + dz != ZMID:
                 A[r, gcol[z + dz]] = s * w * c
         r += 1
+    return A, b
+
+
+def response(Z, log_dt, lam: float, return_lnE: bool = False):
+    """Inverse log response g[256] (float64, g[128] = 0) from samples Z [N, P] (uint8)
+    and log exposure times log_dt [P]; with return_lnE also the samples' ln E [N]."""
+    A, b = system(Z, log_dt, lam)
+    gcol = {z: (z if z < ZMID else z - 1) for z in range(256) if z != ZMID}
     x = np.linalg.lstsq(A, b, rcond=None)[0]
     g = np.zeros(256)
     for z, c in gcol.items():

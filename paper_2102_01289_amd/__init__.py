@@ -211,6 +211,53 @@ def tm_log_luminance(lum: torch.Tensor, stream=None, out=None, offsets=None, min
     return out, offsets, minmax
 
 
+def _stack(stack: torch.Tensor):
+    if (stack.dtype != torch.uint8 or stack.dim() != 4 or stack.shape[1] != 3
+            or stack.stride(3) != 1 or not stack.is_cuda):
+        raise ValueError("stack must be a CUDA uint8 [P, 3, H, W] tensor with unit column stride")
+    P, _, H, W = stack.shape
+    return P, H, W, stack.stride(0), stack.stride(1), stack.stride(2)
+
+
+def _check_log_dt(log_dt, P):
+    if log_dt.dtype != torch.float32 or log_dt.numel() != P or not log_dt.is_contiguous():
+        raise ValueError("log_dt must be a contiguous float32 vector with one entry per exposure")
+
+
+def tm_hdr_response(stack: torch.Tensor, log_dt: torch.Tensor, samples: torch.Tensor,
+                    lam: float = 100.0, g=None, ws=None, stream=None) -> torch.Tensor:
+    """Inverse log camera responses g [3, 256] (FP32, g[:, 128] = 0) from the pixels at the
+    flat indices `samples` (int32) of an exposure stack [P, 3, H, W] with log times log_dt."""
+    P, H, W, es, cs, ld = _stack(stack)
+    dev = stack.device
+    if samples.dtype != torch.int32 or samples.dim() != 1 or not samples.is_contiguous():
+        raise ValueError("samples must be a contiguous int32 vector of flat pixel indices")
+    _check_log_dt(log_dt, P)
+    if g is None:
+        g = torch.empty((3, 256), dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = _ws(_lib().tm_hdr_response_workspace_bytes(), dev)
+    _ck("tm_hdr_response", _lib().tm_hdr_response(
+        _vp(stack), es, cs, ld, P, H, W, _vp(samples), samples.numel(), _vp(log_dt),
+        float(lam), _vp(g), _vp(ws), ws.numel(), _stream(stream)))
+    return g
+
+
+def tm_hdr_merge(stack: torch.Tensor, log_dt: torch.Tensor, g: torch.Tensor, out=None,
+                 stream=None) -> torch.Tensor:
+    """Radiance map E [3, H, W] (FP32, planar) of an exposure stack [P, 3, H, W]."""
+    P, H, W, es, cs, ld = _stack(stack)
+    _check_log_dt(log_dt, P)
+    if g.dtype != torch.float32 or tuple(g.shape) != (3, 256) or not g.is_contiguous():
+        raise ValueError("g must be a contiguous float32 [3, 256] tensor")
+    if out is None:
+        out = torch.empty((3, H, W), dtype=torch.float32, device=stack.device)
+    _ck("tm_hdr_merge", _lib().tm_hdr_merge(
+        _vp(stack), es, cs, ld, P, H, W, _vp(log_dt), _vp(g), _vp(out), out.stride(0),
+        out.stride(1), _stream(stream)))
+    return out
+
+
 def tm_prologue(rgb: torch.Tensor, n_bins: int, stream=None):
     """Eq. 11 and the image statistics in one pass: (lum, edges, offsets, minmax)."""
     _, H, W = rgb.shape

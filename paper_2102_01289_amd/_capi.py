@@ -52,6 +52,10 @@ SIGNATURES = {
     "tm_image_stats": (ctypes.c_int, [P, I64, I32, I32, I32, P, P, P, P, SZ, P]),
     "tm_prologue": (ctypes.c_int, [P, I64, I64, I32, I32, I32, P, I64, P, P, P, P, SZ, P]),
     "tm_log_luminance": (ctypes.c_int, [P, I64, I32, I32, P, I64, P, P, P, SZ, P]),
+    "tm_hdr_response_workspace_bytes": (SZ, []),
+    "tm_hdr_response": (ctypes.c_int, [P, I64, I64, I64, I32, I32, I32, P, I32, P,
+                                       ctypes.c_float, P, P, SZ, P]),
+    "tm_hdr_merge": (ctypes.c_int, [P, I64, I64, I64, I32, I32, I32, P, P, P, I64, I64, P]),
     "tm_integral_image": (ctypes.c_int, [P, I64, I32, I32, ctypes.c_int, P, P, I64, PT, P, SZ,
                                          P]),
     "tm_integral_histogram": (ctypes.c_int, [P, I64, I32, I32, P, I32, ctypes.c_int, P, I64,

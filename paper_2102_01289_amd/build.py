@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtm355.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["tm_prologue.hip", "tm_scan.hip", "tm_query.hip", "tm_backward.hip",
+SOURCES = ["tm_prologue.hip", "tm_scan.hip", "tm_query.hip", "tm_backward.hip", "tm_hdr.hip",
            "tm_batch.cpp", "tm_capi.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

@@ -210,6 +210,46 @@ tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t 
                                      static_cast<StatsPartial *>(ws), (hipStream_t)stream));
 }
 
+// ------------------------------------------------------------------ exposures
+namespace {
+tm_status check_stack(const uint8_t *stack, int64_t exp_stride, int64_t ch_stride, int64_t ld,
+                      int32_t P, int32_t H, int32_t W) {
+    TM_TRY(check_image(H, W));
+    if (!stack) return TM_ERR_ARG;
+    if (P < 1 || P > TM_HDR_MAX_EXPOSURES) return TM_ERR_ARG;
+    if (ld < W || ch_stride < (int64_t)H * ld || exp_stride < 3 * ch_stride) return TM_ERR_SHAPE;
+    if (exp_stride > ((int64_t)1 << 40) / P) return TM_ERR_SHAPE;
+    return TM_OK;
+}
+}  // namespace
+
+size_t tm_hdr_response_workspace_bytes(void) { return round256(hdr_response_ws_bytes()); }
+
+tm_status tm_hdr_response(const uint8_t *stack, int64_t exp_stride, int64_t ch_stride,
+                          int64_t ld, int32_t P, int32_t H, int32_t W, const int32_t *samples,
+                          int32_t n_samples, const float *log_dt, float lambda, float *g,
+                          void *ws, size_t ws_bytes, void *stream) {
+    TM_TRY(check_stack(stack, exp_stride, ch_stride, ld, P, H, W));
+    if (!samples || !log_dt || !g) return TM_ERR_ARG;
+    if (n_samples < 1 || (int64_t)n_samples * P > TM_HDR_MAX_SAMPLE_VALUES) return TM_ERR_ARG;
+    if (!(lambda >= 0.f) || !std::isfinite(lambda)) return TM_ERR_ARG;
+    TM_TRY(check_ws(ws, ws_bytes, tm_hdr_response_workspace_bytes()));
+    return from_hip(launch_hdr_response(stack, exp_stride, ch_stride, ld, P, H, W, samples,
+                                        n_samples, log_dt, lambda, g, ws, (hipStream_t)stream));
+}
+
+tm_status tm_hdr_merge(const uint8_t *stack, int64_t exp_stride, int64_t ch_stride, int64_t ld,
+                       int32_t P, int32_t H, int32_t W, const float *log_dt, const float *g,
+                       float *rgb, int64_t ch_stride_out, int64_t ld_out, void *stream) {
+    TM_TRY(check_stack(stack, exp_stride, ch_stride, ld, P, H, W));
+    if (!log_dt || !g || !rgb) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_out));
+    if (ch_stride_out < (int64_t)H * ld_out) return TM_ERR_SHAPE;
+    if (3 * ch_stride_out >= ((int64_t)1 << 40)) return TM_ERR_SHAPE;
+    return from_hip(launch_hdr_merge(stack, exp_stride, ch_stride, ld, P, H, W, log_dt, g, rgb,
+                                     ch_stride_out, ld_out, (hipStream_t)stream));
+}
+
 // ------------------------------------------------------------------ a2, a3
 size_t tm_tables_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_sat_prec prec,
                                  const tm_tune *tune) {

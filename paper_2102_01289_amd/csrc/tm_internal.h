@@ -47,6 +47,16 @@ hipError_t launch_log_stats(const float *lum, int64_t ld_lum, float *logv, int64
                             int W, float *offsets, float *minmax, StatsPartial *partials,
                             hipStream_t s);
 
+// ---------------------------------------------------------------- multi-exposure front end
+size_t hdr_response_ws_bytes();
+hipError_t launch_hdr_response(const uint8_t *stack, int64_t exp_stride, int64_t ch_stride,
+                               int64_t ld, int P, int H, int W, const int32_t *samples, int N,
+                               const float *log_dt, float lam, float *g, void *ws,
+                               hipStream_t s);
+hipError_t launch_hdr_merge(const uint8_t *stack, int64_t exp_stride, int64_t ch_stride,
+                            int64_t ld, int P, int H, int W, const float *log_dt, const float *g,
+                            float *out, int64_t ch_out, int64_t ld_out, hipStream_t s);
+
 // ---------------------------------------------------------------- scans (a2, a3)
 struct ScanTune {
     int vec;        // columns per lane: 1, 2, 4, 8
