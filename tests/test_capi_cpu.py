@@ -156,3 +156,30 @@ def test_rgb_entry_argument_checks():
     assert need > 0 and lib.tm_tonemap_rgb_workspace_bytes(H, W, ctypes.byref(pp), 7) == 0
     assert lib.tm_tonemap_rgb(fake, H * W, W, H, W, ctypes.byref(pp), 1, 0.6, fake, H * W, W,
                               fake, need - 1, null) == -4
+
+
+def test_log_and_exposure_entry_argument_checks():
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    fake, null = P(1 << 20), P(0)
+    # log-luminance: null output, pitch too small, workspace missing
+    assert lib.tm_log_luminance(fake, 10, 10, 10, null, 10, null, null, fake, 1 << 20, null) == -1
+    assert lib.tm_log_luminance(fake, 10, 10, 10, fake, 9, null, null, fake, 1 << 20, null) == -2
+    assert lib.tm_log_luminance(fake, 10, 10, 10, fake, 10, null, null, null, 0, null) == -4
+    # exposure stacks: P out of range, overlapping channel/exposure strides
+    ws = lib.tm_hdr_response_workspace_bytes()
+    assert ws >= 3 * 255 * 256 * 8
+    H, W, ld = 10, 10, 16
+    cs, es = H * ld, 3 * H * ld
+    f = ctypes.c_float
+    resp = lambda P_, es_=es, cs_=cs, n=50, lam=100.0, w=ws: lib.tm_hdr_response(
+        fake, es_, cs_, ld, P_, H, W, fake, n, fake, f(lam), fake, fake, w, null)
+    assert resp(0) == -1 and resp(17) == -1
+    assert resp(4, cs_=H * ld - 1) == -2 and resp(4, es_=3 * cs - 1) == -2
+    assert resp(4, n=0) == -1 and resp(4, n=32768 // 4 + 1) == -1
+    assert resp(4, lam=-1.0) == -1 and resp(4, lam=float("nan")) == -1
+    assert resp(4, w=ws - 1) == -4
+    merge = lambda P_, ldo=W, cso=H * W, out=fake: lib.tm_hdr_merge(
+        fake, es, cs, ld, P_, H, W, fake, fake, out, cso, ldo, null)
+    assert merge(0) == -1 and merge(4, out=null) == -1
+    assert merge(4, ldo=W - 1) == -2 and merge(4, cso=H * W - 1) == -2
