@@ -25,8 +25,7 @@ PEAK_HBM_GBS = 8000.0
 # PMC summary of the roofline kernel (FETCH_SIZE and WRITE_SIZE per dispatch, calibrated on a
 # plain copy kernel), and the sources whose digest it records
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forward_kernel_wdr_4000x3000_traffic.md")
-QUERY_SOURCES = ("paper_2102_01289_amd/csrc/tm_query.hip", "paper_2102_01289_amd/csrc/tm_device.h",
-                 "paper_2102_01289_amd/build.py")
+QUERY_SOURCES = ("paper_2102_01289_amd/csrc/tm_query.hip", "paper_2102_01289_amd/csrc/tm_device.h")
 # the kernel's parameter struct lives in the shared internal header
 QUERY_STRUCT = ("paper_2102_01289_amd/csrc/tm_internal.h", "struct FwdK {")
 
@@ -337,11 +336,13 @@ def query_bytes_per_px(prec: str, n_bins: int, resid_planes: int = 0) -> int:
 
 def query_source_digest() -> str:
     """Digest of everything the fused query kernel is built from: its source file, the device
-    header, the build flags and its parameter struct."""
+    header, the compiler flags and its parameter struct."""
+    from paper_2102_01289_amd import build as hip_build
     h = hashlib.sha256()
     for f in QUERY_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(hip_build.COMMON[:-1]).encode())   # the flags, without the include path
     with open(os.path.join(ROOT, QUERY_STRUCT[0])) as fh:
         text = fh.read()
     i = text.index(QUERY_STRUCT[1])

@@ -6,11 +6,22 @@ import torch
 
 import oracle
 import paper_2102_01289_amd as tm
+from _bounds import forward_bound, tiling, window_sums
 from _cases import edges_ref, lum_ref, rgb_case, to_dev
 
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(96, 130), (37, 123), (1, 1), (1, 300), (130, 1030)]
+
+
+def colour_tolerance(rgb, lum, Lbound, ref, sat):
+    """|c_gpu - c_oracle| per value: the channel ratio (c/v)^sat times the derived bound on
+    |L_gpu - L_oracle|, plus the FP32 colour arithmetic (a division, powf and a product:
+    1e-6 relative)."""
+    c = np.maximum(rgb.astype(np.float64), 0.0)
+    lv = lum.astype(np.float64)
+    ratio = np.where(lv > 0, c / np.where(lv > 0, lv, 1.0), 1.0) ** sat
+    return ratio * Lbound[None] + 1e-6 * np.abs(ref) + 1e-30
 
 
 @pytest.mark.parametrize("H,W", SHAPES)
@@ -24,11 +35,20 @@ def test_fused_colour_restoration(H, W, prec, sat):
     out = m.run_rgb(to_dev(rgb), sat).clone()
     torch.cuda.synchronize()
     assert torch.equal(m.out, L_plain)             # the fused colour stage leaves L unchanged
-    # Eq. 12 applied by the oracle to the device's own L: only the colour arithmetic differs
-    L = L_plain.cpu().numpy().astype(np.float64)
-    ref = oracle.color_restore(rgb, lum_ref(rgb), L, sat)
+    # against the oracle chain (luminance, exact edges, FP64 forward, Eq. 12); the tolerance
+    # carries the derived per-pixel bound of the fused forward through Eq. 12
+    lum = lum_ref(rgb)
+    e = edges_ref(lum, 5)
+    rx, ry = oracle.paper_radii(H, W, 5)
+    Lref, Lj, Wj, varj = oracle.forward(lum, e, rx, ry, 0.1, per_scale=True)
+    vd = lum.astype(np.float64)
+    mu = (float(np.float32(vd.mean())), float(np.float32((vd * vd).mean())))
+    vec, th = tiling(H, W)
+    Lb = forward_bound(lum, Lref, Lj, Wj, varj, window_sums(lum, rx, ry), rx, ry, 0.1, prec,
+                       vec, th, *(mu if prec == "c32x2" else (0.0, 0.0)))
+    ref = oracle.color_restore(rgb, lum, Lref, sat)
     got = out.cpu().numpy().astype(np.float64)
-    assert np.all(np.abs(got - ref) <= 1e-6 * np.abs(ref) + 1e-30)
+    assert np.all(np.abs(got - ref) <= colour_tolerance(rgb, lum, Lb, ref, sat))
 
 
 @pytest.mark.parametrize("prec", ["c32x2", "f64"])

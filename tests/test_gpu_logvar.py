@@ -125,6 +125,45 @@ def test_log_forward_special_cases():
         tm.ToneMapper(H, W, p, "c32x2", variance="log").query_train()
 
 
+def test_log_variance_maps_and_colour():
+    # the per-field maps (Fig. 3) and the colour stage (Eq. 12) run on the log-variance
+    # tables too: same L as the plain query, weights of the log variance
+    H, W = 120, 200
+    rgb = rgb_case(H, W, 6, -3.0, 5.0, seed=23)
+    lum = lum_ref(rgb)
+    e = edges_ref(lum, 5)
+    rx, ry = oracle.paper_radii(H, W, 5)
+    p = tm.make_params(5, 5, eps=0.1, H=H, W=W)
+    m = tm.ToneMapper(H, W, p, "c32x2", variance="log")
+    L_plain = m.run(to_dev(rgb)).clone()
+    L, maps = m.query_maps()
+    torch.cuda.synchronize()
+    assert torch.equal(L, L_plain)
+    _, Lj, Wj, _ = oracle.forward(lum, e, rx, ry, 0.1, per_scale=True, var_domain="log")
+    mp = maps.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(mp[:5] - Lj)) <= 2e-7
+    # log variances are well conditioned: the FP32 log plane's rounding dominates
+    assert np.max(np.abs(mp[5:] - Wj)) <= 1e-5
+    out = m.query_rgb(to_dev(rgb), 0.6)
+    torch.cuda.synchronize()
+    assert torch.equal(m.out, L_plain)
+    # against the oracle chain, with the log-variance forward bound carried through Eq. 12
+    Lref, Lj2, Wj2, varj2 = oracle.forward(lum, e, rx, ry, 0.1, per_scale=True,
+                                           var_domain="log")
+    lg = _log_ref(lum)
+    mu = (float(np.float32(lg.mean())), float(np.float32((lg * lg).mean())))
+    dl = 2 * _ulp32(lg)
+    vec, th = tiling(H, W)
+    Lb = forward_bound(lg, Lref, Lj2, Wj2, varj2, window_sums(lg, rx, ry), rx, ry, 0.1, "c32x2",
+                       vec, th, *mu, input_err=(dl, 2 * np.abs(lg) * dl + dl * dl))
+    ref = oracle.color_restore(rgb, lum, Lref, 0.6)
+    got = out.cpu().numpy().astype(np.float64)
+    c = np.maximum(rgb.astype(np.float64), 0.0)
+    lv = lum.astype(np.float64)
+    ratio = np.where(lv > 0, c / np.where(lv > 0, lv, 1.0), 1.0) ** 0.6
+    assert np.all(np.abs(got - ref) <= ratio * Lb[None] + 1e-6 * np.abs(ref) + 1e-30)
+
+
 @pytest.mark.slow
 def test_log_forward_4000x3000():
     # the 12 MP, 10^8:1 workload: whole image against the oracle's FP64 log-variance form
