@@ -47,7 +47,7 @@ def _parse():
                     help="after the timed loop, copy 1 GiB device-to-device once (a plain copy "
                          "kernel of known size, for calibrating HBM counters) and report its "
                          "bandwidth")
-    ap.add_argument("--workload", choices=["image", "batch", "precision", "sweep", "hdr"],
+    ap.add_argument("--workload", choices=["image", "batch", "sweep", "hdr"],
                     default="image",
                     help="image: one 4000x3000 image (default); batch: 64 images of uneven "
                          "size, launches replayed from a HIP graph; precision: output error "
@@ -136,67 +136,6 @@ def _median_ms(fn, reps=10, warmup=2):
     return sorted(ts)[len(ts) // 2]
 
 
-def bench_precision(args):
-    """Output error of each integral-image precision against the FP64 oracle on the whole
-    image: the paper set at 4000x3000 (10^8:1) and the n = 64, radii {4, 16, 64} stress set
-    at 1920x1080; for the paper set also the log-domain variance variant against the
-    oracle's FP64 log-variance form.  Each variant's whole forward (prologue, tables, query)
-    is timed beside its error."""
-    import numpy as np
-    import torch
-
-    import oracle
-    import paper_2102_01289_amd as tm
-    from synth import WORKLOADS, gen_wdr
-
-    dev = torch.device("cuda:0")
-    cases = [("wdr_4000x3000", 5, None), ("wdr_1920x1080", 64, [4, 16, 64])]
-    out = {"metric": "max-abs / p99.9 output error vs FP64 oracle per integral-image precision",
-           "data": "synthetic", "cases": []}
-    for name, n, radii in cases:
-        c = WORKLOADS[name]
-        H, W = c["H"], c["W"]
-        rgb = gen_wdr(H, W, c["K"], c["lo"], c["hi"], c["seed"]).rgb
-        lum = oracle.luminance(rgb)
-        e = oracle.exact_edges(lum.min(), lum.max(), n)
-        if radii is None:
-            rx, ry = oracle.paper_radii(H, W, 5)
-        else:
-            rx, ry = radii, radii
-        t0 = time.perf_counter()
-        ref = oracle.forward(lum, e, rx, ry, 0.1)
-        t_orc = time.perf_counter() - t0
-        p = tm.make_params(n, len(rx), rx, ry, 0.1)
-        case = {"workload": name, "n_bins": n, "radii_x": list(rx), "radii_y": list(ry),
-                "dynamic_range": float(lum.max() / lum.min()), "oracle_s": round(t_orc, 2),
-                "variants": {}}
-        refs = {"linear": ref}
-        variants = [(prec, "linear") for prec in ("f32", "c32x2", "f64")]
-        if radii is None:
-            refs["log"] = oracle.forward(lum, e, rx, ry, 0.1, var_domain="log")
-            variants += [(prec, "log") for prec in ("f32", "c32x2", "f64")]
-        x = torch.from_numpy(rgb).to(dev)
-        for prec, dom in variants:
-            m = tm.ToneMapper(H, W, p, prec, device=dev, variance=dom)
-            L = m.run(x).cpu().numpy().astype(np.float64)
-            G = m.hist.padded()[..., 0].numpy().astype(np.uint64)
-            exact = bool(np.array_equal(
-                G, oracle.integral_histogram(oracle.bins(lum, e), n, cumulative=True)))
-            err = np.abs(L - refs[dom])
-            ms = _median_ms(lambda: m.run(x), reps=10)
-            key = prec if dom == "linear" else f"log_{prec}"
-            case["variants"][key] = {
-                "max_abs": float(err.max()), "p99_9": float(np.quantile(err, 0.999)),
-                "mean_abs": float(err.mean()), "frac_above_1_255": float(np.mean(err > 1 / 255)),
-                "histogram_bit_exact": exact, "forward_ms": round(ms, 4),
-                "forward_mp_s": round(H * W / ms / 1e3, 1)}
-            del m
-            print(f"bench: {name} {key} max {err.max():.3e} {ms:.3f} ms", file=sys.stderr,
-                  flush=True)
-        out["cases"].append(case)
-    print(json.dumps(out), flush=True)
-
-
 def bench_hdr(args):
     """The multi-exposure front end at 4000x3000: four 8-bit exposures of the 12 MP workload's
     radiance (seeded camera model), response recovery from 200 sampled pixels, the radiance
@@ -235,8 +174,9 @@ def bench_hdr(args):
 
     chain_ms = _median_ms(chain, reps=args.steps)
     algo = (3 * P + 12) * H * W
-    # the oracle's merge of the same stack with the device's response, on the host
-    g_host = g.cpu().numpy().astype(np.float64)
+    # the oracle on the host: its own response from the same samples, then its merge (timed)
+    Z = [stack[:, ch].reshape(P, -1)[:, idx.cpu().numpy()].T for ch in range(3)]
+    g_host = np.stack([hdr.response(z, np.log(times), 100.0) for z in Z])
     t0 = time.perf_counter()
     hdr.merge(stack, g_host, np.log(times))
     orc_s = time.perf_counter() - t0
@@ -409,9 +349,6 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
-        return
-    if args.workload == "precision":
-        bench_precision(args)
         return
     if args.workload == "sweep":
         bench_sweep(args)
