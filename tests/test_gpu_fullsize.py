@@ -1,6 +1,7 @@
 """Parity at the full workload sizes, in the configuration bench.py times: 1920x1080 and
-4000x3000 forward (whole image against the FP64 oracle, histograms bit-exact) and the
-8 x 1024^2 forward + backward."""
+4000x3000 forward (whole image against the FP64 oracle, histograms bit-exact), the
+8 x 1024^2 forward + backward, and images of the 64-image uneven batch replayed from its
+HIP graph."""
 import numpy as np
 import pytest
 import torch
@@ -9,7 +10,7 @@ import oracle
 import paper_2102_01289_amd as tm
 from _bounds import forward_bound, tiling, window_sums
 from _cases import edges_ref, lum_ref, to_dev
-from synth import WORKLOADS, gen_upstream_grad, gen_wdr
+from synth import WORKLOADS, gen_batch_shapes, gen_upstream_grad, gen_wdr
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -88,3 +89,38 @@ def test_forward_backward_batch8_1024():
             assert np.allclose(gp.cpu().numpy(), gref, rtol=2e-4, atol=1e-6)
         else:
             assert np.all(np.isfinite(gv.cpu().numpy()))
+
+
+def test_batch64_uneven_against_the_oracle():
+    # the 64-image workload at its real sizes (H, W up to 4000), replayed from the HIP graph
+    # with the tiling the batch bench settles on; five images -- the largest, the smallest,
+    # the widest, the tallest and one more -- against the FP64 oracle at every pixel, within
+    # the derived per-pixel bound
+    cfg = WORKLOADS["wdr_batch64_uneven"]
+    shapes = gen_batch_shapes(cfg["count"], 360, 4000, seed=cfg["shape_seed"])
+    imgs = [to_dev(gen_wdr(h, w, cfg["K"], cfg["lo"], cfg["hi"], cfg["seed"] + i).rgb)
+            for i, (h, w) in enumerate(shapes)]
+    b = tm.Batch(imgs, 5, 5, 0.1, prec="c32x2", tune=tm.tune(0, 16, 4))
+    s = torch.cuda.Stream()
+    b.capture(s)
+    b.replay(s)
+    s.synchronize()
+    area = [h * w for h, w in shapes]
+    pick = {int(np.argmax(area)), int(np.argmin(area)),
+            int(np.argmax([w / h for h, w in shapes])), int(np.argmax([h / w for h, w in shapes])),
+            17}
+    for i in sorted(pick):
+        H, W = shapes[i]
+        rgb = imgs[i].cpu().numpy()
+        L = b.outs[i].cpu().numpy().astype(np.float64)
+        lum = lum_ref(rgb)
+        e = edges_ref(lum, 5)
+        rx, ry = oracle.paper_radii(H, W, 5)
+        Lref, Lj, Wj, varj = oracle.forward(lum, e, rx, ry, 0.1, per_scale=True)
+        vd = lum.astype(np.float64)
+        mu = (float(np.float32(vd.mean())), float(np.float32((vd * vd).mean())))
+        vec, th = tiling(H, W, th=16)
+        bound = forward_bound(lum, Lref, Lj, Wj, varj, window_sums(lum, rx, ry), rx, ry, 0.1,
+                              "c32x2", vec, th, *mu)
+        err = np.abs(L - Lref)
+        assert np.all(err <= bound), f"image {i} ({H}x{W}): max err {err.max():.3e}"
