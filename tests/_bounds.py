@@ -85,6 +85,26 @@ def _box_table(a):
     return t
 
 
+def var_bounds(lum, S1j, rx, ry, prec, vec, th, mu1=0.0, mu2=0.0, input_err=None):
+    """Per field, the per-pixel bound on |var_gpu - var_oracle| propagated from the four
+    corners' entry bounds (and input_err, see forward_bound)."""
+    H, W = lum.shape
+    e1, e2 = entry_bound(lum, prec, vec, th, mu1, mu2)
+    b1 = b2 = None
+    if input_err is not None:
+        b1, b2 = _box_table(input_err[0]), _box_table(input_err[1])
+    out = []
+    for j in range(len(rx)):
+        xm, xp, ym, yp, N = corners(H, W, rx[j], ry[j])
+        c1 = e1[ym, xm] + e1[ym, xp] + e1[yp, xm] + e1[yp, xp]
+        c2 = e2[ym, xm] + e2[ym, xp] + e2[yp, xm] + e2[yp, xp]
+        if b1 is not None:
+            c1 = c1 + (b1[yp, xp] - b1[ym, xp] - b1[yp, xm] + b1[ym, xm])
+            c2 = c2 + (b2[yp, xp] - b2[ym, xp] - b2[yp, xm] + b2[ym, xm])
+        out.append((c2 + 2.0 * np.abs(S1j[j] / N) * c1) / N)
+    return out
+
+
 def forward_bound(lum, Lref, Lj, Wj, varj, S1j, rx, ry, eps, prec, vec, th, mu1=0.0,
                   mu2=0.0, input_err=None):
     """Per-pixel bound on |L_gpu - L_oracle| (see module docstring).  lum is the image whose
@@ -92,25 +112,15 @@ def forward_bound(lum, Lref, Lj, Wj, varj, S1j, rx, ry, eps, prec, vec, th, mu1=
     terms q = v and q = v^2 may lie from the oracle's (when the two do not start from the
     same values), added to the table bounds through window sums."""
     H, W = lum.shape
-    e1, e2 = entry_bound(lum, prec, vec, th, mu1, mu2)
-    b1 = b2 = None
-    if input_err is not None:
-        b1, b2 = _box_table(input_err[0]), _box_table(input_err[1])
+    dv = var_bounds(lum, S1j, rx, ry, prec, vec, th, mu1, mu2, input_err)
     D = Wj.sum(axis=0)
     out = np.zeros((H, W))
     with np.errstate(divide="ignore", invalid="ignore"):
         for j in range(len(rx)):
-            xm, xp, ym, yp, N = corners(H, W, rx[j], ry[j])
-            c1 = e1[ym, xm] + e1[ym, xp] + e1[yp, xm] + e1[yp, xp]
-            c2 = e2[ym, xm] + e2[ym, xp] + e2[yp, xm] + e2[yp, xp]
-            if b1 is not None:
-                c1 = c1 + (b1[yp, xp] - b1[ym, xp] - b1[yp, xm] + b1[ym, xm])
-                c2 = c2 + (b2[yp, xp] - b2[ym, xp] - b2[yp, xm] + b2[ym, xm])
-            dvar = (c2 + 2.0 * np.abs(S1j[j] / N) * c1) / N
             sens = np.abs(Lj[j] - Lref) / D * eps / (varj[j] + eps) ** 2
             # with every weight near zero the first-order term is not a bound: count the whole
             # range as possible there
-            term = np.where(D > 0, sens * dvar, 1.0)
+            term = np.where(D > 0, sens * dv[j], 1.0)
             out += term
     return 4.0 * out + 4e-6
 
