@@ -20,11 +20,16 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "wdr_4000x3000"
+WORKLOAD = "wdr_4000x3000"        # the image the metric is quoted on
 PEAK_HBM_GBS = 8000.0
 # PMC summary of the roofline kernel (FETCH_SIZE and WRITE_SIZE per dispatch, calibrated on a
 # plain copy kernel), and the sources whose digest it records
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forward_kernel_wdr_4000x3000_traffic.md")
+IMAGES = ("wdr_4000x3000", "wdr_1920x1080", "wdr_256x256")
+
+
+def traffic_profile(workload: str) -> str:
+    """The committed counter summary of the fused query on one workload."""
+    return os.path.join(ROOT, "profiles", f"forward_kernel_{workload}_traffic.md")
 QUERY_SOURCES = ("paper_2102_01289_amd/csrc/tm_query.hip", "paper_2102_01289_amd/csrc/tm_device.h")
 # the kernel's parameter struct lives in the shared internal header
 QUERY_STRUCT = ("paper_2102_01289_amd/csrc/tm_internal.h", "struct FwdK {")
@@ -49,11 +54,14 @@ def _parse():
                          "bandwidth")
     ap.add_argument("--workload", choices=["image", "batch", "sweep", "hdr"],
                     default="image",
-                    help="image: one 4000x3000 image (default); batch: 64 images of uneven "
-                         "size, launches replayed from a HIP graph; precision: output error "
-                         "per integral-image precision; sweep: the paper's Table IV grid "
-                         "(n, s in {3, 4, 5} at 480x640, 720x1280, 1080x1920) with a per-stage "
-                         "split")
+                    help="image: one image (--image, 4000x3000 by default); batch: 64 images "
+                         "of uneven size, launches replayed from a HIP graph; sweep: the "
+                         "paper's Table IV grid (n, s in {3, 4, 5} at 480x640, 720x1280, "
+                         "1080x1920) with a per-stage split; hdr: the multi-exposure front end "
+                         "at 4000x3000")
+    ap.add_argument("--image", choices=IMAGES, default=WORKLOAD,
+                    help="the image of the image workload (the metric is quoted on "
+                         "wdr_4000x3000)")
     return ap.parse_args()
 
 
@@ -290,13 +298,14 @@ def query_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(variant: str, prec: str, n_bins: int, n_scales: int):
+def measured_traffic(variant: str, prec: str, n_bins: int, n_scales: int,
+                     workload: str = WORKLOAD):
     """HBM bytes per launch of the fused query from the committed counter summary: FETCH_SIZE
     and WRITE_SIZE (KiB per dispatch) each times its copy-kernel calibration factor.  None when
     no record matches this configuration or the kernel's sources changed since the counters
     were taken."""
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(traffic_profile(workload)) as f:
             lines = f.read().splitlines()
     except OSError:
         return None
@@ -306,7 +315,7 @@ def measured_traffic(variant: str, prec: str, n_bins: int, n_scales: int):
             continue
         r = json.loads(ln[len("traffic-record: "):])
         if (r["variant"], r["prec"], r["n_bins"], r["n_scales"], r["workload"]) != (
-                variant, prec, n_bins, n_scales, WORKLOAD):
+                variant, prec, n_bins, n_scales, workload):
             continue
         if r["source_digest"] != digest:
             return None
@@ -363,7 +372,7 @@ def main():
     import paper_2102_01289_amd as tm
     from synth import WORKLOADS, gen_upstream_grad, gen_wdr
 
-    cfg = WORKLOADS[WORKLOAD]
+    cfg = WORKLOADS[args.image]
     H, W = cfg["H"], cfg["W"]
     img = gen_wdr(H, W, cfg["K"], cfg["lo"], cfg["hi"], cfg["seed"])
     dev = torch.device("cuda:0")
@@ -461,7 +470,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"c32x2": "f32x2", "f32": "f32", "f64": "f64"}[args.prec],
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "height": H, "width": W, "n_bins": args.n_bins,
+        "config": {"workload": args.image, "height": H, "width": W, "n_bins": args.n_bins,
                    "n_scales": args.n_scales, "eps": args.eps, "sat_precision": args.prec,
                    "radii_x": list(params.rx[:args.n_scales]),
                    "radii_y": list(params.ry[:args.n_scales]),
@@ -479,7 +488,7 @@ def main():
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic("train" if do_bwd else "forward", args.prec,
-                                                 args.n_bins, args.n_scales),
+                                                 args.n_bins, args.n_scales, args.image),
                      "algorithmic_bytes_per_launch": qbytes,
                      "avg_kernel_ms": round(q_ms, 4)},
     }
