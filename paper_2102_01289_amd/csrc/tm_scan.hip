@@ -395,11 +395,11 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
 }
 
 // ================================================================ stage 2
-// Exclusive prefix of n values at stride `stride`, the loads issued 32 at a time so that
-// the scan's add chain does not serialise the memory latency (a column chain of a 1080-row
-// image with 4-row tiles is 270 values; stage 2 runs far fewer threads than the GPU holds,
-// so its time is the number of load round trips in the longest chain).  src and dst do not
-// overlap.
+// Exclusive prefix of n values at stride `stride`, one thread, the loads issued 32 at a time
+// so that the scan's add chain does not serialise the memory latency (stage 2 runs far fewer
+// threads than the GPU holds, so its time is the number of load round trips in the longest
+// chain).  Used for the chains along tx (tiles_x long); the long chains along ty are split
+// across lanes below.  src and dst do not overlap.
 template <class A, class T>
 __device__ __forceinline__ void excl_scan(const T *__restrict__ src, T *__restrict__ dst, int n,
                                           int64_t stride) {
@@ -433,15 +433,135 @@ __device__ __forceinline__ void excl_scan(const T *__restrict__ src, T *__restri
     }
 }
 
-// Item id in [0, nq H) scans RS along tx for one (quantity, row); [nq H, nq H + nq W) scans
-// CS along ty for one (quantity, column); the rest scan TT along tx for one (quantity, ty).
+// The column chains (one per quantity and image column, tiles_y long) are the long ones:
+// each is split into kSegs segments on lanes c, c + 8, ..., c + 56 of one wave (8 chains per
+// wave).  A lane loads its segment (up to kSegMax values held in registers) and sums it, the
+// segment totals get an exclusive prefix across the chain's lanes (three shuffle steps), and
+// the lane scans its segment from that carry: one round trip of loads instead of tiles_y / 32.
+// Longer segments are summed and then rescanned from memory.
+constexpr int kSegs = 8;
+constexpr int kChainsPerWave = kWave / kSegs;
+constexpr int kSegMax = 32;
+
+__device__ __forceinline__ float shfl_up_v(float v, int d) { return __shfl_up(v, d); }
+__device__ __forceinline__ double shfl_up_v(double v, int d) { return __shfl_up(v, d); }
+__device__ __forceinline__ uint32_t shfl_up_v(uint32_t v, int d) {
+    return (uint32_t)__shfl_up((int)v, d);
+}
+__device__ __forceinline__ f2 shfl_up_v(f2 v, int d) {
+    return f2{shfl_up_v(v.hi, d), shfl_up_v(v.lo, d)};
+}
+
+// Sum of src[t * stride] for t in [b, e), loads issued 32 at a time, added in order.
+template <class A, class T>
+__device__ __forceinline__ T range_sum(const T *__restrict__ src, int b, int e, int64_t stride) {
+    constexpr int kB = 32;
+    T run = A::zero();
+    int t = b;
+    for (; t + kB <= e; t += kB) {
+        T a[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) a[u] = src[(int64_t)(t + u) * stride];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) run = A::add(run, a[u]);
+    }
+    for (; t < e; ++t) run = A::add(run, src[(int64_t)t * stride]);
+    return run;
+}
+
+// Exclusive prefix of src over [b, e) starting from `run`, written to dst.
+template <class A, class T>
+__device__ __forceinline__ void range_scan(const T *__restrict__ src, T *__restrict__ dst, int b,
+                                           int e, int64_t stride, T run) {
+    constexpr int kB = 32;
+    int t = b;
+    for (; t + kB <= e; t += kB) {
+        T a[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) a[u] = src[(int64_t)(t + u) * stride];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            dst[(int64_t)(t + u) * stride] = run;
+            run = A::add(run, a[u]);
+        }
+    }
+    for (; t < e; ++t) {
+        const T a = src[(int64_t)t * stride];
+        dst[(int64_t)t * stride] = run;
+        run = A::add(run, a);
+    }
+}
+
+// One lane's part of a segmented column chain of n values (seg = lane / 16).  Every lane of
+// the wave calls this (inactive lanes with active = false) so that the shuffles see all.
+template <class A, class T>
+__device__ __forceinline__ T seg_carry(T total, int seg) {
+    T inc = total;
+#pragma unroll
+    for (int d = 1; d < kSegs; d *= 2) {
+        const T up = shfl_up_v(inc, d * kChainsPerWave);
+        if (seg >= d) inc = A::add(up, inc);
+    }
+    const T carry = shfl_up_v(inc, kChainsPerWave);
+    return seg == 0 ? A::zero() : carry;
+}
+
+template <class A, class T>
+__device__ __forceinline__ void seg_excl_scan(const T *__restrict__ src, T *__restrict__ dst,
+                                              int n, int64_t stride, int seg, bool active) {
+    const int len = (n + kSegs - 1) / kSegs;   // chain-uniform
+    const int b = min(n, seg * len), e = min(n, b + len);
+    if (len <= kSegMax) {
+        T a[kSegMax];
+        T tot = A::zero();
+#pragma unroll
+        for (int u = 0; u < kSegMax; ++u)
+            a[u] = (active && b + u < e) ? src[(int64_t)(b + u) * stride] : A::zero();
+#pragma unroll
+        for (int u = 0; u < kSegMax; ++u) tot = A::add(tot, a[u]);
+        T run = seg_carry<A>(tot, seg);
+        if (active) {
+#pragma unroll
+            for (int u = 0; u < kSegMax; ++u) {
+                if (b + u < e) dst[(int64_t)(b + u) * stride] = run;
+                run = A::add(run, a[u]);
+            }
+        }
+    } else {
+        const T tot = active ? range_sum<A>(src, b, e, stride) : A::zero();
+        const T carry = seg_carry<A>(tot, seg);
+        if (active) range_scan<A>(src, dst, b, e, stride, carry);
+    }
+}
+
+__host__ __device__ constexpr int64_t round64(int64_t a) { return (a + 63) / 64 * 64; }
+
+// Stage-2 work items of one image: [0, n1) scan RS along tx for one (quantity, row), padded
+// to whole waves; then waves of 16 column chains x 4 segments scan CS along ty; then items
+// scan TT along tx for one (quantity, ty).  The total is a whole number of waves, so in a
+// batch every image's items start on a wave boundary.
+struct Stage2Split {
+    int64_t n1, n1p, groups, n2, n3, total;
+};
+__host__ __device__ inline Stage2Split stage2_split(const ScanK &k, bool sat) {
+    Stage2Split q;
+    const int64_t nq = (sat ? 2 : 0) + k.n_planes;
+    q.n1 = nq * k.H;
+    q.n1p = round64(q.n1);
+    q.groups = (k.W + kChainsPerWave - 1) / kChainsPerWave;
+    q.n2 = nq * q.groups * kWave;
+    q.n3 = nq * k.tiles_y;
+    q.total = round64(q.n1p + q.n2 + q.n3);
+    return q;
+}
+
 template <int P, bool SAT>
 __device__ __forceinline__ void stage2_item(const ScanK &k, int64_t idx) {
     using A = Acc<P>;
     using T = typename A::T;
     const int nq_sat = SAT ? 2 : 0;
-    const int nq = nq_sat + k.n_planes;
-    const int64_t n1 = (int64_t)nq * k.H, n2 = (int64_t)nq * k.W;
+    const Stage2Split sp = stage2_split(k, SAT);
+    const int64_t n1 = sp.n1;
     if (idx < n1) {
         // XC[q][y][tx] = sum_{tx' < tx} RS[q][y][tx']
         const int q = (int)(idx / k.H);
@@ -454,23 +574,30 @@ __device__ __forceinline__ void stage2_item(const ScanK &k, int64_t idx) {
             const int64_t o = ((int64_t)(q - nq_sat) * k.H + y) * k.tiles_x;
             excl_scan<AddU32>(k.rs_h + o, k.xc_h + o, k.tiles_x, 1);
         }
-    } else if (idx < n1 + n2) {
-        // CSE[q][ty][x] = sum_{ty' < ty} CS[q][ty'][x]
-        const int64_t id = idx - n1;
-        const int q = (int)(id / k.W);
-        const int64_t x = id % k.W;
-        if (q < nq_sat) {
-            const int64_t o = (int64_t)q * k.tiles_y * k.W + x;
-            excl_scan<A>(reinterpret_cast<const T *>(k.cs_sat) + o,
-                         reinterpret_cast<T *>(k.cse_sat) + o, k.tiles_y, k.W);
+    } else if (idx < sp.n1p) {
+        return;   // padding to a whole wave
+    } else if (idx < sp.n1p + sp.n2) {
+        // CSE[q][ty][x] = sum_{ty' < ty} CS[q][ty'][x], one wave per (q, 16 columns)
+        const int64_t id = idx - sp.n1p;
+        const int lane = (int)(id & (kWave - 1));
+        const int64_t wv = id >> 6;
+        const int q = (int)(wv / sp.groups);
+        const int64_t x = (wv % sp.groups) * kChainsPerWave + (lane & (kChainsPerWave - 1));
+        const int seg = lane / kChainsPerWave;
+        const bool active = x < k.W;
+        const int64_t xa = active ? x : 0;
+        if (q < nq_sat) {   // wave-uniform
+            const int64_t o = (int64_t)q * k.tiles_y * k.W + xa;
+            seg_excl_scan<A>(reinterpret_cast<const T *>(k.cs_sat) + o,
+                             reinterpret_cast<T *>(k.cse_sat) + o, k.tiles_y, k.W, seg, active);
         } else {
-            const int64_t o = (int64_t)(q - nq_sat) * k.tiles_y * k.W + x;
-            excl_scan<AddU32>(k.cs_h + o, k.cse_h + o, k.tiles_y, k.W);
+            const int64_t o = (int64_t)(q - nq_sat) * k.tiles_y * k.W + xa;
+            seg_excl_scan<AddU32>(k.cs_h + o, k.cse_h + o, k.tiles_y, k.W, seg, active);
         }
     } else {
         // TTE[q][ty][tx] = sum_{tx' < tx} TT[q][ty][tx']
-        const int64_t id = idx - n1 - n2;
-        if (id >= (int64_t)nq * k.tiles_y) return;
+        const int64_t id = idx - sp.n1p - sp.n2;
+        if (id >= sp.n3) return;
         const int q = (int)(id / k.tiles_y);
         const int64_t ty = id % k.tiles_y;
         if (q < nq_sat) {
@@ -1037,10 +1164,7 @@ ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws) {
     return k;
 }
 
-int64_t scan_stage2_items(const ScanK &k, bool sat) {
-    const int64_t nq = (sat ? 2 : 0) + k.n_planes;
-    return nq * ((int64_t)k.H + k.W + k.tiles_y);
-}
+int64_t scan_stage2_items(const ScanK &k, bool sat) { return stage2_split(k, sat).total; }
 
 hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipStream_t s) {
     const ScanK k = make_scank(a, plan, ws);
