@@ -441,7 +441,7 @@ __device__ __forceinline__ void excl_scan(const T *__restrict__ src, T *__restri
 // Longer segments are summed and then rescanned from memory.
 constexpr int kSegs = 8;
 constexpr int kChainsPerWave = kWave / kSegs;
-constexpr int kSegMax = 32;
+constexpr int kSegMax = 48;
 
 __device__ __forceinline__ float shfl_up_v(float v, int d) { return __shfl_up(v, d); }
 __device__ __forceinline__ double shfl_up_v(double v, int d) { return __shfl_up(v, d); }
