@@ -30,7 +30,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kRows = kBlock / kWave;
 constexpr int kS = 8;            // TM_MAX_SCALES
-constexpr int kChunk = 64;       // rows per partial of the column sums
+constexpr int kChunkMax = 64;    // rows per partial of the column sums, at most
 
 struct BwdK {
     const float *v;
@@ -46,7 +46,7 @@ struct BwdK {
     double *Cb;      // [2][s][W]  column range sums
     double2 *Dr;     // [H][W] deposits {D1, D2} in reversed order
     double *part;    // [ncol * nchunks][3] scalar partials
-    int tiles_x, p4, teeth, nchunks;
+    int tiles_x, p4, teeth, nchunks, chunk;
 };
 
 // Residual pair plane of field j: {R1_j, R2_j} per pixel, pitch W.
@@ -78,7 +78,7 @@ __device__ Sum3 block_sum3(Sum3 v) {
 }
 
 // (1) One streaming pass over g, the residual pairs, E and Pbar, one block per (64 columns,
-// kChunk rows):
+// chunk rows):
 //   Rp[q][j][ct][y] = sum over the tile's columns x >= W-1-rx_j of g R_qj(x, y),
 //   Cp[q][j][chunk][x] = sum over the tile's rows y >= H-1-ry_j of g R_qj(x, y),
 //   part[block] = {sum g E, sum g (1 - Pbar), sum g Pbar},
@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
     const int ncol = (k.W + kWave - 1) / kWave;
     const int ct = blockIdx.x % ncol, ch = blockIdx.x / ncol;
     const int x = ct * kWave + lane_id(), w = wave_id();
-    const int y0 = ch * kChunk, y1 = min(k.H, y0 + kChunk);
+    const int y0 = ch * k.chunk, y1 = min(k.H, y0 + k.chunk);
     const int64_t hw = (int64_t)k.H * k.W;
     const float *E = k.R + 2 * (int64_t)s * hw, *Pb = E + hw;
     int lox[kS], loy[kS];
@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
         loy[j] = j < s ? max(k.H - 1 - k.p.ry[j], 0) : k.H;
         cacc[0][j] = cacc[1][j] = 0.0;
     }
-    __shared__ double shr[2 * kS][kChunk];
+    __shared__ double shr[2 * kS][kChunkMax];
     Sum3 sacc{0.0, 0.0, 0.0};
     const int xc = min(x, k.W - 1);      // in-image address for the lanes past the edge
     const bool in = x < k.W;
@@ -340,7 +340,11 @@ BwdPlan make_bwd_plan(int H, int W, int n_scales, const int *ry, bool with_resid
     const int tiles_x = (W + kWave - 1) / kWave;
     comb_params(H, kRows, ry, n_scales, &b.p4, &b.teeth);
     b.nblocks = (int64_t)tiles_x * b.p4 * b.teeth;
-    b.nchunks = (H + kChunk - 1) / kChunk;
+    // rows per block of the border pass: 64, halved (down to 16) while the pass would have
+    // fewer than 2048 blocks, so that smaller images still fill the GPU
+    b.chunk = kChunkMax;
+    while (b.chunk > 16 && (int64_t)tiles_x * ((H + b.chunk - 1) / b.chunk) < 2048) b.chunk /= 2;
+    b.nchunks = (H + b.chunk - 1) / b.chunk;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -383,6 +387,7 @@ hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, voi
     k.p4 = plan.p4;
     k.teeth = plan.teeth;
     k.nchunks = plan.nchunks;
+    k.chunk = plan.chunk;
     const int S = a.p.n_scales;
     const unsigned nbs = (unsigned)(k.tiles_x * plan.nchunks);
     hipLaunchKernelGGL(border_scalar_kernel, dim3(nbs), dim3(kBlock), 0, s, k);

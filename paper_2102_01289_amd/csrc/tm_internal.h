@@ -238,7 +238,7 @@ struct BwdResidArgs {
 };
 struct BwdPlan {
     int64_t nblocks;
-    int p4, teeth, nchunks;
+    int p4, teeth, nchunks, chunk;
     size_t resid, Rp, Rb, Cp, Cb, Dr, part, scan, total;
     ScanPlan scan_plan;
 };
