@@ -190,7 +190,7 @@ __device__ __forceinline__ float merge_px(float num, float den, float plain, flo
     return den > 0.f ? num / den : plain * inv_p;
 }
 
-// Add one exposure's eight values (packed in v, pixel u in byte u) to the sums of a group.
+// The running sums of one group of kPx pixels: sum w (g - ln dt), sum w, sum (g - ln dt).
 struct Acc8 {
     float num[kPx], den[kPx], plain[kPx];
 };
@@ -200,6 +200,7 @@ __device__ __forceinline__ void acc_init(Acc8 &a) {
     for (int u = 0; u < kPx; ++u) a.num[u] = a.den[u] = a.plain[u] = 0.f;
 }
 
+// Add one exposure's eight values (packed in v, pixel u in byte u) to the sums of a group.
 __device__ __forceinline__ void acc_add(Acc8 &a, const float *gc, float tj, const uint2 v) {
     const uint32_t wv[2] = {v.x, v.y};
 #pragma unroll
