@@ -353,8 +353,8 @@ def cpu_baseline(rgb, params_np, backward: bool):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "see DESIGN.md for how the path would shard", file=sys.stderr)
+        print(f"bench.py: the tone-mapping path runs on one GPU only (asked for --gpus "
+              f"{args.gpus}); sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
@@ -457,6 +457,10 @@ def main():
     qbytes = query_bytes_per_px(args.prec, args.n_bins,
                                 tm.residual_planes(args.n_scales) if do_bwd else 0) * H * W
     achieved = qbytes / (q_ms * 1e-3) / 1e9
+    traffic = measured_traffic("train" if do_bwd else "forward", args.prec, args.n_bins,
+                               args.n_scales, args.image)
+    # counted HBM rate: the calibrated counter bytes per launch over the live duration
+    traffic_gbs = traffic / (q_ms * 1e-3) / 1e9 if traffic else None
     line = {
         "metric": "megapixels/s fwd and fwd+bwd at 12MP vs plain fwd; HBM GB/s fraction",
         "value": round(mpx / (ms_step * 1e-3), 3),
@@ -487,8 +491,10 @@ def main():
                      "forward_kernel (fused query+blend)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic("train" if do_bwd else "forward", args.prec,
-                                                 args.n_bins, args.n_scales, args.image),
+                     "traffic": traffic,
+                     "traffic_gbs": round(traffic_gbs, 1) if traffic_gbs else None,
+                     "traffic_frac": round(traffic_gbs / PEAK_HBM_GBS, 4) if traffic_gbs
+                     else None,
                      "algorithmic_bytes_per_launch": qbytes,
                      "avg_kernel_ms": round(q_ms, 4)},
     }

@@ -52,7 +52,7 @@ typedef enum {
     TM_ERR_ALIGN = -3,        /* pointer not aligned as documented */
     TM_ERR_WORKSPACE = -4,    /* ws NULL, misaligned or smaller than required */
     TM_ERR_HIP = -5,          /* a HIP runtime call failed */
-    TM_ERR_UNSUPPORTED = -6   /* valid request this build does not implement */
+    TM_ERR_UNSUPPORTED = -6   /* valid request the library does not implement */
 } tm_status;
 
 /* Storage and accumulation of the integral images of i and i^2 (Eq. 5).

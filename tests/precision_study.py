@@ -1,4 +1,4 @@
-"""Precision study (run as a script on a GPU machine, not collected by pytest): the output error
+"""Precision study (run as a script on a machine with the GPU, not collected by pytest): the output error
 of each integral-image precision against the FP64 oracle on whole images -- the paper set at
 4000x3000 (10^8:1) and the n = 64, radii {4, 16, 64} stress set at 1920x1080 -- and, for
 the paper set, the log-domain variance variant against the oracle's FP64 log-variance form.
