@@ -33,7 +33,9 @@
  *   - Every argument is checked on the host before anything is launched; a failed check
  *     returns a negative tm_status and launches nothing.  HIP launch errors map to
  *     TM_ERR_HIP.  No C++ exception crosses this interface.
- *   - Sizes: 1 <= H, W; H*W < 2^31; every table and plane holds < 2^31 entries.
+ *   - Sizes: 1 <= H; 1 <= W <= TM_MAX_WIDTH (2^24, so that every per-lane byte offset
+ *     along a table row fits in 32 bits); H*W < 2^31; every table and plane holds
+ *     < 2^31 entries.
  */
 #ifndef TM_H
 #define TM_H
@@ -72,6 +74,7 @@ typedef enum { TM_SAT_F32 = 0, TM_SAT_C32X2 = 1, TM_SAT_F64 = 2 } tm_sat_prec;
  * Plane p (0-based) starts at hist + p * plane_stride. */
 typedef enum { TM_HIST_PER_BIN = 0, TM_HIST_CUMULATIVE = 1 } tm_hist_layout;
 
+#define TM_MAX_WIDTH (1 << 24)
 #define TM_MAX_SCALES 8
 #define TM_MAX_BINS 256
 

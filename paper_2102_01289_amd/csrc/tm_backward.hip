@@ -262,17 +262,20 @@ __global__ void __launch_bounds__(kBlock) deposit_kernel(BwdK k) {
         const int rx = k.p.rx[j], ry = k.p.ry[j];
         const int ax = max(cx - rx, 0), bx = min(cx + rx + 1, k.W - 1);
         const int ay = max(cy - ry, 0), by = min(cy + ry + 1, k.H - 1);
-        const float2 *Rj = rpair(k, j);
-        const float2 *Ra = Rj + (int64_t)ay * k.W, *Rb_ = Rj + (int64_t)by * k.W;
-        const float *ga = k.g + (int64_t)ay * k.ld_g, *gb = k.g + (int64_t)by * k.ld_g;
-        rv[j][0] = Ra[ax];
-        rv[j][1] = Ra[bx];
-        rv[j][2] = Rb_[ax];
-        rv[j][3] = Rb_[bx];
-        gw[j][0] = ga[ax];
-        gw[j][1] = ga[bx];
-        gw[j][2] = gb[ax];
-        gw[j][3] = gb[bx];
+        // corner rows are wave-uniform: scalar row bases, 32-bit lane offsets
+        const char *Rj = reinterpret_cast<const char *>(rpair(k, j));
+        const char *Ra = Rj + (int64_t)ay * k.W * 8, *Rb_ = Rj + (int64_t)by * k.W * 8;
+        const char *ga = reinterpret_cast<const char *>(k.g + (int64_t)ay * k.ld_g);
+        const char *gb = reinterpret_cast<const char *>(k.g + (int64_t)by * k.ld_g);
+        const uint32_t oa = (uint32_t)ax, ob = (uint32_t)bx;
+        rv[j][0] = load_at<float2>(Ra, oa * 8u);
+        rv[j][1] = load_at<float2>(Ra, ob * 8u);
+        rv[j][2] = load_at<float2>(Rb_, oa * 8u);
+        rv[j][3] = load_at<float2>(Rb_, ob * 8u);
+        gw[j][0] = load_at<float>(ga, oa * 4u);
+        gw[j][1] = load_at<float>(ga, ob * 4u);
+        gw[j][2] = load_at<float>(gb, oa * 4u);
+        gw[j][3] = load_at<float>(gb, ob * 4u);
     }
 #pragma unroll
     for (int j = 0; j < S; ++j) {

@@ -96,7 +96,8 @@ tm_status check(const tm_image_desc *d, int32_t count, const tm_params *p, tm_sa
         return TM_ERR_ARG;
     for (int i = 0; i < count; ++i) {
         const tm_image_desc &x = d[i];
-        if (x.H < 1 || x.W < 1 || (int64_t)x.H * x.W >= ((int64_t)1 << 31)) return TM_ERR_SHAPE;
+        if (x.H < 1 || x.W < 1 || x.W > TM_MAX_WIDTH || (int64_t)x.H * x.W >= ((int64_t)1 << 31))
+            return TM_ERR_SHAPE;
         if (!x.rgb || !x.out) return TM_ERR_ARG;
         if (x.ld_rgb < x.W || x.ld_out < x.W || x.ch_stride < (int64_t)x.H * x.ld_rgb)
             return TM_ERR_SHAPE;

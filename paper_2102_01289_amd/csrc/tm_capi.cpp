@@ -17,7 +17,7 @@ constexpr int64_t kMaxEntries = (int64_t)1 << 31;
 bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 
 tm_status check_image(int32_t H, int32_t W) {
-    if (H < 1 || W < 1) return TM_ERR_SHAPE;
+    if (H < 1 || W < 1 || W > TM_MAX_WIDTH) return TM_ERR_SHAPE;
     if ((int64_t)H * W >= kMaxEntries) return TM_ERR_SHAPE;
     return TM_OK;
 }

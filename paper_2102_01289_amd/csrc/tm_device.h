@@ -30,6 +30,13 @@ __device__ __forceinline__ TM_GLOBAL T *gptr(T *p) {
     return (TM_GLOBAL T *)p;
 }
 
+// Load at a wave-uniform row base plus a per-lane unsigned 32-bit byte offset, the form
+// the global_load "saddr + voffset" addressing takes directly (no 64-bit lane arithmetic).
+template <typename T>
+__device__ __forceinline__ T load_at(const char *row, uint32_t off) {
+    return *reinterpret_cast<const TM_GLOBAL T *>(gptr(row) + off);
+}
+
 // ------------------------------------------------------------------ DPP moves (GFX9)
 // dpp_ctrl encodings: row_shr:n = 0x110 + n, wave_shr:1 = 0x138, row_bcast:15 = 0x142,
 // row_bcast:31 = 0x143.  Lanes whose source is outside the row/wave, or that row_mask /
@@ -184,15 +191,15 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
-// ------------------------------------------------------------------ blockIdx -> tile
-// Workgroups are dispatched to the 8 XCDs round-robin by block index.  Remap so that each
-// XCD receives one contiguous range of tiles, keeping neighbouring tiles (which share
-// table rows) in one XCD's L2.  The map is a bijection on [0, nblocks).
 // Index of the calling wave inside its block, as a wave-uniform (scalar) value.
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
 }
 
+// ------------------------------------------------------------------ blockIdx -> tile
+// Workgroups are dispatched to the 8 XCDs round-robin by block index.  Remap so that each
+// XCD receives one contiguous range of tiles, keeping neighbouring tiles (which share
+// table rows) in one XCD's L2.  The map is a bijection on [0, nblocks).
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
     constexpr uint32_t kXcd = 8;
     uint32_t q = nblocks / kXcd, r = nblocks % kXcd;

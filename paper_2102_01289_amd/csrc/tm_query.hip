@@ -26,13 +26,6 @@ template <int P> struct SatEntry { using T = float2; };     // {I1, I2}
 template <> struct SatEntry<kC32x2> { using T = float4; };  // {I1.hi, I1.lo, I2.hi, I2.lo}
 template <> struct SatEntry<kF64> { using T = double2; };
 
-// Load at a wave-uniform row base plus a per-lane unsigned 32-bit byte offset, the form
-// the global_load "saddr + voffset" addressing takes directly (no 64-bit lane arithmetic).
-template <typename T>
-__device__ __forceinline__ T load_at(const char *row, uint32_t off) {
-    return *reinterpret_cast<const TM_GLOBAL T *>(gptr(row) + off);
-}
-
 // Window mean m and variance var (Eq. 10 read as the population variance, not yet clamped)
 // from the four corner entries of the interleaved integral image and the reciprocal of the
 // window area.  The corner sums cancel heavily (large quadrant sums, small window sums), so

@@ -76,6 +76,8 @@ def test_argument_checks_return_before_launch():
     # bad shapes / pointers
     assert lib.tm_luminance(fake, 100, 10, 0, 10, fake, 10, null) == -2
     assert lib.tm_luminance(null, 100, 10, 10, 10, fake, 10, null) == -1
+    wide = (1 << 24) + 1                                  # one column past TM_MAX_WIDTH
+    assert lib.tm_luminance(fake, 2 * wide, wide, 1, wide, fake, wide, null) == -2
     assert lib.tm_luminance(fake, 10, 10, 10, 10, fake, 10, null) == -2     # ch_stride < H*ld
     assert lib.tm_image_stats(fake, 10, 10, 10, 0, fake, null, null, fake, 1 << 20, null) == -1
     assert lib.tm_image_stats(fake, 10, 10, 10, 257, fake, null, null, fake, 1 << 20, null) == -1
