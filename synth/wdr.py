@@ -19,7 +19,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["WdrImage", "gen_wdr", "gen_batch_shapes", "gen_upstream_grad", "WORKLOADS"]
+__all__ = ["WdrImage", "gen_wdr", "gen_wdr_row", "gen_batch_shapes", "gen_upstream_grad", "WORKLOADS"]
 
 
 @dataclass(frozen=True)
@@ -79,6 +79,27 @@ def gen_wdr(H: int, W: int, K: int = 8, lo: float = -2.0, hi: float = 4.0,
     for c in range(3):
         rgb[c] = (Y * chroma[dom, c]).astype(np.float32)
     return WdrImage(rgb=rgb, seed=seed, blobs=K, lo=lo, hi=hi)
+
+
+def gen_wdr_row(W: int, K: int = 8, lo: float = -2.0, hi: float = 4.0,
+                seed: int = 0) -> np.ndarray:
+    """One seeded WDR luminance row [W] (float32): the recipe above along one axis, with
+    sigma ~ U(0.03, 0.25) * W and no colour.  Broadcast down the rows, it gives an image whose
+    every row is the same, for tests at sizes the oracle cannot cover in two dimensions."""
+    if W < 1 or K < 1:
+        raise ValueError("W and K must be positive")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cx = rng.uniform(0.0, W, size=K)
+    sig = rng.uniform(0.03, 0.25, size=K) * W
+    amp = rng.uniform(0.2, 1.0, size=K)
+    xs = np.arange(W, dtype=np.float64)
+    F = np.zeros(W)
+    for k in range(K):
+        F += amp[k] * np.exp(-((xs - cx[k]) ** 2) / (2.0 * sig[k] * sig[k]))
+    fmin, fmax = float(F.min()), float(F.max())
+    F = (F - fmin) / (fmax - fmin) if fmax > fmin else np.zeros_like(F)
+    noise = rng.standard_normal(W) * 0.05
+    return np.power(10.0, lo + (hi - lo) * F + noise).astype(np.float32)
 
 
 def gen_batch_shapes(count: int, lo: int = 360, hi: int = 4000, seed: int = 0):
