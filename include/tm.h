@@ -266,10 +266,10 @@ int32_t tm_residual_planes(int32_t n_scales);
  *   R1_j = -2 c_j (S1_j/N_j) / N_j,  R2_j = c_j / N_j          (j < s)
  *   E    = sum_j (L_j - L)/D (-var_j/(var_j + eps)^2)
  *   Pbar = sum_j W_j P_j / D (mean of P_j where D = 0)
- * resid: tm_residual_planes(s) * H * W FP32 values, caller-owned, laid out as s interleaved
- * pair planes (pair plane j starts at resid + 2*j*H*W and holds {R1_j, R2_j} of pixel (x, y)
- * at offset 2*(y*W + x)), then the E plane at resid + 2*s*H*W and the Pbar plane at
- * resid + (2*s + 1)*H*W (pitch W).
+ * resid: tm_residual_planes(s) * H * W FP32 values, caller-owned, 8-byte aligned (else
+ * TM_ERR_ALIGN), laid out as s interleaved pair planes (pair plane j starts at
+ * resid + 2*j*H*W and holds {R1_j, R2_j} of pixel (x, y) at offset 2*(y*W + x)), then the
+ * E plane at resid + 2*s*H*W and the Pbar plane at resid + (2*s + 1)*H*W (pitch W).
  * A window of one pixel has zero variance by definition. */
 tm_status tm_tonemap_forward_train(const float *v, int64_t ld_v, int32_t H, int32_t W,
                                    const void *sat, int64_t ld_sat, tm_sat_prec prec,

@@ -487,7 +487,7 @@ tm_status tm_tonemap_forward_train(const float *v, int64_t ld_v, int32_t H, int3
                                    const tm_params *p, float *out, int64_t ld_out, float *resid,
                                    void *stream) {
     if (!resid) return TM_ERR_ARG;
-    if (!aligned(resid, 4)) return TM_ERR_ALIGN;
+    if (!aligned(resid, 8)) return TM_ERR_ALIGN;   // pair planes are read as 8-byte pairs
     TM_TRY(check_image(H, W));
     TM_TRY(check_params(p));
     if (!v || !out || !valid_prec(prec)) return TM_ERR_ARG;
@@ -556,7 +556,7 @@ tm_status tm_tonemap_backward_resid(const float *v, int64_t ld_v, int32_t H, int
                                     size_t ws_bytes, void *stream) {
     TM_TRY(check_bwd_common(v, ld_v, H, W, p, grad_out, ld_g, grad_v, ld_gv, grad_params));
     if (!resid) return TM_ERR_ARG;
-    if (!aligned(resid, 4)) return TM_ERR_ALIGN;
+    if (!aligned(resid, 8)) return TM_ERR_ALIGN;   // pair planes are read as 8-byte pairs
     BwdPlan plan = make_bwd_plan(H, W, p->n_scales, p->ry, false);
     TM_TRY(check_ws(ws, ws_bytes, plan.total));
     return run_backward_resid(v, ld_v, H, W, p, resid, grad_out, ld_g, grad_v, ld_gv,

@@ -112,6 +112,19 @@ def test_argument_checks_return_before_launch():
                                   ctypes.byref(p), fake, 10, null) == -1
 
 
+def test_residual_planes_must_be_8_byte_aligned():
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    fake = P(1 << 20)
+    odd = P((1 << 20) + 4)                          # 4-byte aligned only
+    null = P(0)
+    p = _params()
+    assert lib.tm_tonemap_forward_train(fake, 10, 10, 10, fake, 64, 1, fake, fake, 64, 1 << 12,
+                                        fake, ctypes.byref(p), fake, 10, odd, null) == -3
+    assert lib.tm_tonemap_backward_resid(fake, 10, 10, 10, ctypes.byref(p), odd, fake, 10, fake,
+                                         10, fake, fake, 1 << 20, null) == -3
+
+
 def test_table_padded_view_layout_on_host():
     # the layout helper itself, exercised on a CPU buffer filled by hand
     H, W = 3, 5
