@@ -242,6 +242,68 @@ __host__ __device__ constexpr int row_group() {
     return ADJ ? 2 : (VEC >= 8 || THIRD ? 4 : 8);
 }
 
+// Row totals of a group of eight rows without a wave reduction per row.  Each lane writes
+// its in-lane sums of the eight rows to the wave's LDS slice (row-major, pitch 65); lane l
+// then adds the eight entries [8p, 8p + 8) of row l & 7 (p = l >> 3), and the eight parts
+// of a row (lanes differing in bits 3, 4 and 5) are added by a rotation of 8 inside each
+// 16-lane row and gfx950's 16- and 32-lane swaps.  Every lane then holds the total of row
+// l & 7; lanes 0..7 hold rows 0..7.  Three cross-lane steps per row and quantity replace the
+// six of a full wave reduction, and the eight in-lane additions are shared by eight rows.
+constexpr int kRtRows = 8;
+constexpr int kRtPitch = kWave + 1;
+
+__device__ __forceinline__ void lane_swap16(uint32_t x, uint32_t &a, uint32_t &b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    a = r[0];
+    b = r[1];
+}
+__device__ __forceinline__ void lane_swap32(uint32_t x, uint32_t &a, uint32_t &b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    a = r[0];
+    b = r[1];
+}
+
+// {value of this lane, value of lane l ^ 16} (H16) or {.., lane l ^ 32}, in a lane-independent
+// order, for each scan value type.
+template <bool H16>
+__device__ __forceinline__ void swap_pair(uint32_t x, uint32_t &a, uint32_t &b) {
+    if constexpr (H16) lane_swap16(x, a, b); else lane_swap32(x, a, b);
+}
+template <bool H16>
+__device__ __forceinline__ void swap_pair(float x, float &a, float &b) {
+    uint32_t u, v;
+    swap_pair<H16>(__float_as_uint(x), u, v);
+    a = __uint_as_float(u);
+    b = __uint_as_float(v);
+}
+template <bool H16>
+__device__ __forceinline__ void swap_pair(double x, double &a, double &b) {
+    const uint64_t bits = __double_as_longlong(x);
+    uint32_t l0, l1, h0, h1;
+    swap_pair<H16>((uint32_t)bits, l0, l1);
+    swap_pair<H16>((uint32_t)(bits >> 32), h0, h1);
+    a = __longlong_as_double((long long)(((uint64_t)h0 << 32) | l0));
+    b = __longlong_as_double((long long)(((uint64_t)h1 << 32) | l1));
+}
+template <bool H16>
+__device__ __forceinline__ void swap_pair(f2 x, f2 &a, f2 &b) {
+    swap_pair<H16>(x.hi, a.hi, b.hi);
+    swap_pair<H16>(x.lo, a.lo, b.lo);
+}
+
+template <class A, class T>
+__device__ __forceinline__ T group_row_total(const T *row_part) {
+    T s = row_part[0];
+#pragma unroll
+    for (int e = 1; e < kRtRows; ++e) s = A::add(s, row_part[e]);
+    s = A::add(s, dpp<0x128>(s));   // row_ror:8, the partner l ^ 8 inside the 16-lane row
+    T a, b;
+    swap_pair<true>(s, a, b);
+    s = A::add(a, b);
+    swap_pair<false>(s, a, b);
+    return A::add(a, b);
+}
+
 template <int G, int VEC, bool ADJ, bool OUT_V>
 __device__ __forceinline__ void load_group(const ScanK &k, int y, int n, int xl, bool wide,
                                            RowIn<VEC, ADJ> (&b)[G]) {
@@ -265,6 +327,9 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
     const bool full = x0 + TW <= k.W;   // tile-uniform
     const bool wide = ADJ ? full : (k.vec_load && full);
     __shared__ double2 sh_adj[ADJ ? kWavesPerBlock * kWave * VEC : 1];
+    constexpr bool kLdsRows = SAT && !ADJ && G == kRtRows;
+    __shared__ T sh_rt[kLdsRows ? kWavesPerBlock * 2 * kRtRows * kRtPitch : 1];
+    T *rt = sh_rt + (kLdsRows ? wave_id() * 2 * kRtRows * kRtPitch : 0);
 
     for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
         const bool do_sat = SAT && ch == 0;
@@ -317,11 +382,16 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
                         s1 = A::add(s1, q1[i]);
                         s2 = A::add(s2, q2[i]);
                     }
-                    s1 = wave_sum<A>(s1);
-                    s2 = wave_sum<A>(s2);
-                    t1 = A::add(t1, s1);
-                    t2 = A::add(t2, s2);
-                    if (lane == u) { k1 = s1; k2 = s2; }
+                    if constexpr (kLdsRows) {
+                        rt[u * kRtPitch + lane] = s1;
+                        rt[(kRtRows + u) * kRtPitch + lane] = s2;
+                    } else {
+                        s1 = wave_sum<A>(s1);
+                        s2 = wave_sum<A>(s2);
+                        t1 = A::add(t1, s1);
+                        t2 = A::add(t2, s2);
+                        if (lane == u) { k1 = s1; k2 = s2; }
+                    }
                 }
                 if (do_h) {
                     uint32_t lc[CHUNK];
@@ -350,6 +420,15 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
                     }
                 }
             }
+            if constexpr (kLdsRows) {
+                if (do_sat) {   // rows u >= n of the slice are stale; their totals go unused
+                    wave_lds_sync();
+                    const int ru = lane & (kRtRows - 1), part = lane >> 3;
+                    k1 = group_row_total<A>(rt + ru * kRtPitch + part * kRtRows);
+                    k2 = group_row_total<A>(rt + (kRtRows + ru) * kRtPitch + part * kRtRows);
+                    wave_lds_sync();
+                }
+            }
             if (lane < n) {
                 const int64_t y = y0 + r0 + lane;
                 if (do_sat) {
@@ -362,6 +441,18 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
                     for (int c = 0; c < CHUNK; ++c)
                         if (c < pe.np) gptr(k.rs_h)[((int64_t)(p0 + c) * k.H + y) * k.tiles_x + tx] = kh[c];
                 }
+            }
+        }
+        if constexpr (kLdsRows) {
+            if (do_sat) {   // tile totals from the column totals
+                T a = c1[0], b = c2[0];
+#pragma unroll
+                for (int i = 1; i < VEC; ++i) {
+                    a = A::add(a, c1[i]);
+                    b = A::add(b, c2[i]);
+                }
+                t1 = wave_sum<A>(a);
+                t2 = wave_sum<A>(b);
             }
         }
         if (do_sat) {

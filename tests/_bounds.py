@@ -3,8 +3,9 @@
 Integral images.  Every stored entry is a sum of the pixel terms q over its quadrant,
 formed by a fixed tree of additions in the table's arithmetic.  Along any root-to-leaf path
 the tree has at most
-    depth = 2 tiles_x + 2 tiles_y + th + 2 vec + 24
-additions (in-lane prefix, 6 DPP levels, row and column carries, the tile's column run),
+    depth = 2 tiles_x + 2 tiles_y + th + 2 vec + 28
+additions (in-lane prefix, 6 DPP levels, row and column carries, the tile's column run; a
+row total of a group of eight rows takes 8 + 3 levels across the lanes),
 so the entry's error is at most depth * u * sum |q| over the quadrant, with u = 2^-24
 (FP32), 2^-44 (compensated FP32 pairs: TwoSum of the leading parts plus the trailing parts)
 or 2^-53 (FP64).  For TM_SAT_C32X2, q = v - mu1 (and v^2 - mu2), |q| <= v + mu1.
@@ -42,7 +43,7 @@ def tiling(H, W, vec=None, th=None):
 def sat_depth(H, W, vec, th):
     tx = -(-W // (64 * vec))
     ty = -(-H // th)
-    return 2 * tx + 2 * ty + th + 2 * vec + 24
+    return 2 * tx + 2 * ty + th + 2 * vec + 28
 
 
 def abs_tables(lum, prec, mu1=0.0, mu2=0.0):
