@@ -83,23 +83,26 @@ __device__ Sum3 block_sum3(Sum3 v) {
 //   Cp[q][j][chunk][x] = sum over the tile's rows y >= H-1-ry_j of g R_qj(x, y),
 //   part[block] = {sum g E, sum g (1 - Pbar), sum g Pbar},
 // each combined in a fixed order.  A residual pair is loaded only where some field needs it.
+// S: the number of fields, fixed at compile time so that a row's state holds only the fields
+// in use.
+template <int S>
 __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
-    const int s = k.p.n_scales;
+    constexpr int s = S;
     const int ncol = (k.W + kWave - 1) / kWave;
     const int ct = blockIdx.x % ncol, ch = blockIdx.x / ncol;
     const int x = ct * kWave + lane_id(), w = wave_id();
     const int y0 = ch * k.chunk, y1 = min(k.H, y0 + k.chunk);
     const int64_t hw = (int64_t)k.H * k.W;
     const float *E = k.R + 2 * (int64_t)s * hw, *Pb = E + hw;
-    int lox[kS], loy[kS];
-    double cacc[2][kS];
+    int lox[S], loy[S];
+    double cacc[2][S];
 #pragma unroll
-    for (int j = 0; j < kS; ++j) {
-        lox[j] = j < s ? max(k.W - 1 - k.p.rx[j], 0) : k.W;
-        loy[j] = j < s ? max(k.H - 1 - k.p.ry[j], 0) : k.H;
+    for (int j = 0; j < S; ++j) {
+        lox[j] = max(k.W - 1 - k.p.rx[j], 0);
+        loy[j] = max(k.H - 1 - k.p.ry[j], 0);
         cacc[0][j] = cacc[1][j] = 0.0;
     }
-    __shared__ double shr[2 * kS][kChunkMax];
+    __shared__ double shr[2 * S][kChunkMax];
     Sum3 sacc{0.0, 0.0, 0.0};
     const int xc = min(x, k.W - 1);      // in-image address for the lanes past the edge
     const bool in = x < k.W;
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
     // current one is reduced
     struct Row {
         float g, e, p;
-        float2 r[kS];
+        float2 r[S];
     };
     auto load_row = [&](int y, Row &q) {
         const int64_t o = (int64_t)y * k.W + xc;
@@ -116,10 +119,10 @@ __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
         q.e = E[o];
         q.p = Pb[o];
 #pragma unroll
-        for (int j = 0; j < kS; ++j) {
+        for (int j = 0; j < S; ++j) {
             q.r[j] = make_float2(0.f, 0.f);
             // wave-uniform: does any field-j range sum need this tile row?
-            if (j < s && (tile_end > lox[j] || y >= loy[j])) q.r[j] = rpair(k, j)[o];
+            if (tile_end > lox[j] || y >= loy[j]) q.r[j] = rpair(k, j)[o];
         }
     };
     Row cur, nxt;
@@ -134,20 +137,18 @@ __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
         sacc.b = __builtin_fma(gx, 1.0 - pb, sacc.b);
         sacc.c = __builtin_fma(gx, pb, sacc.c);
 #pragma unroll
-        for (int j = 0; j < kS; ++j) {
-            if (j < s) {
-                const double a = gx * (double)cur.r[j].x, b = gx * (double)cur.r[j].y;
-                if (y >= loy[j]) { cacc[0][j] += a; cacc[1][j] += b; }
-                double ra = 0.0, rb = 0.0;
-                if (tile_end > lox[j]) {   // block-uniform: the row range reaches this tile
-                    const bool inr = x >= lox[j];
-                    ra = wave_sum<Acc<kF64>>(inr ? a : 0.0);
-                    rb = wave_sum<Acc<kF64>>(inr ? b : 0.0);
-                }
-                if (lane_id() == 0) {
-                    shr[j][y - y0] = ra;
-                    shr[kS + j][y - y0] = rb;
-                }
+        for (int j = 0; j < S; ++j) {
+            const double a = gx * (double)cur.r[j].x, b = gx * (double)cur.r[j].y;
+            if (y >= loy[j]) { cacc[0][j] += a; cacc[1][j] += b; }
+            double ra = 0.0, rb = 0.0;
+            if (tile_end > lox[j]) {   // block-uniform: the row range reaches this tile
+                const bool inr = x >= lox[j];
+                ra = wave_sum<Acc<kF64>>(inr ? a : 0.0);
+                rb = wave_sum<Acc<kF64>>(inr ? b : 0.0);
+            }
+            if (lane_id() == 0) {
+                shr[j][y - y0] = ra;
+                shr[S + j][y - y0] = rb;
             }
         }
         if (more) cur = nxt;
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
         const int q = qj / s, j = qj % s;
         double v = 0.0;
 #pragma unroll
-        for (int jj = 0; jj < kS; ++jj)
+        for (int jj = 0; jj < S; ++jj)
             if (jj == j) v = q ? cacc[1][jj] : cacc[0][jj];
         __syncthreads();
         shc[w][lane_id()] = v;
@@ -173,7 +174,7 @@ __global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
     for (int t = threadIdx.x; t < 2 * s * (y1 - y0); t += kBlock) {
         const int qj = t / (y1 - y0), r = t % (y1 - y0);
         const int q = qj / s, j = qj % s;
-        k.Rp[(((int64_t)q * s + j) * ncol + ct) * k.H + y0 + r] = shr[q * kS + j][r];
+        k.Rp[(((int64_t)q * s + j) * ncol + ct) * k.H + y0 + r] = shr[q * S + j][r];
     }
     const Sum3 tot = block_sum3(sacc);
     if (threadIdx.x == 0) {
@@ -393,7 +394,16 @@ hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, voi
     k.chunk = plan.chunk;
     const int S = a.p.n_scales;
     const unsigned nbs = (unsigned)(k.tiles_x * plan.nchunks);
-    hipLaunchKernelGGL(border_scalar_kernel, dim3(nbs), dim3(kBlock), 0, s, k);
+    switch (S) {
+#define TM_BORDER(n)                                                                            \
+    case n:                                                                                    \
+        hipLaunchKernelGGL(border_scalar_kernel<n>, dim3(nbs), dim3(kBlock), 0, s, k);         \
+        break;
+        TM_BORDER(1) TM_BORDER(2) TM_BORDER(3) TM_BORDER(4)
+        TM_BORDER(5) TM_BORDER(6) TM_BORDER(7) TM_BORDER(8)
+#undef TM_BORDER
+        default: return hipErrorInvalidValue;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nred = (unsigned)(((int64_t)2 * S * (a.H + a.W) + kBlock - 1) / kBlock);
