@@ -247,8 +247,8 @@ __host__ __device__ constexpr int row_group() {
 // then adds the eight entries [8p, 8p + 8) of row l & 7 (p = l >> 3), and the eight parts
 // of a row (lanes differing in bits 3, 4 and 5) are added by a rotation of 8 inside each
 // 16-lane row and gfx950's 16- and 32-lane swaps.  Every lane then holds the total of row
-// l & 7; lanes 0..7 hold rows 0..7.  Three cross-lane steps per row and quantity replace the
-// six of a full wave reduction, and the eight in-lane additions are shared by eight rows.
+// l & 7; lanes 0..7 hold rows 0..7.  Per group and quantity this costs seven additions and
+// three cross-lane steps, where a wave reduction per row cost eight times six steps.
 constexpr int kRtRows = 8;
 constexpr int kRtPitch = kWave + 1;
 
