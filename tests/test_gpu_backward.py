@@ -52,6 +52,35 @@ def test_backward_radii_and_clamping(rx, ry):
     _check(lum, 5, rx, ry, 0.05, "f64", seed=3, ld=(0.2, 0.8))
 
 
+# field counts the cases above do not reach (the border and deposit kernels are compiled per
+# field count)
+@pytest.mark.parametrize("rx,ry", [([30, 15, 8, 4, 2, 1], [25, 12, 6, 3, 1, 0]),
+                                   ([33, 16, 8, 4, 2, 1, 0], [20, 10, 5, 2, 1, 0, 1])])
+def test_backward_six_and_seven_fields(rx, ry):
+    lum = lum_ref(rgb_case(52, 77, 5, -2.0, 4.0, seed=10 + len(rx)))
+    _check(lum, 5, rx, ry, 0.1, "c32x2", seed=len(rx))
+
+
+def test_backward_one_field():
+    # With one field L = L_1 wherever W_1 > 0 (and by definition where it is 0), so the exact
+    # gradient wrt v and eps is zero.  The device's is the FP32 rounding of L - L_1 (at most
+    # 2^-22 of L <= 1) carried through the residuals: |E| <= 2^-22 / eps per pixel, and dv must
+    # stay far below (1e-5 of) the gradient the same image has with two fields.  The display
+    # range gradients are sums of g P_1 and match the oracle.
+    lum = lum_ref(rgb_case(52, 77, 5, -2.0, 4.0, seed=11))
+    g = np.random.default_rng(1).standard_normal(lum.shape).astype(np.float32)
+    gv, gp = _gpu_grad(lum, 5, [17], [11], 0.1, "c32x2", g)
+    e = edges_ref(lum, 5)
+    g64 = g.astype(np.float64)
+    dv1, gref = oracle.backward(lum, e, [17], [11], g64, 0.1, 0.0, 1.0)
+    dv2, _ = oracle.backward(lum, e, [17, 8], [11, 5], g64, 0.1, 0.0, 1.0)
+    assert np.max(np.abs(dv1)) <= 1e-15 * np.max(np.abs(dv2))     # the oracle agrees: zero
+    assert np.max(np.abs(gv)) <= 1e-5 * np.max(np.abs(dv2))
+    assert abs(gp[0]) <= 2.0 ** -22 / 0.1 * np.sum(np.abs(g64))
+    for a, b in zip(gp[1:], gref[1:]):
+        assert abs(a - b) <= 1e-6 * (1.0 + abs(b)) + 2e-4 * abs(b), (gp, gref)
+
+
 def test_backward_matches_central_differences_of_gpu_forward():
     # directional derivative along a random direction on pixels far from every bin edge
     H, W = 64, 96
