@@ -92,6 +92,7 @@ struct ScanK {
     int n_bins, layout, n_planes;
     uint32_t *hist;
     int64_t ld_hist, plane_stride;
+    int stream_out;               // tables larger than the memory-side cache: non-temporal stores
     // aggregates (each an array of quantities; see ScanPlan)
     void *rs_sat, *cs_sat, *tt_sat, *xc_sat, *cse_sat, *tte_sat;
     uint32_t *rs_h, *cs_h, *tt_h, *xc_h, *cse_h, *tte_h;

@@ -192,24 +192,44 @@ __device__ __forceinline__ void sat_terms(const ScanK &k, int xl, const RowIn<VE
     }
 }
 
+// Store of a table value (4, 8 or 16 bytes), non-temporal when nt.  Tables larger than the
+// memory-side cache cannot stay there for the query anyway; streaming them out keeps them
+// from displacing the lines the scans and the query still read.  Smaller tables are stored
+// normally, so the query finds them in that cache.
+template <typename T>
+__device__ __forceinline__ void st_tab(TM_GLOBAL T *p, const T &v, bool nt) {
+    if (!nt) {
+        *p = v;
+    } else if constexpr (sizeof(T) == 4) {
+        uint32_t w;
+        __builtin_memcpy(&w, &v, 4);
+        __builtin_nontemporal_store(w, reinterpret_cast<TM_GLOBAL uint32_t *>(p));
+    } else {
+        using V = uint32_t __attribute__((ext_vector_type(sizeof(T) / 4)));
+        V w;
+        __builtin_memcpy(&w, &v, sizeof(T));
+        __builtin_nontemporal_store(w, reinterpret_cast<TM_GLOBAL V *>(p));
+    }
+}
+
 // Store a lane's VEC consecutive counts of one row: 16-byte stores inside the image (the
 // row pitch is a multiple of 64 entries and xl a multiple of VEC, so they are aligned),
 // element stores on the ragged last tile.
 template <int VEC>
 __device__ __forceinline__ void store_counts(TM_GLOBAL uint32_t *out, int xl, int W, bool full,
-                                             const uint32_t (&c)[VEC]) {
+                                             const uint32_t (&c)[VEC], bool nt) {
     if (full && VEC % 4 == 0) {
 #pragma unroll
         for (int i = 0; i < VEC; i += 4)
-            *reinterpret_cast<TM_GLOBAL uint4 *>(out + xl + i) =
-                make_uint4(c[i], c[i + 1], c[i + 2], c[i + 3]);
+            st_tab(reinterpret_cast<TM_GLOBAL uint4 *>(out + xl + i),
+                   make_uint4(c[i], c[i + 1], c[i + 2], c[i + 3]), nt);
     } else if (full) {
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) out[xl + i] = c[i];
+        for (int i = 0; i < VEC; ++i) st_tab(out + xl + i, c[i], nt);
     } else {
 #pragma unroll
         for (int i = 0; i < VEC; ++i)
-            if (xl + i < W) out[xl + i] = c[i];
+            if (xl + i < W) st_tab(out + xl + i, c[i], nt);
     }
 }
 
@@ -219,15 +239,15 @@ __device__ __forceinline__ void store_counts(TM_GLOBAL uint32_t *out, int xl, in
 // instruction covers 64 consecutive entries.
 template <int VEC, typename ET>
 __device__ __forceinline__ void store_entries_full(TM_GLOBAL ET *out, int x0, int lane,
-                                                   const ET (&e)[VEC], ET *st) {
+                                                   const ET (&e)[VEC], ET *st, bool nt) {
     if constexpr (VEC == 1) {
-        out[x0 + lane] = e[0];
+        st_tab(out + x0 + lane, e[0], nt);
     } else {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) st[lane * VEC + i] = e[i];
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) out[x0 + i * kWave + lane] = st[i * kWave + lane];
+        for (int i = 0; i < VEC; ++i) st_tab(out + x0 + i * kWave + lane, st[i * kWave + lane], nt);
         wave_lds_sync();
     }
 }
@@ -921,11 +941,12 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
 #pragma unroll
                             for (int i = 0; i < VEC; ++i) e[i] = E::make(c1[i], c2[i]);
                             store_entries_full<VEC, ET>(out, x0, lane, e,
-                                                        sh_stage + wave_id() * (kWave * VEC));
+                                                        sh_stage + wave_id() * (kWave * VEC),
+                                                        k.stream_out != 0);
                         } else {
 #pragma unroll
                             for (int i = 0; i < VEC; ++i)
-                                if (xl + i < k.W) out[xl + i] = E::make(c1[i], c2[i]);
+                                if (xl + i < k.W) st_tab(out + xl + i, E::make(c1[i], c2[i]), k.stream_out != 0);
                         }
                     }
                 }
@@ -950,14 +971,14 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
                             TM_GLOBAL uint32_t *out = gptr(k.hist) + (int64_t)(p0 + c) * k.plane_stride + (int64_t)y * k.ld_hist;
 #pragma unroll
                             for (int i = 0; i < VEC; ++i) cc[c][i] += xc + exa + pa[i];
-                            store_counts<VEC>(out, xl, k.W, full, cc[c]);
+                            store_counts<VEC>(out, xl, k.W, full, cc[c], k.stream_out != 0);
                         }
                         if (c + 1 < CHUNK && c + 1 < pe.np) {
                             const uint32_t xc = readlane(gxh[c + 1], u);
                             TM_GLOBAL uint32_t *out = gptr(k.hist) + (int64_t)(p0 + c + 1) * k.plane_stride + (int64_t)y * k.ld_hist;
 #pragma unroll
                             for (int i = 0; i < VEC; ++i) cc[c + 1][i] += xc + exb + pb[i];
-                            store_counts<VEC>(out, xl, k.W, full, cc[c + 1]);
+                            store_counts<VEC>(out, xl, k.W, full, cc[c + 1], k.stream_out != 0);
                         }
                     }
                 }
@@ -1240,6 +1261,12 @@ ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws) {
     k.hist = a.hist;
     k.ld_hist = a.ld_hist;
     k.plane_stride = a.plane_stride;
+    // the memory-side cache (Infinity Cache) of MI355X holds 256 MiB
+    constexpr int64_t kMallBytes = (int64_t)256 << 20;
+    const int64_t sat_bytes =
+        (a.sat && a.sat_prec >= 0) ? (int64_t)(a.sat_prec == kF32 ? 8 : 16) * (a.H + 1) * a.ld_sat : 0;
+    const int64_t hist_bytes = (int64_t)k.n_planes * a.plane_stride * 4;
+    k.stream_out = sat_bytes + hist_bytes > kMallBytes;
     k.rs_sat = w + plan.rs_sat;
     k.cs_sat = w + plan.cs_sat;
     k.tt_sat = w + plan.tt_sat;
