@@ -52,13 +52,13 @@ def _parse():
                     help="after the timed loop, copy 1 GiB device-to-device once (a plain copy "
                          "kernel of known size, for calibrating HBM counters) and report its "
                          "bandwidth")
-    ap.add_argument("--workload", choices=["image", "batch", "sweep", "hdr"],
+    ap.add_argument("--workload", choices=["image", "batch", "sweep", "hdr", "stress"],
                     default="image",
                     help="image: one image (--image, 4000x3000 by default); batch: 64 images "
                          "of uneven size, launches replayed from a HIP graph; sweep: the "
                          "paper's Table IV grid (n, s in {3, 4, 5} at 480x640, 720x1280, "
                          "1080x1920) with a per-stage split; hdr: the multi-exposure front end "
-                         "at 4000x3000")
+                         "at 4000x3000; stress: 64 bins and radii 4/16/64 at 4000x3000")
     ap.add_argument("--image", choices=IMAGES, default=WORKLOAD,
                     help="the image of the image workload (the metric is quoted on "
                          "wdr_4000x3000)")
@@ -124,6 +124,72 @@ def bench_sweep(args):
     print(json.dumps({"metric": "forward ms and MP/s over the Table IV grid (n, s, resolution)",
                       "data": "synthetic", "sat_precision": args.prec, "steps": args.steps,
                       "rows": rows}), flush=True)
+
+
+STRESS_BINS = 64
+STRESS_RADII = (4, 16, 64)
+
+
+def bench_stress(args):
+    """The stress parameter set (n = 64 bins, fields of radius 4, 16 and 64 on both axes,
+    eps = 0.1) on the 4000x3000 image: forward MP/s, per-stage split and each stage's
+    algorithmic bytes over its time.  Algorithmic bytes per pixel (every input read once,
+    every table written once and read once): prologue 16; tables 4 + E + 4 (n - 1) with E the
+    integral-image entry; query 4 + E + 4 (n - 1) + 4; forward 564 B/px with C32X2 tables."""
+    import torch
+
+    import paper_2102_01289_amd as tm
+    from synth import WORKLOADS, gen_wdr
+
+    cfg = WORKLOADS[WORKLOAD]
+    H, W = cfg["H"], cfg["W"]
+    dev = torch.device("cuda:0")
+    rgb = torch.from_numpy(gen_wdr(H, W, cfg["K"], cfg["lo"], cfg["hi"], cfg["seed"]).rgb).to(dev)
+    n, r = STRESS_BINS, list(STRESS_RADII)
+    p = tm.make_params(n, len(r), r, r, args.eps)
+    m = tm.ToneMapper(H, W, p, args.prec, device=dev)
+    m.run(rgb)
+    stream = torch.cuda.current_stream()
+    stage = {}
+    for name, fn in (("prologue", lambda: m.prologue(rgb)), ("tables", m.tables),
+                     ("query", m.query)):
+        for _ in range(args.warmup):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        stage[name] = a.elapsed_time(b) / args.steps
+    ms = sum(stage.values())
+    esz = {"f32": 8, "c32x2": 16, "f64": 16}[args.prec]
+    bpx = {"prologue": 16, "tables": 4 + esz + 4 * (n - 1),
+           "query": 4 + esz + 4 * (n - 1) + 4}
+    total_b = sum(bpx.values())
+    dom = max(stage, key=stage.get)
+    gbs = {k: bpx[k] * H * W / (v * 1e-3) / 1e9 for k, v in stage.items()}
+    line = {
+        "metric": "megapixels/s, forward with the stress parameter set (64 bins, radii 4/16/64)",
+        "value": round(H * W / 1e6 / (ms * 1e-3), 3), "unit": "megapixels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"c32x2": "f32x2", "f32": "f32", "f64": "f64"}[args.prec], "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD}_stress", "height": H, "width": W, "n_bins": n,
+                   "radii": r, "eps": args.eps, "sat_precision": args.prec},
+        "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "stage_algorithmic_gb_s": {k: round(v, 1) for k, v in gbs.items()},
+        "algorithmic_bytes_per_px": {**bpx, "forward": total_b},
+        "forward_algorithmic_frac": round(total_b * H * W / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": {"prologue": "lum_stats_kernel",
+                                                 "tables": "scan_stage1-3 (one table build)",
+                                                 "query": "forward_kernel"}[dom],
+                     "achieved": round(gbs[dom], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbs[dom] / PEAK_HBM_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": bpx[dom] * H * W,
+                     "avg_kernel_ms": round(stage[dom], 4)},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def _median_ms(fn, reps=10, warmup=2):
@@ -324,9 +390,36 @@ def measured_traffic(variant: str, prec: str, n_bins: int, n_scales: int,
     return None
 
 
-def cpu_baseline(rgb, params_np, backward: bool):
-    """The oracle, single-threaded, on the full image (forward about 3-15 s; the backward
-    about three times that)."""
+def host_threads() -> int:
+    """Host threads this process may use: its CPU affinity, capped by OMP_NUM_THREADS when
+    that is set (the share of the host given to one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(n, 1)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rgb, params_np, backward: bool, gpu_outputs=None):
+    """The oracle on the full image, on all the host threads this process may use and on one
+    thread (the forward's per-pixel loops and the adjoint's box sums run on OpenMP threads;
+    the double-double tables are built serially either way).  gpu_outputs: {name: L} device
+    forwards of the same image, whose max-abs and p99.9 error against the oracle's FP64 L are
+    reported beside the timing."""
     import numpy as np
 
     import oracle
@@ -334,20 +427,38 @@ def cpu_baseline(rgb, params_np, backward: bool):
     n, s, eps, seed = params_np
     H, W = rgb.shape[1:]
     g = gen_upstream_grad((H, W), seed=seed).astype(np.float64) if backward else None
-    t0 = time.perf_counter()
-    lum = oracle.luminance(rgb)
-    e = oracle.exact_edges(lum.min(), lum.max(), n)
-    rx, ry = oracle.paper_radii(H, W, s)
-    oracle.forward(lum, e, rx, ry, eps)
-    if backward:
-        oracle.backward(lum, e, rx, ry, g, eps)
-    dt = time.perf_counter() - t0
+
+    def run(threads):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        lum = oracle.luminance(rgb)
+        e = oracle.exact_edges(lum.min(), lum.max(), n)
+        rx, ry = oracle.paper_radii(H, W, s)
+        L = oracle.forward(lum, e, rx, ry, eps)
+        if backward:
+            oracle.backward(lum, e, rx, ry, g, eps)
+        return time.perf_counter() - t0, L
+
+    threads = host_threads()
+    dt, L = run(threads)
+    dt1, _ = run(1) if threads > 1 else (dt, None)
+    oracle.set_threads(1)
     what = "forward+backward" if backward else "forward"
-    return {"value": round(H * W / dt / 1e6, 4), "unit": "megapixels/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"full {W}x{H} {what} (luminance, exact edges, FP64 double-double "
-                       f"tables, per-pixel pass{', adjoint' if backward else ''}), one thread, "
-                       f"{dt:.1f} s")}
+    out = {"value": round(H * W / dt / 1e6, 4), "unit": "megapixels/s", "cores": threads,
+           "kind": "oracle",
+           "sample": (f"full {W}x{H} {what} (luminance, exact edges, FP64 double-double "
+                      f"tables, per-pixel pass{', adjoint' if backward else ''}) on {threads} "
+                      f"OpenMP threads, {dt:.1f} s; one thread {dt1:.1f} s"),
+           "single_thread_value": round(H * W / dt1 / 1e6, 4),
+           "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+    if gpu_outputs:
+        err = {}
+        for name, Lg in gpu_outputs.items():
+            d = np.abs(Lg.astype(np.float64) - L)
+            err[name] = {"max_abs": float(f"{d.max():.3e}"),
+                         "p99_9": float(f"{np.quantile(d, 0.999):.3e}")}
+        out["forward_error_vs_oracle"] = err
+    return out
 
 
 def main():
@@ -364,6 +475,9 @@ def main():
         return
     if args.workload == "hdr":
         bench_hdr(args)
+        return
+    if args.workload == "stress":
+        bench_stress(args)
         return
 
     import numpy as np
@@ -498,9 +612,32 @@ def main():
                      "algorithmic_bytes_per_launch": qbytes,
                      "avg_kernel_ms": round(q_ms, 4)},
     }
+    # the FP64-table forward of the same image beside the default precision (same stages)
+    other = None
+    if args.prec != "f64" and args.kernel_only is None:
+        m64 = tm.ToneMapper(H, W, params, "f64", device=dev)
+        m64.run(rgb)
+        st64 = {}
+        for name, fn in (("prologue", lambda: m64.prologue(rgb)), ("tables", m64.tables),
+                         ("query", m64.query)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(5):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            st64[name] = round(a.elapsed_time(b) / 5, 4)
+        f64_ms = sum(st64.values())
+        line["f64_tables"] = {"fwd_mp_s": round(mpx / (f64_ms * 1e-3), 3), "stage_ms": st64}
+        m64.run(rgb)
+        other = m64
     if not args.no_cpu_baseline:
+        outs = {args.prec: mapper.run(rgb).cpu().numpy()}
+        if other is not None:
+            outs["f64"] = other.run(rgb).cpu().numpy()
+        torch.cuda.synchronize()
         line["cpu_baseline"] = cpu_baseline(img.rgb, (args.n_bins, args.n_scales, args.eps,
-                                                      cfg["seed"] + 1), do_bwd)
+                                                      cfg["seed"] + 1), do_bwd, outs)
     print(json.dumps(line), flush=True)
 
 

@@ -83,9 +83,17 @@ typedef enum { TM_HIST_PER_BIN = 0, TM_HIST_CUMULATIVE = 1 } tm_hist_layout;
  *   n_bins   n, 1..256 (number of equal-width log-luminance bins, Eq. 7)
  *   n_scales s, 1..8   (number of receptive fields, Eq. 3)
  *   rx, ry   per-field half-widths >= 0; field j covers x-(rx+1) < x' <= x+rx and the same
- *            in y (Algorithm 1), clamped to the image
+ *            in y (Algorithm 1), clamped to the image.  Any radius >= the image's width
+ *            (height) gives the whole row (column), so larger radii act as that size.
  *   eps      the regulariser of Eq. 4, > 0, in units of luminance squared
- *   ld_min, ld_max  display luminance range of Eq. 2, ld_max > ld_min */
+ *   ld_min, ld_max  display luminance range of Eq. 2, ld_max > ld_min
+ *   scalars  NULL, or a DEVICE pointer to float[3] = {eps, ld_min, ld_max} that the kernels
+ *            read when they run, in place of the three fields above (which are then neither
+ *            used nor checked).  It lets a caller whose parameters live in device memory (an
+ *            autograd graph, a captured HIP graph) change them without a host
+ *            synchronisation.  The device values must meet the same conditions (eps > 0,
+ *            ld_max > ld_min, finite); the library cannot check them.  4-byte aligned, else
+ *            TM_ERR_ALIGN.  The batch entry points ignore it. */
 typedef struct {
     int32_t n_bins;
     int32_t n_scales;
@@ -94,6 +102,7 @@ typedef struct {
     float eps;
     float ld_min;
     float ld_max;
+    const float *scalars;
 } tm_params;
 
 /* Scan tiling (chosen by the autotuner; NULL anywhere means the built-in default).
@@ -375,8 +384,13 @@ typedef struct tm_batch tm_batch;
 size_t tm_batch_workspace_bytes(const tm_image_desc *descs, int32_t count, const tm_params *p,
                                 tm_sat_prec prec, const tm_tune *tune);
 
-/* Lay the batch out in ws and upload its descriptor tables on `stream` (asynchronously; the
- * object keeps the host copies alive).  descs is read during the call only.  tune: one scan
+/* Lay the batch out in ws and upload its descriptor tables on `stream`: the copies are
+ * enqueued and the call returns without synchronising; the object keeps their host source
+ * buffers alive until tm_batch_destroy, so the caller must not destroy the batch before the
+ * stream has passed those copies (any later synchronisation of the stream ensures it; the
+ * batch's own launches on the same stream are ordered after them).  This call cannot be
+ * captured into a HIP graph (it copies from pageable host memory).  descs is read during
+ * the call only.  tune: one scan
  * tiling for all images, except that tile_w_vec = 0 and tile_h = 0 give every image the
  * library default for its own shape (NULL: {0, 0, 4}).  The images are processed in groups
  * of equal columns per lane; outputs go to each descriptor's own buffer. */

@@ -27,6 +27,7 @@ from . import build as _build
 __all__ = [
     "FLT_MIN", "paper_radii", "exact_edges", "luminance", "bins", "integral_histogram",
     "integral_image", "forward", "forward_direct", "backward", "box_filter", "lib",
+    "set_threads",
 ]
 
 FLT_MIN = float(np.finfo(np.float32).tiny)  # 2^-126, smallest normal FP32
@@ -34,10 +35,11 @@ _LIB = None
 
 
 def lib() -> ctypes.CDLL:
-    """Load the oracle's C library, compiling it first if it has not been built."""
+    """Load the oracle's C library, compiling it first if it has not been built or is older
+    than its source."""
     global _LIB
     if _LIB is None:
-        if not os.path.exists(_build.LIB):
+        if _build.stale():
             _build.build()
         L = ctypes.CDLL(_build.LIB)
         P = ctypes.c_void_p
@@ -58,6 +60,8 @@ def lib() -> ctypes.CDLL:
         L.orc_box_filter.restype = I
         L.orc_color_restore.argtypes = [P, P, P, I64, I64, D, P]
         L.orc_color_restore.restype = None
+        L.orc_set_threads.argtypes = [I]
+        L.orc_set_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -68,6 +72,11 @@ def _ptr(a: np.ndarray):
 
 def _c(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's per-pixel loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------------------- pyramid

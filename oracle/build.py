@@ -14,12 +14,17 @@ def build(verbose: bool = False) -> str:
     """Compile oracle/tm_oracle.c into oracle/libtm_oracle.so (always recompiles)."""
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+           "-fopenmp", "-shared", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
+
+
+def stale() -> bool:
+    """The library is missing or older than its source."""
+    return not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)
 
 
 if __name__ == "__main__":

@@ -15,12 +15,22 @@
  *   images are row-major [H][W]; pixel (x, y) is column x, row y;
  *   integral tables are (H+1) x (W+1): entry [y+1][x+1] holds the sum over x' <= x,
  *   y' <= y, and row 0 / column 0 are zero (the "x = -1" / "y = -1" corners).
+ *
+ * Threads (orc_set_threads, default 1): the per-pixel loops of orc_forward and orc_backward
+ * may run on several OpenMP threads, each pixel computed exactly as on one thread; every
+ * sum across pixels is then taken serially in pixel order from per-pixel terms, so results
+ * are bitwise the same for any thread count.  Used only to time the oracle on all host cores.
  */
 #include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+static int g_threads = 1;
+
+/* Number of OpenMP threads of the per-pixel loops (>= 1). */
+void orc_set_threads(int n) { g_threads = n > 0 ? n : 1; }
 
 /* ------------------------------------------------------------------ double-double */
 typedef struct { double hi, lo; } dd_t;
@@ -373,12 +383,15 @@ int orc_forward(const float *v, int64_t H, int64_t W, const float *edges, int n,
                 int var_log, double *L, double *Lj, double *Wj, double *varj)
 {
     tables_t t;
+    if (n < 1 || n > 256 || s < 1 || s > 16)
+        return -1;
     if (tables_build(v, H, W, edges, n, var_log, &t))
         return -1;
-    scale_t sc[16];
-    uint64_t *f = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
     const int64_t np = H * W;
-    for (int64_t y = 0; y < H; ++y)
+#pragma omp parallel for num_threads(g_threads) schedule(dynamic, 16)
+    for (int64_t y = 0; y < H; ++y) {
+        scale_t sc[16];
+        uint64_t f[256];
         for (int64_t x = 0; x < W; ++x) {
             pixel_scales(&t, x, y, s, rx, ry, eps, ldmin, ldmax, sc, f);
             double D, Pbar;
@@ -389,7 +402,7 @@ int orc_forward(const float *v, int64_t H, int64_t W, const float *edges, int n,
                 if (varj) varj[j * np + y * W + x] = sc[j].var;
             }
         }
-    free(f);
+    }
     tables_free(&t);
     return 0;
 }
@@ -456,33 +469,43 @@ int orc_backward(const float *v, int64_t H, int64_t W, const float *edges, int n
                  const double *g, double *grad_v, double *grad_params)
 {
     tables_t t;
+    if (n < 1 || n > 256 || s < 1 || s > 16)
+        return -1;
     if (tables_build(v, H, W, edges, n, 0, &t))
         return -1;
     const int64_t np = H * W, ld = W + 1, ps = (H + 1) * (W + 1);
     double *A1 = (double *)malloc((size_t)s * (size_t)np * sizeof(double));
     double *A2 = (double *)malloc((size_t)s * (size_t)np * sizeof(double));
     dd_t *sat = (dd_t *)malloc((size_t)ps * sizeof(dd_t));
-    uint64_t *f = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
-    if (!A1 || !A2 || !sat || !f) {
-        free(A1); free(A2); free(sat); free(f); tables_free(&t);
+    /* per-pixel terms of the scalar gradients, summed below in pixel order */
+    double *te = (double *)malloc((size_t)s * (size_t)np * sizeof(double));
+    double *tmin = (double *)malloc((size_t)np * sizeof(double));
+    double *tmax = (double *)malloc((size_t)np * sizeof(double));
+    unsigned char *dpos = (unsigned char *)malloc((size_t)np);
+    if (!A1 || !A2 || !sat || !te || !tmin || !tmax || !dpos) {
+        free(A1); free(A2); free(sat); free(te); free(tmin); free(tmax); free(dpos);
+        tables_free(&t);
         return -1;
     }
-    double geps = 0.0, gmin = 0.0, gmax = 0.0;
-    scale_t sc[16];
-    for (int64_t y = 0; y < H; ++y)
+#pragma omp parallel for num_threads(g_threads) schedule(dynamic, 16)
+    for (int64_t y = 0; y < H; ++y) {
+        scale_t sc[16];
+        uint64_t f[256];
         for (int64_t x = 0; x < W; ++x) {
             const int64_t p = y * W + x;
             pixel_scales(&t, x, y, s, rx, ry, eps, ldmin, ldmax, sc, f);
             double D, Pbar;
             double Lp = fuse(sc, s, &D, &Pbar);
-            gmin += g[p] * (1.0 - Pbar);
-            gmax += g[p] * Pbar;
+            tmin[p] = g[p] * (1.0 - Pbar);
+            tmax[p] = g[p] * Pbar;
+            dpos[p] = D > 0.0;
             for (int j = 0; j < s; ++j) {
                 double a = 0.0;
+                te[j * np + p] = 0.0;
                 if (D > 0.0) {
                     double dLdW = (sc[j].L - Lp) / D;
                     double den = sc[j].var + eps;
-                    geps += g[p] * dLdW * (-sc[j].var / (den * den));
+                    te[j * np + p] = g[p] * dLdW * (-sc[j].var / (den * den));
                     if (!sc[j].clamped)
                         a = g[p] * dLdW * eps / (den * den);
                 }
@@ -490,11 +513,21 @@ int orc_backward(const float *v, int64_t H, int64_t W, const float *edges, int n
                 A2[j * np + p] = a / sc[j].N;
             }
         }
+    }
+    double geps = 0.0, gmin = 0.0, gmax = 0.0;
+    for (int64_t p = 0; p < np; ++p) {
+        gmin += tmin[p];
+        gmax += tmax[p];
+        if (dpos[p])
+            for (int j = 0; j < s; ++j)
+                geps += te[j * np + p];
+    }
     for (int64_t p = 0; p < np; ++p)
         grad_v[p] = 0.0;
     for (int j = 0; j < s; ++j) {
         for (int pass = 0; pass < 2; ++pass) {
             sat_dd_f64(pass == 0 ? A1 + j * np : A2 + j * np, H, W, sat);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
             for (int64_t y = 0; y < H; ++y)
                 for (int64_t x = 0; x < W; ++x) {
                     win_t w = window_of(x, y, W, H, rx[j], ry[j]);
@@ -509,7 +542,7 @@ int orc_backward(const float *v, int64_t H, int64_t W, const float *edges, int n
     grad_params[0] = geps;
     grad_params[1] = gmin;
     grad_params[2] = gmax;
-    free(A1); free(A2); free(sat); free(f);
+    free(A1); free(A2); free(sat); free(te); free(tmin); free(tmax); free(dpos);
     tables_free(&t);
     return 0;
 }

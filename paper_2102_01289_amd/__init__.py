@@ -81,8 +81,10 @@ def paper_radii(H: int, W: int, s: int):
 
 def make_params(n_bins: int = 5, n_scales: int = 5, rx=None, ry=None, eps: float = 0.1,
                 ld_min: float = 0.0, ld_max: float = 1.0, H: int | None = None,
-                W: int | None = None) -> _capi.TmParams:
-    """tm_params; radii default to the paper's pyramid for an H x W image."""
+                W: int | None = None, scalars=None) -> _capi.TmParams:
+    """tm_params; radii default to the paper's pyramid for an H x W image.  scalars: a device
+    float32 tensor [3] = (eps, ld_min, ld_max) the kernels read at run time instead of the
+    eps, ld_min, ld_max arguments (the caller keeps it alive while launches use it)."""
     p = _capi.TmParams()
     p.n_bins = n_bins
     p.n_scales = n_scales
@@ -98,6 +100,11 @@ def make_params(n_bins: int = 5, n_scales: int = 5, rx=None, ry=None, eps: float
     p.eps = eps
     p.ld_min = ld_min
     p.ld_max = ld_max
+    if scalars is not None:
+        if (scalars.dtype != torch.float32 or scalars.numel() != 3 or not scalars.is_cuda
+                or not scalars.is_contiguous()):
+            raise ValueError("scalars must be a contiguous CUDA float32 tensor of 3 values")
+        p.scalars = scalars.data_ptr()
     return p
 
 

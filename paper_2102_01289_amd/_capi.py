@@ -20,7 +20,8 @@ HIST_LAYOUT = {"per_bin": 0, "cumulative": 1}
 class TmParams(ctypes.Structure):
     _fields_ = [("n_bins", ctypes.c_int32), ("n_scales", ctypes.c_int32),
                 ("rx", ctypes.c_int32 * TM_MAX_SCALES), ("ry", ctypes.c_int32 * TM_MAX_SCALES),
-                ("eps", ctypes.c_float), ("ld_min", ctypes.c_float), ("ld_max", ctypes.c_float)]
+                ("eps", ctypes.c_float), ("ld_min", ctypes.c_float), ("ld_max", ctypes.c_float),
+                ("scalars", ctypes.c_void_p)]
 
 
 class TmTune(ctypes.Structure):

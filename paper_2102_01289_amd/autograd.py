@@ -8,6 +8,9 @@ everywhere.  recompute=False (fastest): the forward writes the backward's residu
 (2s + 2 FP32 per pixel) and the backward reads no table.  recompute=True (least memory kept
 between the passes): only the luminance, edges and offsets are kept; the backward rebuilds
 the integral tables and derives the residual planes from them.
+
+The three scalars reach the kernels through device memory (tm_params.scalars), so neither
+pass synchronises with the host and both can be recorded into a CUDA/HIP graph.
 """
 from __future__ import annotations
 
@@ -19,16 +22,15 @@ from . import (make_params, tm_image_stats, tm_integral_tables, tm_tonemap_backw
 __all__ = ["TonemapFn", "tonemap_luminance"]
 
 
-def _params(H, W, n_bins, rx, ry, eps, ld_min, ld_max):
-    return make_params(n_bins, len(rx), rx, ry, float(eps), float(ld_min), float(ld_max), H, W)
-
-
 class TonemapFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, lum, eps, ld_min, ld_max, n_bins: int, rx, ry, prec: str = "c32x2",
                 recompute: bool = True):
         H, W = lum.shape
-        p = _params(H, W, n_bins, rx, ry, eps.item(), ld_min.item(), ld_max.item())
+        # device copy of (eps, ld_min, ld_max) that the kernels read when they run
+        scal = torch.stack([t.detach().reshape(()).to(device=lum.device, dtype=torch.float32)
+                            for t in (eps, ld_min, ld_max)]).contiguous()
+        p = make_params(n_bins, len(rx), rx, ry, H=H, W=W, scalars=scal)
         edges, offsets, _ = tm_image_stats(lum, n_bins)
         sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")
         if recompute:
@@ -38,6 +40,7 @@ class TonemapFn(torch.autograd.Function):
             out, ctx.resid = tm_tonemap_forward_train(lum, sat, hist, edges, p, offsets)
         del sat, hist
         ctx.meta = (p, prec, n_bins, eps.dtype)
+        ctx.scal = scal            # p points into it
         ctx.save_for_backward(lum, edges, offsets)
         return out
 

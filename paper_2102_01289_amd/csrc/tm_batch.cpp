@@ -197,8 +197,10 @@ size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int pre
         b->ck[i] = make_scank(a, sp, c.ptr<char>(o_scan));
         QueryParams qi = q;
         for (int j = 0; j < TM_MAX_SCALES; ++j) {
-            qi.rx[j] = j < p->n_scales ? x.rx[j] : 0;
-            qi.ry[j] = j < p->n_scales ? x.ry[j] : 0;
+            // radii beyond the image act as the image's size (Algorithm 1's clamping); held
+            // there so that no index expression of the kernels can overflow
+            qi.rx[j] = j < p->n_scales ? (x.rx[j] < x.W ? x.rx[j] : x.W) : 0;
+            qi.ry[j] = j < p->n_scales ? (x.ry[j] < x.H ? x.ry[j] : x.H) : 0;
         }
         b->fk[i] = make_fwdk(lum, ld_lum, H, W, sat, ld, offsets, n > 1 ? hist : nullptr, ld,
                              elems, edges, qi, x.out, x.ld_out);
@@ -291,7 +293,7 @@ tm_status tm_batch_create(const tm_image_desc *descs, int32_t count, const tm_pa
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_tiles, b->tiles.data(), n_pf, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_items, b->items.data(), n_pf, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_qtiles, b->qtiles.data(), n_pf, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host vectors back the copies
+    // no synchronisation: the host vectors backing the copies live until tm_batch_destroy
     if (e != hipSuccess) {
         delete b;
         return TM_ERR_HIP;

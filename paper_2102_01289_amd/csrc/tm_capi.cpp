@@ -62,6 +62,10 @@ tm_status check_params(const tm_params *p) {
     if (p->n_scales < 1 || p->n_scales > TM_MAX_SCALES) return TM_ERR_ARG;
     for (int j = 0; j < p->n_scales; ++j)
         if (p->rx[j] < 0 || p->ry[j] < 0) return TM_ERR_ARG;
+    if (p->scalars) {   // device values: read by the kernels, not checkable here
+        if (!aligned(p->scalars, 4)) return TM_ERR_ALIGN;
+        return TM_OK;
+    }
     if (!(p->eps > 0.f) || !std::isfinite(p->eps)) return TM_ERR_ARG;
     if (!std::isfinite(p->ld_min) || !std::isfinite(p->ld_max) || !(p->ld_max > p->ld_min))
         return TM_ERR_ARG;
@@ -82,17 +86,22 @@ ScanTune resolve_tune(const tm_tune *t, int H, int W, tm_status *st) {
 
 size_t round256(size_t a) { return (a + 255) / 256 * 256; }
 
-QueryParams to_query(const tm_params *p) {
+// Kernel parameters of an H x W image.  A radius of at least the image's width (height)
+// already covers the whole row (column) at every pixel under Algorithm 1's clamping, so radii
+// are clamped to W and H: the windows are the same and every index expression of the kernels
+// (x + rx, 2 rmin + 1, ...) stays far from int32 overflow.
+QueryParams to_query(const tm_params *p, int32_t H, int32_t W) {
     QueryParams q{};
     q.n_bins = p->n_bins;
     q.n_scales = p->n_scales;
     for (int j = 0; j < TM_MAX_SCALES; ++j) {
-        q.rx[j] = j < p->n_scales ? p->rx[j] : 0;
-        q.ry[j] = j < p->n_scales ? p->ry[j] : 0;
+        q.rx[j] = j < p->n_scales ? (p->rx[j] < W ? p->rx[j] : W) : 0;
+        q.ry[j] = j < p->n_scales ? (p->ry[j] < H ? p->ry[j] : H) : 0;
     }
     q.eps = p->eps;
     q.ld_min = p->ld_min;
     q.ld_max = p->ld_max;
+    q.scalars = p->scalars;
     return q;
 }
 
@@ -349,7 +358,7 @@ tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
         if (!edges) return TM_ERR_ARG;
         TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
     }
-    const QueryParams q = to_query(p);
+    const QueryParams q = to_query(p, H, W);
     return from_hip(launch_forward(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
                                    ld_hist, plane_stride, edges, q, out, ld_out, nullptr,
                                    (hipStream_t)stream));
@@ -373,7 +382,7 @@ tm_status tm_tonemap_forward_maps(const float *v, int64_t ld_v, int32_t H, int32
         if (!edges) return TM_ERR_ARG;
         TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
     }
-    const QueryParams q = to_query(p);
+    const QueryParams q = to_query(p, H, W);
     return from_hip(launch_forward_maps(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
                                         ld_hist, plane_stride, edges, q, out, ld_out, maps,
                                         (hipStream_t)stream));
@@ -403,7 +412,7 @@ tm_status tm_tonemap_forward_rgb(const float *v, int64_t ld_v, int32_t H, int32_
         if (!edges) return TM_ERR_ARG;
         TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
     }
-    const QueryParams q = to_query(p);
+    const QueryParams q = to_query(p, H, W);
     return from_hip(launch_forward_rgb(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
                                        ld_hist, plane_stride, edges, q, out, ld_out, rgb,
                                        ch_stride, ld_rgb, rgb_out, ch_stride_out, ld_rgb_out,
@@ -499,7 +508,7 @@ tm_status tm_tonemap_forward_train(const float *v, int64_t ld_v, int32_t H, int3
         if (!edges) return TM_ERR_ARG;
         TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
     }
-    const QueryParams q = to_query(p);
+    const QueryParams q = to_query(p, H, W);
     return from_hip(launch_forward(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets, hist_cum,
                                    ld_hist, plane_stride, edges, q, out, ld_out, resid,
                                    (hipStream_t)stream));
@@ -508,12 +517,12 @@ tm_status tm_tonemap_forward_train(const float *v, int64_t ld_v, int32_t H, int3
 // ------------------------------------------------------------------ a5
 size_t tm_backward_workspace_bytes(int32_t H, int32_t W, const tm_params *p) {
     if (check_image(H, W) != TM_OK || check_params(p) != TM_OK) return 0;
-    return make_bwd_plan(H, W, p->n_scales, p->ry, true).total;
+    return make_bwd_plan(H, W, p->n_scales, to_query(p, H, W).ry, true).total;
 }
 
 size_t tm_backward_resid_workspace_bytes(int32_t H, int32_t W, const tm_params *p) {
     if (check_image(H, W) != TM_OK || check_params(p) != TM_OK) return 0;
-    return make_bwd_plan(H, W, p->n_scales, p->ry, false).total;
+    return make_bwd_plan(H, W, p->n_scales, to_query(p, H, W).ry, false).total;
 }
 
 static tm_status run_backward_resid(const float *v, int64_t ld_v, int32_t H, int32_t W,
@@ -526,7 +535,7 @@ static tm_status run_backward_resid(const float *v, int64_t ld_v, int32_t H, int
     a.ld_v = ld_v;
     a.H = H;
     a.W = W;
-    a.p = to_query(p);
+    a.p = to_query(p, H, W);
     a.resid = resid;
     a.g = grad_out;
     a.ld_g = ld_g;
@@ -557,7 +566,7 @@ tm_status tm_tonemap_backward_resid(const float *v, int64_t ld_v, int32_t H, int
     TM_TRY(check_bwd_common(v, ld_v, H, W, p, grad_out, ld_g, grad_v, ld_gv, grad_params));
     if (!resid) return TM_ERR_ARG;
     if (!aligned(resid, 8)) return TM_ERR_ALIGN;   // pair planes are read as 8-byte pairs
-    BwdPlan plan = make_bwd_plan(H, W, p->n_scales, p->ry, false);
+    BwdPlan plan = make_bwd_plan(H, W, p->n_scales, to_query(p, H, W).ry, false);
     TM_TRY(check_ws(ws, ws_bytes, plan.total));
     return run_backward_resid(v, ld_v, H, W, p, resid, grad_out, ld_g, grad_v, ld_gv,
                               grad_params, plan, ws, (hipStream_t)stream);
@@ -578,12 +587,12 @@ tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W
         if (!edges) return TM_ERR_ARG;
         TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist_cum, p->n_bins - 1));
     }
-    BwdPlan plan = make_bwd_plan(H, W, p->n_scales, p->ry, true);
+    BwdPlan plan = make_bwd_plan(H, W, p->n_scales, to_query(p, H, W).ry, true);
     TM_TRY(check_ws(ws, ws_bytes, plan.total));
     float *resid = reinterpret_cast<float *>(static_cast<char *>(ws) + plan.resid);
     hipStream_t s = (hipStream_t)stream;
     // the residual planes from the tables (the query in training mode, no tone output)
-    const QueryParams q = to_query(p);
+    const QueryParams q = to_query(p, H, W);
     tm_status st = from_hip(launch_forward(v, ld_v, H, W, sat, ld_sat, (int)prec, offsets,
                                            hist_cum, ld_hist, plane_stride, edges, q, nullptr,
                                            W, resid, s));

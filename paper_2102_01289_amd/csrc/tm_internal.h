@@ -152,8 +152,9 @@ void comb_params(int H, int rows, const int *ry, int n_scales, int *p4, int *tee
 // ---------------------------------------------------------------- query (a4)
 struct QueryParams {
     int n_bins, n_scales;
-    int rx[8], ry[8];
+    int rx[8], ry[8];          // clamped to the image's width and height
     float eps, ld_min, ld_max;
+    const float *scalars;      // null, or device {eps, ld_min, ld_max} read at run time
 };
 
 struct FwdK {

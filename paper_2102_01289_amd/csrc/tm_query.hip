@@ -109,7 +109,15 @@ __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float
     const char *hist0 = reinterpret_cast<const char *>(k.hist - (k.ld_hist + 1));
 
     const int s = k.p.n_scales;
-    const float ldr = k.p.ld_max - k.p.ld_min;
+    // eps and the display range: the launch's values, or device values read at run time
+    float eps = k.p.eps, ld_min = k.p.ld_min, ld_max = k.p.ld_max;
+    if (k.p.scalars) {
+        const TM_GLOBAL float *sc = gptr(k.p.scalars);
+        eps = sc[0];
+        ld_min = sc[1];
+        ld_max = sc[2];
+    }
+    const float ldr = ld_max - ld_min;
     const float mu1 = P == kC32x2 ? gptr(k.offsets)[0] : 0.f;
     const float mu2 = P == kC32x2 ? gptr(k.offsets)[1] : 0.f;
     float num = 0.f, den = 0.f, lsum = 0.f, pn = 0.f, psum = 0.f;
@@ -149,10 +157,10 @@ __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float
                 }
             }
             const float Pj = (float)c * (float)inv_n;
-            const float Lj = __builtin_fmaf(ldr, Pj, k.p.ld_min);
+            const float Lj = __builtin_fmaf(ldr, Pj, ld_min);
             // Eq. 4 with the hardware reciprocal, held in [0, 1] (the reciprocal's last-bit
             // error could otherwise lift W_j of a very large variance one ulp above 1)
-            const float Wj = fminf(var * __builtin_amdgcn_rcpf(var + k.p.eps), 1.f);
+            const float Wj = fminf(var * __builtin_amdgcn_rcpf(var + eps), 1.f);
             if (k.maps) {
                 TM_GLOBAL float *mp = gptr(k.maps) + (int64_t)y * k.W + x;
                 __builtin_nontemporal_store(Lj, mp + (int64_t)j * k.mstride);
@@ -194,10 +202,10 @@ __device__ __forceinline__ void forward_tile(const FwdK &k, uint32_t tile, float
         for (int j = 0; j < kMaxS; ++j) {
             if (j < s) {
                 const float d = (lj[j] - L) * inv_d;
-                const float r = __builtin_amdgcn_rcpf(vj[j] + k.p.eps);
+                const float r = __builtin_amdgcn_rcpf(vj[j] + eps);
                 const float r2 = r * r;
                 E = __builtin_fmaf(d, -vj[j] * r2, E);
-                const float c = clj[j] ? 0.f : d * k.p.eps * r2;
+                const float c = clj[j] ? 0.f : d * eps * r2;
                 const float cn = c * nj[j];
                 TM_GLOBAL float *pr = gptr(k.resid) + 2 * ((int64_t)j * ps + (int64_t)y * k.W + x);
                 __builtin_nontemporal_store(-2.0f * cn * mj[j], pr);

@@ -198,3 +198,32 @@ def test_log_and_exposure_entry_argument_checks():
         fake, es, cs, ld, P_, H, W, fake, fake, out, cso, ldo, null)
     assert merge(0) == -1 and merge(4, out=null) == -1
     assert merge(4, ldo=W - 1) == -2 and merge(4, cso=H * W - 1) == -2
+
+
+def test_device_scalars_checks():
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    fake = P(1 << 20)      # never dereferenced: every call below fails its host checks
+    null = P(0)
+    # device scalars: a misaligned pointer is refused; host eps/ld are then not checked
+    p = tm.make_params(5, 2, [4, 2], [4, 2], eps=-1.0, ld_min=1.0, ld_max=0.0)
+    bad = (1 << 20) + 2
+    p.scalars = bad
+    ld, org, el = tm.table_geometry(10, 10)
+    assert lib.tm_tonemap_forward(fake, 10, 10, 10, fake, ld, 1, fake, fake, ld, el, fake,
+                                  ctypes.byref(p), fake, 10, null) == -3
+    p.scalars = None
+    assert lib.tm_tonemap_forward(fake, 10, 10, 10, fake, ld, 1, fake, fake, ld, el, fake,
+                                  ctypes.byref(p), fake, 10, null) == -1
+
+
+def test_radii_beyond_the_image_are_clamped_on_the_host():
+    # workspace sizing runs the comb schedule on the radii: INT32_MAX must size exactly as the
+    # image size does (and not overflow)
+    lib = _capi.load()
+    big = 2 ** 31 - 1
+    a = tm.make_params(5, 3, [big, 4000, 7], [big, 3000, big])
+    b = tm.make_params(5, 3, [4000, 4000, 7], [3000, 3000, 3000])
+    for f in (lib.tm_backward_workspace_bytes, lib.tm_backward_resid_workspace_bytes):
+        sa, sb = f(3000, 4000, ctypes.byref(a)), f(3000, 4000, ctypes.byref(b))
+        assert sa == sb > 0

@@ -7,30 +7,29 @@ import torch
 import oracle
 import paper_2102_01289_amd as tm
 from paper_2102_01289_amd.autograd import tonemap_luminance
-from _cases import edges_ref, lum_ref, rgb_case, to_dev
+from _cases import check_gradient, edges_ref, lum_ref, rgb_case, to_dev
 
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_grad(lum, n, rx, ry, eps, prec, g, ld=(0.0, 1.0)):
+def _gpu_grad(lum, n, rx, ry, eps, prec, g, ld=(0.0, 1.0), tables=False):
     v = to_dev(lum)
     p = tm.make_params(n, len(rx), rx, ry, eps, ld[0], ld[1])
     edges, offsets, _ = tm.tm_image_stats(v, n)
     sat, hist = tm.tm_integral_tables(v, prec, offsets, edges, n, "cumulative")
     gv, gp = tm.tm_tonemap_backward(v, sat, hist, edges, p, to_dev(g.astype(np.float32)), offsets)
     torch.cuda.synchronize()
-    return gv.cpu().numpy().astype(np.float64), gp.cpu().numpy()
+    out = gv.cpu().numpy().astype(np.float64), gp.cpu().numpy()
+    return (*out, sat, offsets) if tables else out
 
 
 def _check(lum, n, rx, ry, eps, prec, seed, ld=(0.0, 1.0), rtol=2e-4):
+    # the gradient at every pixel within the derived per-pixel bound (tests/_bounds.py), the
+    # scalar gradients within 2e-4 relative
     g = np.random.default_rng(seed).standard_normal(lum.shape).astype(np.float32)
-    gv, gp = _gpu_grad(lum, n, rx, ry, eps, prec, g, ld)
+    gv, gp, sat, offsets = _gpu_grad(lum, n, rx, ry, eps, prec, g, ld, tables=True)
     e = edges_ref(lum, n)
-    dv, gref = oracle.backward(lum, e, rx, ry, g.astype(np.float64), eps, ld[0], ld[1])
-    scale = np.max(np.abs(dv))
-    err = np.abs(gv - dv)
-    assert np.all(err <= rtol * scale + 1e-3 * np.abs(dv)), \
-        f"max err {err.max():.3e} vs scale {scale:.3e}"
+    dv, gref, _ = check_gradient(lum, e, rx, ry, eps, g, gv, sat, offsets, prec, ld)
     for a, b in zip(gp, gref):
         assert abs(a - b) <= 1e-6 * (1.0 + abs(b)) + rtol * abs(b), (gp, gref)
     return gv, dv
@@ -172,3 +171,26 @@ def test_training_forward_and_residual_backward(prec):
     mj = np.stack([oracle.box_filter(lum.astype(np.float64), rx[j], ry[j]) for j in range(5)]) / N
     r1 = -2 * r2 * mj
     assert np.max(np.abs(pairs[..., 0] - r1)) <= 1e-3 * np.max(np.abs(r1)) + 1e-12
+
+
+@pytest.mark.parametrize("prec", ["c32x2", "f64"])
+def test_radii_beyond_the_image_act_as_the_image_size(prec):
+    # Algorithm 1's clamping makes any radius >= the image's width (height) a whole-row
+    # (whole-column) window; the library clamps such radii to the image size, so INT32_MAX
+    # gives bit for bit what W (H) gives, in the forward, the training forward and the backward
+    H, W = 40, 70
+    big = 2 ** 31 - 1
+    rgb = to_dev(rgb_case(H, W, 5, seed=23))
+    g = to_dev(np.random.default_rng(6).standard_normal((H, W)).astype(np.float32))
+    outs = []
+    for rx, ry in (([big, W, 5], [H, big, 3]), ([W, W, 5], [H, H, 3])):
+        p = tm.make_params(5, 3, rx, ry, 0.1)
+        m = tm.ToneMapper(H, W, p, prec)
+        L = m.run(rgb).clone()
+        Lt = m.run_train(rgb).clone()
+        gv, gp = (t.clone() for t in m.backward_resid(g))
+        gt, gq = (t.clone() for t in m.backward(g))
+        torch.cuda.synchronize()
+        outs.append((L, Lt, gv, gp, gt, gq))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)

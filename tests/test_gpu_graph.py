@@ -50,3 +50,66 @@ def test_forward_and_backward_graph_replays(prec):
     fresh = tm.ToneMapper(H, W, p, prec).run(rgb)
     torch.cuda.synchronize()
     assert torch.equal(m.out, fresh)
+
+
+@pytest.mark.parametrize("recompute", [True, False])
+def test_autograd_forward_backward_graph_capture(recompute):
+    # The autograd Function passes eps, min L_d and max L_d to the kernels in device memory,
+    # so its forward and backward make no host synchronisation and record into one graph
+    # (torch's whole-network capture recipe: warm-up on a side stream, grads None before
+    # capture).  Every replay equals the eager pass; new scalar values take effect on replay.
+    from paper_2102_01289_amd.autograd import tonemap_luminance
+    from _cases import lum_ref
+    H, W = 96, 120
+    lum = to_dev(lum_ref(rgb_case(H, W, 5, seed=31)))
+    x = lum.clone().requires_grad_(True)
+    eps = torch.tensor(0.1, device="cuda", requires_grad=True)
+    lo = torch.tensor(0.0, device="cuda", requires_grad=True)
+    hi = torch.tensor(1.0, device="cuda", requires_grad=True)
+    g = to_dev(np.random.default_rng(5).standard_normal((H, W)).astype(np.float32))
+    leaves = (x, eps, lo, hi)
+
+    def step():
+        L = tonemap_luminance(x, eps, lo, hi, n_bins=5, n_scales=4, recompute=recompute)
+        L.backward(g)
+        return L
+
+    L_ref = step().detach().clone()
+    grads_ref = [t.grad.clone() for t in leaves]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            for t in leaves:
+                t.grad = None
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for t in leaves:
+        t.grad = None
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        L_static = step()
+    for rep in range(4):
+        L_static.zero_()
+        for t in leaves:
+            t.grad.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(L_static, L_ref), rep
+        for t, r in zip(leaves, grads_ref):
+            assert torch.equal(t.grad, r), rep
+        _ = torch.randn(4096, device="cuda").sum().item()   # eager work between replays
+    # a new eps read at replay time, without capturing again
+    with torch.no_grad():
+        eps.fill_(0.25)
+    graph.replay()
+    torch.cuda.synchronize()
+    x2 = lum.clone().requires_grad_(True)
+    e2 = torch.tensor(0.25, device="cuda", requires_grad=True)
+    L2 = tonemap_luminance(x2, e2, lo.detach(), hi.detach(), n_bins=5, n_scales=4,
+                           recompute=recompute)
+    L2.backward(g)
+    torch.cuda.synchronize()
+    assert torch.equal(L_static, L2.detach())
+    assert torch.equal(x.grad, x2.grad) and torch.equal(eps.grad, e2.grad)

@@ -398,3 +398,36 @@ def test_color_channel_ratios_and_exponent_law(orc):
     assert np.allclose(oa[0, pos] / oa[2, pos], (c[0, pos] / c[2, pos]) ** a, rtol=1e-13)
     # the black pixel is neutral and the negative channel is zero
     assert np.all(oa[:, 0, 0] == L[0, 0]) and oa[1, 1, 1] == 0.0
+
+
+def test_paper_radii_reproduce_the_paper_pyramid_example():
+    import oracle
+    # Section II-C: on a 2048 x 2048 image with five fields, the largest field is the image
+    # and the smallest is 128 x 128.  With r_j = floor(dim / 2^j) the smallest window spans
+    # 2 r_5 + 1 = 129 pixels (r_5 = 64) -- the paper's 128 up to the centre pixel -- and the
+    # largest (r_1 = 1024) covers the whole image from every pixel once clamped.
+    rx, ry = oracle.paper_radii(2048, 2048, 5)
+    assert rx == ry == [1024, 512, 256, 128, 64]
+    assert 2 * rx[-1] + 1 == 129
+    assert all(2 * a == b for a, b in zip(rx[1:], rx[:-1]))      # each field half the last
+    assert 2 * rx[0] + 1 >= 2048
+
+
+def test_oracle_results_do_not_depend_on_thread_count():
+    import oracle
+    lum = oracle.luminance(gen_wdr(45, 67, 5, -2.0, 4.0, 3).rgb)
+    e = oracle.exact_edges(lum.min(), lum.max(), 5)
+    rx, ry = oracle.paper_radii(45, 67, 4)
+    g = np.random.default_rng(0).standard_normal(lum.shape)
+    try:
+        oracle.set_threads(1)
+        a = oracle.forward(lum, e, rx, ry, 0.1, per_scale=True)
+        da, ga = oracle.backward(lum, e, rx, ry, g, 0.1)
+        oracle.set_threads(4)
+        b = oracle.forward(lum, e, rx, ry, 0.1, per_scale=True)
+        db, gb = oracle.backward(lum, e, rx, ry, g, 0.1)
+    finally:
+        oracle.set_threads(1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert np.array_equal(da, db) and ga == gb
