@@ -163,6 +163,22 @@ tm_status tm_prologue(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32
                       int32_t W, int32_t n_bins, float *lum, int64_t ld_lum, float *edges,
                       float *offsets, float *minmax, void *ws, size_t ws_bytes, void *stream);
 
+/* tm_prologue without a workspace, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * per-block partials of the reduction live in a static device array of the library,
+ * TM_PROLOGUE_SCRATCH_BYTES (32 KiB) per GPU, held until the process ends; every image size
+ * tm_prologue accepts fits (the reduction never uses more than 1024 partials), and a
+ * request that would need more returns TM_ERR_UNSUPPORTED.  No memory is allocated or
+ * freed.  Every call on one GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (on different streams, or from different threads before their work is ordered) race
+ * and give wrong statistics; calls ordered on one stream are safe.  Results are bitwise
+ * those of tm_prologue.  The first call on a device looks up the array's device address
+ * (a host-side query, not a stream operation); a failure there returns TM_ERR_HIP. */
+#define TM_PROLOGUE_SCRATCH_BYTES 32768
+tm_status tm_prologue_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                              int32_t W, int32_t n_bins, float *lum, int64_t ld_lum,
+                              float *edges, float *offsets, float *minmax, void *stream);
+
 /* Log-domain variance variant.  Section II-A builds the integral images "of i and i^2"
  * (Eq. 5) for Eq. 10's window variance; the method is also defined with that variance taken
  * of the logarithmic image l the bins are cut from.  This call writes

@@ -21,7 +21,7 @@ __all__ = [
     "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
     "residual_planes", "residual_pairs", "ToneMapper", "tonemap", "Batch",
-    "tm_tonemap_forward_rgb", "tonemap_rgb", "tm_tonemap_forward_maps",
+    "tm_tonemap_forward_rgb", "tonemap_rgb", "tm_tonemap_forward_maps", "tm_prologue_noalloc",
 ]
 
 
@@ -277,6 +277,27 @@ def tm_prologue(rgb: torch.Tensor, n_bins: int, stream=None):
     _ck("tm_prologue", _lib().tm_prologue(_vp(rgb), rgb.stride(0), rgb.stride(1), H, W, n_bins,
                                           _vp(lum), lum.stride(0), _vp(edges), _vp(offsets),
                                           _vp(minmax), _vp(ws), ws.numel(), _stream(stream)))
+    return lum, edges[:n_bins - 1], offsets, minmax
+
+
+def tm_prologue_noalloc(rgb: torch.Tensor, n_bins: int, lum=None, edges=None, offsets=None,
+                        minmax=None, stream=None):
+    """tm_prologue with no workspace (its partials live in the library's static device
+    array): (lum, edges, offsets, minmax).  Outputs may be passed in preallocated."""
+    _check_rgb(rgb)
+    _, H, W = rgb.shape
+    dev = rgb.device
+    if lum is None:
+        lum = torch.empty((H, W), dtype=torch.float32, device=dev)
+    if edges is None:
+        edges = torch.empty(max(n_bins - 1, 1), dtype=torch.float32, device=dev)
+    if offsets is None:
+        offsets = torch.empty(2, dtype=torch.float32, device=dev)
+    if minmax is None:
+        minmax = torch.empty(2, dtype=torch.float32, device=dev)
+    _ck("tm_prologue_noalloc", _lib().tm_prologue_noalloc(
+        _vp(rgb), rgb.stride(0), rgb.stride(1), H, W, n_bins, _vp(lum), lum.stride(0),
+        _vp(edges), _vp(offsets), _vp(minmax), _stream(stream)))
     return lum, edges[:n_bins - 1], offsets, minmax
 
 

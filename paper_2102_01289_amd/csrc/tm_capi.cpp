@@ -207,6 +207,21 @@ tm_status tm_prologue(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32
                                  (hipStream_t)stream));
 }
 
+tm_status tm_prologue_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                              int32_t W, int32_t n_bins, float *lum, int64_t ld_lum,
+                              float *edges, float *offsets, float *minmax, void *stream) {
+    TM_TRY(check_image(H, W));
+    if (!rgb || !lum || n_bins < 1 || n_bins > TM_MAX_BINS) return TM_ERR_ARG;
+    if (n_bins > 1 && !edges) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_rgb));
+    TM_TRY(check_plane(H, W, ld_lum));
+    if (ch_stride < (int64_t)H * ld_rgb) return TM_ERR_SHAPE;
+    static_assert(TM_PROLOGUE_SCRATCH_BYTES == kPrologueScratchBytes, "scratch size");
+    if (tm_image_stats_workspace_bytes(H, W) > kPrologueScratchBytes) return TM_ERR_UNSUPPORTED;
+    return from_hip(launch_stats_noalloc(rgb, ch_stride, ld_rgb, lum, ld_lum, H, W, n_bins,
+                                         edges, offsets, minmax, (hipStream_t)stream));
+}
+
 tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t W, float *logv,
                            int64_t ld_log, float *offsets, float *minmax, void *ws,
                            size_t ws_bytes, void *stream) {

@@ -46,6 +46,12 @@ hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, con
 hipError_t launch_log_stats(const float *lum, int64_t ld_lum, float *logv, int64_t ld_log, int H,
                             int W, float *offsets, float *minmax, StatsPartial *partials,
                             hipStream_t s);
+// launch_stats from RGB with the partials in the library's static per-device scratch array
+// (no workspace).  Fails with hipErrorInvalidValue if the partials would not fit.
+constexpr size_t kPrologueScratchBytes = 32768;
+hipError_t launch_stats_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rgb,
+                                float *lum_out, int64_t ld_lum_out, int H, int W, int n_bins,
+                                float *edges, float *offsets, float *minmax, hipStream_t s);
 
 // ---------------------------------------------------------------- multi-exposure front end
 size_t hdr_response_ws_bytes();

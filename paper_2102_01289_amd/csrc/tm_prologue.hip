@@ -8,6 +8,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "tm_device.h"
 #include "tm_internal.h"
 
@@ -359,6 +361,53 @@ hipError_t launch_log_stats(const float *lum, int64_t ld_lum, float *logv, int64
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- prologue without workspace
+// The reduction partials of tm_prologue_noalloc live in this file-scope device array (one
+// copy per GPU, for the life of the process).  Host code must not pass the array's name to a
+// kernel: in host code it is only a stand-in for the symbol.  Its device address is looked up
+// once per device with hipGetSymbolAddress, with that device current, and kept here.  Every
+// partial the stats kernel needs is written by its own block before the finalize kernel reads
+// it, so nothing has to be cleared between calls; calls that overlap on one GPU share the
+// array and race.
+static __device__ __align__(256) StatsPartial scratch[kPrologueScratchBytes / sizeof(StatsPartial)];
+static_assert(kPrologueScratchBytes / sizeof(StatsPartial) >= (size_t)kStatsMaxBlocks,
+              "the scratch array holds the largest number of partials");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+StatsPartial *scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static hipError_t scratch_address(StatsPartial **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_ptr[dev] = static_cast<StatsPartial *>(p);
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_stats_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rgb,
+                                float *lum_out, int64_t ld_lum_out, int H, int W, int n_bins,
+                                float *edges, float *offsets, float *minmax, hipStream_t s) {
+    if ((size_t)stats_blocks(H, W) * sizeof(StatsPartial) > kPrologueScratchBytes)
+        return hipErrorInvalidValue;
+    StatsPartial *part = nullptr;
+    const hipError_t e = scratch_address(&part);
+    if (e != hipSuccess) return e;
+    return launch_stats(rgb, ch_stride, ld_rgb, nullptr, 0, lum_out, ld_lum_out, H, W, n_bins,
+                        edges, offsets, minmax, part, s);
 }
 
 hipError_t launch_stats_batch(const StatsK *ks, const int64_t *part_prefix, int count,

@@ -227,3 +227,18 @@ def test_radii_beyond_the_image_are_clamped_on_the_host():
     for f in (lib.tm_backward_workspace_bytes, lib.tm_backward_resid_workspace_bytes):
         sa, sb = f(3000, 4000, ctypes.byref(a)), f(3000, 4000, ctypes.byref(b))
         assert sa == sb > 0
+
+
+def test_noalloc_prologue_checks():
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    fake = P(1 << 20)      # never dereferenced: every call below fails its host checks
+    null = P(0)
+    assert lib.tm_prologue_noalloc(null, 100, 10, 10, 10, 5, fake, 10, fake, fake, fake,
+                                   null) == -1
+    assert lib.tm_prologue_noalloc(fake, 100, 10, 0, 10, 5, fake, 10, fake, fake, fake,
+                                   null) == -2
+    assert lib.tm_prologue_noalloc(fake, 100, 10, 10, 10, 5, fake, 10, null, fake, fake,
+                                   null) == -1          # edges missing with n > 1
+    assert lib.tm_prologue_noalloc(fake, 50, 10, 10, 10, 5, fake, 10, fake, fake, fake,
+                                   null) == -2          # channel stride below H * ld
