@@ -118,8 +118,9 @@ typedef struct {
 const char *tm_status_string(tm_status s);
 
 /* The scan tiling an H x W image gets when an entry point is passed tune = NULL (host
- * function): 4 columns per lane from width 2048 up, else 2; 16 rows per tile, halved (not
- * below 4) while the image has fewer than 2048 tiles; 4 planes per pass. */
+ * function): 4 columns per lane from width 2048 up, else 2; rows per tile 4 (H < 900),
+ * 8 (H < 1800) or 16, halved (not below 4) while the image has fewer than 512 tiles; 4 planes
+ * per pass. */
 tm_status tm_default_tune(int32_t H, int32_t W, tm_tune *t);
 
 /* Radii of the receptive-field pyramid (Section II-C): the largest field is the image and
@@ -418,8 +419,20 @@ tm_status tm_batch_create(const tm_image_desc *descs, int32_t count, const tm_pa
  * tables together stay within 160 MiB (so that the fused query finds them still in the
  * memory-side cache); for each group, one launch per phase covers all its images (prologue
  * parts, per-image finalize, scan stages 1-3, fused query) -- 6 launches per group, no host
- * sync. */
+ * sync.  With concurrency set (tm_batch_set_concurrency), the groups are dealt to internal
+ * streams that start after the work already queued on `stream` and that `stream` waits for
+ * at the end, so phases of different groups overlap; the call stays ordered on `stream` and
+ * capturable into a graph. */
 tm_status tm_batch_forward(tm_batch *batch, void *stream);
+
+/* How tm_batch_forward spreads the work: `streams` (1..TM_BATCH_MAX_STREAMS) internal
+ * streams (1: everything on the caller's stream, the default), created here at the default
+ * priority and owned by the batch; at most `images_per_group` images per group (0: only the
+ * table rule, 160 MiB divided by the number of streams).  Groups are dealt, in order, to the
+ * stream with the fewest pixels so far.  Host call; not capturable itself.  Outputs are the
+ * same bit for bit for any setting. */
+#define TM_BATCH_MAX_STREAMS 8
+tm_status tm_batch_set_concurrency(tm_batch *batch, int32_t streams, int32_t images_per_group);
 
 /* Record tm_batch_forward into a HIP graph (stream must not be the null stream; nothing is
  * executed).  A later call replaces the graph. */

@@ -713,6 +713,12 @@ class Batch:
             self.ws.numel(), _stream(stream), ctypes.byref(h)))
         self.handle = h
 
+    def set_concurrency(self, streams: int = 1, images_per_group: int = 0):
+        """Spread forward() over `streams` internal streams (phases of different image groups
+        overlap), with at most `images_per_group` images per group (0: no limit)."""
+        _ck("tm_batch_set_concurrency", _lib().tm_batch_set_concurrency(
+            self.handle, int(streams), int(images_per_group)))
+
     def forward(self, stream=None):
         _ck("tm_batch_forward", _lib().tm_batch_forward(self.handle, _stream(stream)))
         return self.outs

@@ -86,6 +86,7 @@ SIGNATURES = {
     "tm_batch_create": (ctypes.c_int, [ctypes.POINTER(TmImageDesc), I32, PP, ctypes.c_int, PT, P,
                                        SZ, P, ctypes.POINTER(P)]),
     "tm_batch_forward": (ctypes.c_int, [P, P]),
+    "tm_batch_set_concurrency": (ctypes.c_int, [P, I32, I32]),
     "tm_batch_capture": (ctypes.c_int, [P, P]),
     "tm_batch_replay": (ctypes.c_int, [P, P]),
     "tm_batch_destroy": (ctypes.c_int, [P]),

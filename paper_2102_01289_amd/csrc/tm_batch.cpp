@@ -56,6 +56,14 @@ struct tm_batch {
     std::vector<char> host_tables;   // staging of the uploaded descriptor tables
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // concurrency: groups dealt to internal streams (forked from and joined back to the
+    // caller's stream), at most images_per_group images per group (0: table bytes only)
+    size_t per_entry = 0;
+    int images_per_group = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<int> group_stream;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
 };
 
 namespace {
@@ -205,8 +213,8 @@ size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int pre
         b->fk[i] = make_fwdk(lum, ld_lum, H, W, sat, ld, offsets, n > 1 ? hist : nullptr, ld,
                              elems, edges, qi, x.out, x.ld_out);
         b->parts[i + 1] = b->parts[i] + b->sk[i].nparts;
-        // scan work items: each tile is built as kFusedScanItems items
-        b->tiles[i + 1] = b->tiles[i] + (int64_t)kFusedScanItems * sp.tiles_x * sp.tiles_y;
+        // scan work items: each tile is its integral image plus hist_items histogram items
+        b->tiles[i + 1] = b->tiles[i] + (int64_t)(1 + b->ck[i].hist_items) * sp.tiles_x * sp.tiles_y;
         b->items[i + 1] = b->items[i] + scan_stage2_items(b->ck[i], true);
         b->qtiles[i + 1] = b->qtiles[i] + query_blocks(b->fk[i]);
     }
@@ -227,6 +235,65 @@ tm_status from_hip(hipError_t e) { return e == hipSuccess ? TM_OK : TM_ERR_HIP; 
 
 unsigned clampu(int64_t v, int64_t lo, int64_t hi) {
     return (unsigned)(v < lo ? lo : (v > hi ? hi : v));
+}
+
+// Image groups: consecutive descriptors whose integral tables together stay within
+// kGroupTableBytes divided by the number of streams (so that the groups in flight together
+// still fit the memory-side cache), of one scan variant, at most images_per_group images
+// (0: no limit), at
+// least one image each; their grids give one work item per block (per wave for the scan
+// tiles), handed out in order by the hardware, so the items in flight stay a compact window
+// of the list.  With several streams the groups are dealt in list order, each to the stream
+// with the fewest pixels so far (dealing them largest first measured no better).
+void make_groups(tm_batch *b) {
+    b->groups.clear();
+    b->group_stream.clear();
+    const size_t limit = kGroupTableBytes / (b->streams.empty() ? 1 : b->streams.size());
+    for (int i0 = 0; i0 < b->count;) {
+        int i1 = i0;
+        size_t bytes = 0;
+        while (i1 < b->count) {
+            const size_t bi = (size_t)b->fk[i1].plane_stride * b->per_entry;
+            if (i1 > i0 && (bytes + bi > limit || b->vec[i1] != b->vec[i0])) break;
+            if (b->images_per_group > 0 && i1 - i0 >= b->images_per_group) break;
+            bytes += bi;
+            ++i1;
+        }
+        tm_batch::Group g;
+        g.i0 = i0;
+        g.i1 = i1;
+        g.vec = b->vec[i0];
+        const int64_t kMaxGrid = ((int64_t)1 << 31) - 1;
+        g.g_stats = clampu(b->parts[i1] - b->parts[i0], 1, kMaxGrid);
+        g.g_tiles = clampu((b->tiles[i1] - b->tiles[i0] + 3) / 4, 1, kMaxGrid);
+        g.g_items = clampu((b->items[i1] - b->items[i0] + 255) / 256, 1, kMaxGrid);
+        g.g_query = clampu(b->qtiles[i1] - b->qtiles[i0], 1, kMaxGrid);   // one block per tile
+        b->groups.push_back(g);
+        i0 = i1;
+    }
+    const size_t ng = b->groups.size();
+    std::vector<int64_t> px(ng, 0);
+    for (size_t gi = 0; gi < ng; ++gi)
+        for (int i = b->groups[gi].i0; i < b->groups[gi].i1; ++i)
+            px[gi] += (int64_t)b->fk[i].H * b->fk[i].W;
+    std::vector<int64_t> load(b->streams.empty() ? 1 : b->streams.size(), 0);
+    b->group_stream.assign(ng, 0);
+    for (size_t gi = 0; gi < ng; ++gi) {
+        int best = 0;
+        for (int k = 1; k < (int)load.size(); ++k)
+            if (load[k] < load[best]) best = k;
+        load[best] += px[gi];
+        b->group_stream[gi] = best;
+    }
+}
+
+void release_streams(tm_batch *b) {
+    for (hipStream_t s : b->streams) hipStreamDestroy(s);
+    for (hipEvent_t e : b->ev_join) hipEventDestroy(e);
+    if (b->ev_fork) hipEventDestroy(b->ev_fork);
+    b->streams.clear();
+    b->ev_join.clear();
+    b->ev_fork = nullptr;
 }
 
 }  // namespace
@@ -256,32 +323,9 @@ tm_status tm_batch_create(const tm_image_desc *descs, int32_t count, const tm_pa
     b->prec = (int)prec;
     b->tune = t;
     layout(descs, count, p, (int)prec, t, static_cast<char *>(ws), b);
-    // Image groups (consecutive, tables within kGroupTableBytes, at least one image each)
-    // and their grids: one work item per block (per wave for the scan tiles), handed out
-    // in order by the hardware, so the items in flight stay a compact window of the list.
     for (int i = 0; i < count; ++i) b->h32 = b->h32 && hist_offsets_fit_32(b->fk[i]);
-    const size_t per_entry = entry_bytes((int)prec) + 4 * (size_t)(p->n_bins > 1 ? p->n_bins - 1 : 0);
-    for (int i0 = 0; i0 < count;) {
-        int i1 = i0;
-        size_t bytes = 0;
-        while (i1 < count) {
-            const size_t bi = (size_t)b->fk[i1].plane_stride * per_entry;
-            if (i1 > i0 && (bytes + bi > kGroupTableBytes || b->vec[i1] != b->vec[i0])) break;
-            bytes += bi;
-            ++i1;
-        }
-        tm_batch::Group g;
-        g.i0 = i0;
-        g.i1 = i1;
-        g.vec = b->vec[i0];
-        const int64_t kMaxGrid = ((int64_t)1 << 31) - 1;
-        g.g_stats = clampu(b->parts[i1] - b->parts[i0], 1, kMaxGrid);
-        g.g_tiles = clampu((b->tiles[i1] - b->tiles[i0] + 3) / 4, 1, kMaxGrid);
-        g.g_items = clampu((b->items[i1] - b->items[i0] + 255) / 256, 1, kMaxGrid);
-        g.g_query = clampu(b->qtiles[i1] - b->qtiles[i0], 1, kMaxGrid);   // one block per tile
-        b->groups.push_back(g);
-        i0 = i1;
-    }
+    b->per_entry = entry_bytes((int)prec) + 4 * (size_t)(p->n_bins > 1 ? p->n_bins - 1 : 0);
+    make_groups(b);
     // upload the descriptor tables (contiguous in ws from d_sk to the end of the prefixes)
     const size_t n_sk = sizeof(StatsK) * count, n_ck = sizeof(ScanK) * count,
                  n_fk = sizeof(FwdK) * count, n_pf = sizeof(int64_t) * (count + 1);
@@ -302,10 +346,41 @@ tm_status tm_batch_create(const tm_image_desc *descs, int32_t count, const tm_pa
     return TM_OK;
 }
 
+tm_status tm_batch_set_concurrency(tm_batch *b, int32_t streams, int32_t images_per_group) {
+    if (!b || streams < 1 || streams > TM_BATCH_MAX_STREAMS || images_per_group < 0)
+        return TM_ERR_ARG;
+    release_streams(b);
+    if (streams > 1) {
+        b->streams.resize(streams, nullptr);
+        b->ev_join.resize(streams, nullptr);
+        bool ok = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+        for (int k = 0; ok && k < streams; ++k) {
+            ok = hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming) == hipSuccess;
+        }
+        if (!ok) {
+            release_streams(b);
+            make_groups(b);
+            return TM_ERR_HIP;
+        }
+    }
+    b->images_per_group = images_per_group;
+    make_groups(b);
+    return TM_OK;
+}
+
 tm_status tm_batch_forward(tm_batch *b, void *stream) {
     if (!b) return TM_ERR_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    for (const tm_batch::Group &g : b->groups) {
+    hipStream_t s0 = (hipStream_t)stream;
+    const bool fork = !b->streams.empty();
+    if (fork) {   // the internal streams start after everything already queued on stream
+        if (hipEventRecord(b->ev_fork, s0) != hipSuccess) return TM_ERR_HIP;
+        for (hipStream_t t : b->streams)
+            if (hipStreamWaitEvent(t, b->ev_fork, 0) != hipSuccess) return TM_ERR_HIP;
+    }
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const tm_batch::Group &g = b->groups[gi];
+        hipStream_t s = fork ? b->streams[b->group_stream[gi]] : s0;
         const int n = g.i1 - g.i0;
         hipError_t e = launch_stats_batch(b->d_sk + g.i0, b->d_parts + g.i0, n, g.g_stats, s);
         if (e != hipSuccess) return TM_ERR_HIP;
@@ -316,6 +391,12 @@ tm_status tm_batch_forward(tm_batch *b, void *stream) {
         e = launch_forward_batch(b->d_fk + g.i0, b->d_qtiles + g.i0, n, b->prec, b->h32,
                                  g.g_query, s);
         if (e != hipSuccess) return TM_ERR_HIP;
+    }
+    if (fork) {   // and stream waits for all of them
+        for (size_t k = 0; k < b->streams.size(); ++k) {
+            if (hipEventRecord(b->ev_join[k], b->streams[k]) != hipSuccess) return TM_ERR_HIP;
+            if (hipStreamWaitEvent(s0, b->ev_join[k], 0) != hipSuccess) return TM_ERR_HIP;
+        }
     }
     return TM_OK;
 }
@@ -352,6 +433,7 @@ tm_status tm_batch_destroy(tm_batch *b) {
     if (!b) return TM_ERR_ARG;
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
+    release_streams(b);
     delete b;
     return TM_OK;
 }

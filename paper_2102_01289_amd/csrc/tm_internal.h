@@ -70,6 +70,7 @@ struct ScanTune {
     int chunk;      // histogram planes per pass: 2, 4, 8
 };
 ScanTune scan_tune_default(int H, int W);
+ScanTune scan_tune_adjoint(int H, int W);   // the backward's suffix scans
 bool scan_tune_valid(const ScanTune &t);
 
 // Workspace carve-up of the three-stage scan (a pure function of the shape and options).
@@ -99,6 +100,7 @@ struct ScanK {
     uint32_t *hist;
     int64_t ld_hist, plane_stride;
     int stream_out;               // tables larger than the memory-side cache: non-temporal stores
+    int hist_items, hist_chunks;  // histogram work items per tile, plane chunks per item
     // aggregates (each an array of quantities; see ScanPlan)
     void *rs_sat, *cs_sat, *tt_sat, *xc_sat, *cse_sat, *tte_sat;
     uint32_t *rs_h, *cs_h, *tt_h, *xc_h, *cse_h, *tte_h;
@@ -130,11 +132,11 @@ ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws);
 
 // Integral image + cumulative histogram of images [0, count): three launches over flattened
 // work lists (device arrays: ks[count], tile_prefix[count+1], item_prefix[count+1]).
-// Work items per scan tile when one launch builds both the integral image and the histogram
-// planes: the tile's integral image and its planes go to neighbouring waves of one block, so
-// each wave holds the state of one kind of table only (fewer registers, more waves in
-// flight) and the second read of the tile's luminance rows is served by the cache.
-constexpr int kFusedScanItems = 2;
+// A scan tile that builds both tables is 1 + k.hist_items work items (ScanK): its integral
+// image, then its histogram planes split into at most kMaxHistItems items, on neighbouring
+// waves, so each wave holds the state of one kind of table only (fewer registers, more waves
+// in flight) and the later reads of the tile's luminance rows are served by the cache.
+constexpr int kMaxHistItems = 8;
 
 struct BatchScan {
     const ScanK *ks;

@@ -333,7 +333,8 @@ __device__ __forceinline__ void load_group(const ScanK &k, int y, int n, int xl,
 }
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
-__device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
+__device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile, int cb = 0,
+                                            int ce = 1 << 30) {
     using A = Acc<P>;
     using T = typename A::T;
     constexpr int G = row_group<VEC, ADJ, false>();
@@ -351,7 +352,9 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile) {
     __shared__ T sh_rt[kLdsRows ? kWavesPerBlock * 2 * kRtRows * kRtPitch : 1];
     T *rt = sh_rt + (kLdsRows ? wave_id() * 2 * kRtRows * kRtPitch : 0);
 
-    for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
+    // a histogram-only work item covers the plane chunks [cb, ce)
+    const int ch0 = SAT ? 0 : cb, ch1 = SAT ? (nchunks > 1 ? nchunks : 1) : min(ce, nchunks);
+    for (int ch = ch0; ch < ch1; ++ch) {
         const bool do_sat = SAT && ch == 0;
         const bool do_h = HIST && ch < nchunks;
         const int p0 = ch * CHUNK;
@@ -815,7 +818,8 @@ __device__ __forceinline__ void tile_carries(const ScanK &k, bool do_sat, bool d
 }
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
-__device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
+__device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile, int cb = 0,
+                                            int ce = 1 << 30) {
     using A = Acc<P>;
     using T = typename A::T;
     using E = Entry<P>;
@@ -833,7 +837,9 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
     __shared__ ET sh_stage[(ADJ || !SAT) ? 1 : kWavesPerBlock * kWave * VEC];
     __shared__ double2 sh_adj[ADJ ? kWavesPerBlock * kWave * VEC : 1];
 
-    for (int ch = 0; ch < (SAT ? (nchunks > 1 ? nchunks : 1) : nchunks); ++ch) {
+    // a histogram-only work item covers the plane chunks [cb, ce)
+    const int ch0 = SAT ? 0 : cb, ch1 = SAT ? (nchunks > 1 ? nchunks : 1) : min(ce, nchunks);
+    for (int ch = ch0; ch < ch1; ++ch) {
         const bool do_sat = SAT && ch == 0;
         const bool do_h = HIST && ch < nchunks;
         const int p0 = ch * CHUNK;
@@ -1018,23 +1024,39 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile) {
 }
 
 // ---------------------------------------------------------------- single-image kernels
-// A launch that builds both the integral image and the histogram planes runs every tile as
-// kFusedScanItems work items (its integral image on an even wave, its planes on the next).
+// Work items of a tile: its integral image (one item, when built) and its histogram planes
+// (k.hist_items items, each k.hist_chunks plane chunks), on neighbouring waves, so that every
+// wave holds the state of one kind of table only and the tile's luminance rows are read from
+// the cache after the first.
 template <bool SAT, bool HIST>
-__host__ __device__ constexpr int items_per_tile() {
-    return (SAT && HIST) ? kFusedScanItems : 1;
+__host__ __device__ __forceinline__ int items_per_tile(const ScanK &k) {
+    return (SAT ? 1 : 0) + (HIST ? k.hist_items : 0);
+}
+
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ, bool THIRD>
+__device__ __forceinline__ void tile_item(const ScanK &k, int item) {
+    const int ipt = items_per_tile<SAT, HIST>(k);
+    const int tile = item / ipt, r = item - tile * ipt;
+    if constexpr (SAT) {
+        if (r == 0) {
+            if (THIRD) stage3_tile<P, VEC, CHUNK, true, false, ADJ>(k, tile);
+            else stage1_tile<P, VEC, CHUNK, true, false, ADJ>(k, tile);
+            return;
+        }
+    }
+    if constexpr (HIST) {
+        const int h = r - (SAT ? 1 : 0);
+        const int cb = h * k.hist_chunks, ce = cb + k.hist_chunks;
+        if (THIRD) stage3_tile<P, VEC, CHUNK, false, true, ADJ>(k, tile, cb, ce);
+        else stage1_tile<P, VEC, CHUNK, false, true, ADJ>(k, tile, cb, ce);
+    }
 }
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
 __global__ void __launch_bounds__(kBlock) scan_stage1(ScanK k) {
     const int item = blockIdx.x * kWavesPerBlock + wave_id();
-    if (item >= k.tiles_x * k.tiles_y * items_per_tile<SAT, HIST>()) return;
-    if constexpr (items_per_tile<SAT, HIST>() == 2) {
-        if (item & 1) stage1_tile<P, VEC, CHUNK, false, true, ADJ>(k, item >> 1);
-        else stage1_tile<P, VEC, CHUNK, true, false, ADJ>(k, item >> 1);
-    } else {
-        stage1_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, item);
-    }
+    if (item >= k.tiles_x * k.tiles_y * items_per_tile<SAT, HIST>(k)) return;
+    tile_item<P, VEC, CHUNK, SAT, HIST, ADJ, false>(k, item);
 }
 
 template <int P, bool SAT>
@@ -1046,13 +1068,8 @@ __global__ void __launch_bounds__(kBlock) scan_stage2(ScanK k, int64_t items) {
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ>
 __global__ void __launch_bounds__(kBlock) scan_stage3(ScanK k) {
     const int item = blockIdx.x * kWavesPerBlock + wave_id();
-    if (item >= k.tiles_x * k.tiles_y * items_per_tile<SAT, HIST>()) return;
-    if constexpr (items_per_tile<SAT, HIST>() == 2) {
-        if (item & 1) stage3_tile<P, VEC, CHUNK, false, true, ADJ>(k, item >> 1);
-        else stage3_tile<P, VEC, CHUNK, true, false, ADJ>(k, item >> 1);
-    } else {
-        stage3_tile<P, VEC, CHUNK, SAT, HIST, ADJ>(k, item);
-    }
+    if (item >= k.tiles_x * k.tiles_y * items_per_tile<SAT, HIST>(k)) return;
+    tile_item<P, VEC, CHUNK, SAT, HIST, ADJ, true>(k, item);
 }
 
 // ---------------------------------------------------------------- batched kernels
@@ -1071,20 +1088,7 @@ __global__ void __launch_bounds__(kBlock) scan_tiles_batch(const ScanK *__restri
     int i = g < total ? __builtin_amdgcn_readfirstlane(find_image(prefix, count, g)) : 0;
     for (; g < total; g += step) {
         while (g >= prefix[i + 1]) ++i;
-        const int item = (int)(g - prefix[i]);
-        if constexpr (items_per_tile<SAT, HIST>() == 2) {
-            const int tile = item >> 1;
-            if (item & 1) {
-                if (THIRD) stage3_tile<P, VEC, CHUNK, false, true, false>(ks[i], tile);
-                else stage1_tile<P, VEC, CHUNK, false, true, false>(ks[i], tile);
-            } else {
-                if (THIRD) stage3_tile<P, VEC, CHUNK, true, false, false>(ks[i], tile);
-                else stage1_tile<P, VEC, CHUNK, true, false, false>(ks[i], tile);
-            }
-        } else {
-            if (THIRD) stage3_tile<P, VEC, CHUNK, SAT, HIST, false>(ks[i], item);
-            else stage1_tile<P, VEC, CHUNK, SAT, HIST, false>(ks[i], item);
-        }
+        tile_item<P, VEC, CHUNK, SAT, HIST, false, THIRD>(ks[i], (int)(g - prefix[i]));
     }
 }
 
@@ -1103,7 +1107,7 @@ __global__ void __launch_bounds__(kBlock) scan_stage2_batch(const ScanK *__restr
 
 template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ = false>
 hipError_t run3(const ScanK &k, hipStream_t s) {
-    const int items = k.tiles_x * k.tiles_y * items_per_tile<SAT, HIST>();
+    const int items = k.tiles_x * k.tiles_y * items_per_tile<SAT, HIST>(k);
     const int grid = (items + kWavesPerBlock - 1) / kWavesPerBlock;
     hipLaunchKernelGGL((scan_stage1<P, VEC, CHUNK, SAT, HIST, ADJ>), dim3(grid), dim3(kBlock), 0, s, k);
     hipError_t e = hipGetLastError();
@@ -1186,11 +1190,28 @@ hipError_t launch_tables_batch(const BatchScan &b, hipStream_t s) {
     }
 }
 
+// Default tiling, from a sweep of every candidate over shapes 360..4000 per side: rows per
+// tile grow with the image height (taller tiles shorten the column-carry chains and amortise
+// each tile's carries), halved while the image would have fewer than 512 tiles.  32-row
+// tiles were up to 6 % faster from 2600 rows but raised the 12 MP output error by a third,
+// so tiles stop at 16 rows.
 ScanTune scan_tune_default(int H, int W) {
     ScanTune t;
     t.vec = W >= 2048 ? 4 : 2;
+    t.th = H < 900 ? 4 : H < 1800 ? 8 : 16;
+    const int64_t tw = 64 * t.vec;
+    const int64_t tiles_x = (W + tw - 1) / tw;
+    while (t.th > 4 && tiles_x * ((H + t.th - 1) / t.th) < 512) t.th /= 2;
+    t.chunk = 4;
+    return t;
+}
+
+// Tiling of the adjoint scans of the backward (FP64 deposit pairs in, gradient out): 16 rows
+// per tile, halved (not below 4) while the image has fewer than 2048 tiles.
+ScanTune scan_tune_adjoint(int H, int W) {
+    ScanTune t;
+    t.vec = W >= 2048 ? 4 : 2;
     t.th = 16;
-    // keep at least ~2048 tiles when the image allows
     const int64_t tw = 64 * t.vec;
     const int64_t tiles_x = (W + tw - 1) / tw;
     while (t.th > 4 && tiles_x * ((H + t.th - 1) / t.th) < 2048) t.th /= 2;
@@ -1258,6 +1279,11 @@ ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws) {
     k.n_bins = a.n_bins;
     k.layout = a.layout;
     k.n_planes = (a.n_planes > 0 && a.hist != nullptr) ? a.n_planes : 0;
+    // histogram work items per tile: many planes are spread over up to kMaxHistItems waves
+    const int nchunks = (k.n_planes + plan.chunk - 1) / plan.chunk;
+    k.hist_items = nchunks < kMaxHistItems ? nchunks : kMaxHistItems;
+    k.hist_chunks = k.hist_items > 0 ? (nchunks + k.hist_items - 1) / k.hist_items : 0;
+    if (k.hist_chunks > 0) k.hist_items = (nchunks + k.hist_chunks - 1) / k.hist_chunks;
     k.hist = a.hist;
     k.ld_hist = a.ld_hist;
     k.plane_stride = a.plane_stride;

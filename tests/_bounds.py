@@ -33,9 +33,9 @@ def tiling(H, W, vec=None, th=None):
     if vec is None:
         vec = 4 if W >= 2048 else 2
     if th is None:
-        th = 16
+        th = 4 if H < 900 else 8 if H < 1800 else 16
         tx = -(-W // (64 * vec))
-        while th > 4 and tx * (-(-H // th)) < 2048:
+        while th > 4 and tx * (-(-H // th)) < 512:
             th //= 2
     return vec, th
 

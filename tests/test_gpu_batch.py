@@ -101,3 +101,44 @@ def test_autotune_picks_a_valid_tiling(tmp_path, monkeypatch):
     assert t2.tile_w_vec in (2, 4, 8)
     t3, _ = autotune.tune_image(imgs[0], reps=2)       # second call is served by the cache
     assert (t3.tile_w_vec, t3.tile_h, t3.bin_chunk) == (t2.tile_w_vec, t2.tile_h, t2.bin_chunk)
+
+
+@pytest.mark.parametrize("streams,per_group", [(2, 0), (4, 1), (3, 2), (8, 1)])
+def test_batch_concurrency_changes_no_output_bit(streams, per_group):
+    # groups dealt to internal streams (forked from and joined back to the caller's stream):
+    # eager and graph-replayed outputs equal the single-stream batch bit for bit
+    imgs = _images(seed=3, shapes=SHAPES + [(40, 2500), (700, 900)])
+    b = tm.Batch(imgs, 5, 5)
+    ref = [o.clone() for o in b.forward()]
+    torch.cuda.synchronize()
+    b.set_concurrency(streams, per_group)
+    for o in b.outs:
+        o.fill_(float("nan"))
+    outs = [o.clone() for o in b.forward()]
+    torch.cuda.synchronize()
+    for i in range(len(imgs)):
+        assert torch.equal(outs[i], ref[i]), i
+    s = torch.cuda.Stream()
+    b.capture(s)
+    for rep in range(3):
+        for o in b.outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        b.replay(s)
+        s.synchronize()
+        for i in range(len(imgs)):
+            assert torch.equal(b.outs[i], ref[i]), (rep, i)
+        _ = torch.randn(1024, device="cuda").sum().item()
+    # back to one stream
+    b.set_concurrency(1, 0)
+    outs = [o.clone() for o in b.forward()]
+    torch.cuda.synchronize()
+    for i in range(len(imgs)):
+        assert torch.equal(outs[i], ref[i]), i
+
+
+def test_batch_concurrency_arguments():
+    b = tm.Batch(_images(seed=4, shapes=[(20, 30)]), 5, 5)
+    for bad in ((0, 0), (9, 0), (2, -1)):
+        with pytest.raises(tm.TmError):
+            b.set_concurrency(*bad)
