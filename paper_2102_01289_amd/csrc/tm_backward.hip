@@ -15,11 +15,15 @@
 // Each window sum is four corner reads of an integral image (Eq. 6), so its adjoint deposits
 // +-g R at those four corners and the integral image's adjoint is a suffix sum:
 //   dv = suffix2D(D1) + 2 v suffix2D(D2),   D = sum_j sum_corners +-g R_j.
-// Kernels: (1) the deposits that clamping piles onto the last column / row, as row sums and
-// (two-level) column sums; (2) the deposit gather D1, D2 (FP64, comb block order), written in
-// reversed pixel order so that (3) the ordinary three-stage prefix scan, run in adjoint
-// mode, yields the suffix sums and writes dv; (4) a streaming two-level fixed-order reduction
-// of the scalar gradients.  No atomics anywhere, so every result is bit-reproducible.
+// Kernels: (1) one launch that interleaves two independent kinds of block: border blocks,
+// which stream g, E, Pbar and the residual pairs and form the deposits that clamping piles
+// onto the last column / row (row sums and partial column sums) and the scalar partials,
+// and deposit blocks, which gather D1, D2 (FP64, comb block order) at every virtual pixel
+// off the last column and row, written in reversed pixel order; (2) fixed-order sums of the
+// border partials and of the scalar gradients; (3) the deposits of the last column and row
+// (only clamped ranges reach them); (4) the ordinary three-stage prefix scan, run in adjoint
+// mode, which yields the suffix sums and writes dv.  No atomics anywhere, so every result is
+// bit-reproducible.
 #include "tm_device.h"
 #include "tm_internal.h"
 
@@ -46,7 +50,10 @@ struct BwdK {
     double *Cb;      // [2][s][W]  column range sums
     double2 *Dr;     // [H][W] deposits {D1, D2} in reversed order
     double *part;    // [ncol * nchunks][3] scalar partials
+    double *gp;      // [3] scalar gradients
+    double *K;       // [2][s] totals of the row range sums over each field's clamped rows
     int tiles_x, p4, teeth, nchunks, chunk;
+    uint32_t ndep, nbor;  // deposit and border blocks of the interleaved launch
 };
 
 // Residual pair plane of field j: {R1_j, R2_j} per pixel, pitch W.
@@ -77,115 +84,132 @@ __device__ Sum3 block_sum3(Sum3 v) {
     return r;
 }
 
-// (1) One streaming pass over g, the residual pairs, E and Pbar, one block per (64 columns,
-// chunk rows):
-//   Rp[q][j][ct][y] = sum over the tile's columns x >= W-1-rx_j of g R_qj(x, y),
-//   Cp[q][j][chunk][x] = sum over the tile's rows y >= H-1-ry_j of g R_qj(x, y),
-//   part[block] = {sum g E, sum g (1 - Pbar), sum g Pbar},
-// each combined in a fixed order.  A residual pair is loaded only where some field needs it.
-// S: the number of fields, fixed at compile time so that a row's state holds only the fields
-// in use.
+// (1a) Border block bid (64 columns, chunk rows): streaming passes over g, E, Pbar and the
+// residual pairs.  First the scalar partials
+//   part[bid] = {sum g E, sum g (1 - Pbar), sum g Pbar},
+// then, one field at a time (so the per-row state stays a few registers), only where the
+// field's clamped ranges reach this block:
+//   Rp[q][j][ct][y] = sum over the tile's columns x >= W-1-rx_j of g R_qj(x, y)
+//                     (tiles that end right of W-1-rx_j),
+//   Cp[q][j][chunk][x] = sum over the chunk's rows y >= H-1-ry_j of g R_qj(x, y)
+//                     (chunks that end below H-1-ry_j).
+// Entries of Rp and Cp outside those ranges are never written nor read.  Every sum is in a
+// fixed order.  Rows are wave-uniform (scalar row bases, 32-bit lane offsets), two rows in
+// flight per wave.
 template <int S>
-__global__ void __launch_bounds__(kBlock) border_scalar_kernel(BwdK k) {
-    constexpr int s = S;
+__device__ __forceinline__ void border_block(const BwdK &k, int bid) {
     const int ncol = (k.W + kWave - 1) / kWave;
-    const int ct = blockIdx.x % ncol, ch = blockIdx.x / ncol;
+    const int ct = bid % ncol, ch = bid / ncol;
     const int x = ct * kWave + lane_id(), w = wave_id();
     const int y0 = ch * k.chunk, y1 = min(k.H, y0 + k.chunk);
     const int64_t hw = (int64_t)k.H * k.W;
-    const float *E = k.R + 2 * (int64_t)s * hw, *Pb = E + hw;
-    int lox[S], loy[S];
-    double cacc[2][S];
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-        lox[j] = max(k.W - 1 - k.p.rx[j], 0);
-        loy[j] = max(k.H - 1 - k.p.ry[j], 0);
-        cacc[0][j] = cacc[1][j] = 0.0;
-    }
-    __shared__ double shr[2 * S][kChunkMax];
-    Sum3 sacc{0.0, 0.0, 0.0};
+    const float *E = k.R + 2 * (int64_t)S * hw, *Pb = E + hw;
     const int xc = min(x, k.W - 1);      // in-image address for the lanes past the edge
     const bool in = x < k.W;
     const int tile_end = min(ct * kWave + kWave, k.W);
-    // every load of a row in one phase; the next row of this wave is loaded before the
-    // current one is reduced
-    struct Row {
-        float g, e, p;
-        float2 r[S];
-    };
-    auto load_row = [&](int y, Row &q) {
-        const int64_t o = (int64_t)y * k.W + xc;
-        q.g = k.g[(int64_t)y * k.ld_g + xc];
-        q.e = E[o];
-        q.p = Pb[o];
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            q.r[j] = make_float2(0.f, 0.f);
-            // wave-uniform: does any field-j range sum need this tile row?
-            if (tile_end > lox[j] || y >= loy[j]) q.r[j] = rpair(k, j)[o];
+    const uint32_t o4 = (uint32_t)xc * 4u, o8 = (uint32_t)xc * 8u;
+    auto grow = [&](int y) { return reinterpret_cast<const char *>(k.g + (int64_t)y * k.ld_g); };
+    {
+        Sum3 sacc{0.0, 0.0, 0.0};
+        float g[2], e[2], pb[2];
+        auto load = [&](int y, int u) {
+            const int64_t ro = (int64_t)y * k.W;
+            g[u] = load_at<float>(grow(y), o4);
+            e[u] = load_at<float>(reinterpret_cast<const char *>(E + ro), o4);
+            pb[u] = load_at<float>(reinterpret_cast<const char *>(Pb + ro), o4);
+        };
+        auto use = [&](int u) {
+            const double gx = in ? (double)g[u] : 0.0;
+            const double pv = (double)pb[u];
+            sacc.a = __builtin_fma(gx, (double)e[u], sacc.a);
+            sacc.b = __builtin_fma(gx, 1.0 - pv, sacc.b);
+            sacc.c = __builtin_fma(gx, pv, sacc.c);
+        };
+        int y = y0 + w;   // wave-uniform
+        if (y < y1) load(y, 0);
+        while (y < y1) {
+            if (y + kRows < y1) load(y + kRows, 1);
+            use(0);
+            y += kRows;
+            if (y >= y1) break;
+            if (y + kRows < y1) load(y + kRows, 0);
+            use(1);
+            y += kRows;
         }
-    };
-    Row cur, nxt;
-    int y = y0 + w;   // wave-uniform
-    if (y < y1) load_row(y, cur);
-    for (; y < y1; y += kRows) {
-        const bool more = y + kRows < y1;
-        if (more) load_row(y + kRows, nxt);
-        const double gx = in ? (double)cur.g : 0.0;
-        const double pb = (double)cur.p;
-        sacc.a = __builtin_fma(gx, (double)cur.e, sacc.a);
-        sacc.b = __builtin_fma(gx, 1.0 - pb, sacc.b);
-        sacc.c = __builtin_fma(gx, pb, sacc.c);
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const double a = gx * (double)cur.r[j].x, b = gx * (double)cur.r[j].y;
-            if (y >= loy[j]) { cacc[0][j] += a; cacc[1][j] += b; }
-            double ra = 0.0, rb = 0.0;
-            if (tile_end > lox[j]) {   // block-uniform: the row range reaches this tile
-                const bool inr = x >= lox[j];
-                ra = wave_sum<Acc<kF64>>(inr ? a : 0.0);
-                rb = wave_sum<Acc<kF64>>(inr ? b : 0.0);
-            }
-            if (lane_id() == 0) {
-                shr[j][y - y0] = ra;
-                shr[S + j][y - y0] = rb;
-            }
+        const Sum3 tot = block_sum3(sacc);
+        if (threadIdx.x == 0) {
+            k.part[3 * bid] = tot.a;
+            k.part[3 * bid + 1] = tot.b;
+            k.part[3 * bid + 2] = tot.c;
         }
-        if (more) cur = nxt;
     }
-    // column partials: the four waves' sums in a fixed order
+    __shared__ double shr[2][kChunkMax];
     __shared__ double shc[kRows][kWave];
-    for (int qj = 0; qj < 2 * s; ++qj) {
-        const int q = qj / s, j = qj % s;
-        double v = 0.0;
-#pragma unroll
-        for (int jj = 0; jj < S; ++jj)
-            if (jj == j) v = q ? cacc[1][jj] : cacc[0][jj];
-        __syncthreads();
-        shc[w][lane_id()] = v;
-        __syncthreads();
-        if (w == 0 && x < k.W) {
-            double r = shc[0][lane_id()];
-            for (int i = 1; i < kRows; ++i) r += shc[i][lane_id()];
-            k.Cp[(((int64_t)q * s + j) * k.nchunks + ch) * k.W + x] = r;
+    for (int j = 0; j < S; ++j) {
+        const int lox = max(k.W - 1 - k.p.rx[j], 0), loy = max(k.H - 1 - k.p.ry[j], 0);
+        const bool rows = tile_end > lox, cols = y1 > loy;   // block-uniform
+        if (!rows && !cols) continue;
+        const bool inr = in && x >= lox;
+        const char *Rj = reinterpret_cast<const char *>(rpair(k, j));
+        double c0 = 0.0, c1 = 0.0;
+        float g[2];
+        float2 r[2];
+        auto load = [&](int y, int u) {
+            g[u] = load_at<float>(grow(y), o4);
+            r[u] = load_at<float2>(Rj + (int64_t)y * k.W * 8, o8);
+        };
+        auto use = [&](int y, int u) {
+            const double gx = in ? (double)g[u] : 0.0;
+            const double a = gx * (double)r[u].x, b = gx * (double)r[u].y;
+            if (y >= loy) {
+                c0 += a;
+                c1 += b;
+            }
+            if (rows) {
+                double ra, rb;
+                wave_sum2(inr ? a : 0.0, inr ? b : 0.0, ra, rb);
+                if (lane_id() == 0) {
+                    shr[0][y - y0] = ra;
+                    shr[1][y - y0] = rb;
+                }
+            }
+        };
+        int y = (rows ? y0 : max(y0, loy)) + w;   // wave-uniform
+        if (y < y1) load(y, 0);
+        while (y < y1) {
+            if (y + kRows < y1) load(y + kRows, 1);
+            use(y, 0);
+            y += kRows;
+            if (y >= y1) break;
+            if (y + kRows < y1) load(y + kRows, 0);
+            use(y, 1);
+            y += kRows;
         }
-    }
-    // row partials, coalesced along y
-    for (int t = threadIdx.x; t < 2 * s * (y1 - y0); t += kBlock) {
-        const int qj = t / (y1 - y0), r = t % (y1 - y0);
-        const int q = qj / s, j = qj % s;
-        k.Rp[(((int64_t)q * s + j) * ncol + ct) * k.H + y0 + r] = shr[q * S + j][r];
-    }
-    const Sum3 tot = block_sum3(sacc);
-    if (threadIdx.x == 0) {
-        k.part[3 * blockIdx.x] = tot.a;
-        k.part[3 * blockIdx.x + 1] = tot.b;
-        k.part[3 * blockIdx.x + 2] = tot.c;
+        if (cols) {   // the four waves' column sums in a fixed order
+            for (int q = 0; q < 2; ++q) {
+                __syncthreads();
+                shc[w][lane_id()] = q ? c1 : c0;
+                __syncthreads();
+                if (w == 0 && x < k.W) {
+                    double v = shc[0][lane_id()];
+                    for (int i = 1; i < kRows; ++i) v += shc[i][lane_id()];
+                    k.Cp[(((int64_t)q * S + j) * k.nchunks + ch) * k.W + x] = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (rows) {   // row sums, coalesced along y
+            for (int t = threadIdx.x; t < 2 * (y1 - y0); t += kBlock) {
+                const int q = t / (y1 - y0), rr = t % (y1 - y0);
+                k.Rp[(((int64_t)q * S + j) * ncol + ct) * k.H + y0 + rr] = shr[q][rr];
+            }
+        }
+        __syncthreads();
     }
 }
 
-// (1') Rb[q][j][y] = sum over column tiles of Rp and Cb[q][j][x] = sum over row chunks of Cp,
-// in a fixed order, loads issued 16 at a time (the pass is a few memory round trips long).
+// (2) Sums of border partials over column tiles / row chunks in a fixed order, loads issued
+// 16 at a time (the pass is a few memory round trips long).
 __device__ __forceinline__ double strided_sum(const double *src, int n, int64_t stride) {
     constexpr int kB = 16;
     double r = 0.0;
@@ -206,55 +230,76 @@ __device__ __forceinline__ double strided_sum(const double *src, int n, int64_t 
     return r;
 }
 
+// (2) Rb[q][j][y] = sum over column tiles of Rp and Cb[q][j][x] = sum over row chunks of Cp;
+// 2s blocks form the totals K of the Rb terms over each field's clamped rows (for the
+// bottom-right corner), and the last block adds the border blocks' scalar partials into the
+// three scalar gradients.  All in a fixed order.
 __global__ void __launch_bounds__(kBlock) border_reduce_kernel(BwdK k) {
     const int s = k.p.n_scales;
     const int ncol = (k.W + kWave - 1) / kWave;
+    const int nK = 2 * s;
+    if (blockIdx.x >= gridDim.x - 1 - nK && blockIdx.x < gridDim.x - 1) {
+        // K[q][j] = sum over y >= H-1-ry_j of Rb[q][j][y], each Rb term formed as below
+        const int qj = (int)(blockIdx.x - (gridDim.x - 1 - nK)), j = qj % s;
+        const int ct0 = max(k.W - 1 - k.p.rx[j], 0) / kWave;
+        const int y0 = max(k.H - 1 - k.p.ry[j], 0);
+        double acc = 0.0;
+        for (int y = y0 + (int)threadIdx.x; y < k.H; y += kBlock)
+            acc += strided_sum(k.Rp + ((int64_t)qj * ncol + ct0) * k.H + y, ncol - ct0, k.H);
+        acc = wave_sum<Acc<kF64>>(acc);
+        __shared__ double shp[kRows];
+        if (lane_id() == 0) shp[wave_id()] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double r = shp[0];
+            for (int i = 1; i < kRows; ++i) r += shp[i];
+            k.K[qj] = r;
+        }
+        return;
+    }
+    if (blockIdx.x == gridDim.x - 1) {
+        Sum3 acc{0.0, 0.0, 0.0};
+        for (uint32_t i = threadIdx.x; i < k.nbor; i += kBlock) {
+            acc.a += k.part[3 * i];
+            acc.b += k.part[3 * i + 1];
+            acc.c += k.part[3 * i + 2];
+        }
+        const Sum3 r = block_sum3(acc);
+        if (threadIdx.x == 0) {
+            k.gp[0] = r.a;
+            k.gp[1] = r.b;
+            k.gp[2] = r.c;
+        }
+        return;
+    }
     const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t nr = (int64_t)2 * s * k.H, nc = (int64_t)2 * s * k.W;
+    // only the tiles / chunks that the field's clamped range reaches hold partials
     if (id < nr) {
         const int64_t qj = id / k.H, y = id % k.H;
-        k.Rb[qj * k.H + y] = strided_sum(k.Rp + qj * ncol * k.H + y, ncol, k.H);
+        const int j = (int)(qj % s), ct0 = max(k.W - 1 - k.p.rx[j], 0) / kWave;
+        k.Rb[qj * k.H + y] =
+            strided_sum(k.Rp + (qj * ncol + ct0) * k.H + y, ncol - ct0, k.H);
     } else if (id < nr + nc) {
         const int64_t i = id - nr, qj = i / k.W, x = i % k.W;
-        k.Cb[qj * k.W + x] = strided_sum(k.Cp + qj * k.nchunks * k.W + x, k.nchunks, k.W);
+        const int j = (int)(qj % s), ch0 = max(k.H - 1 - k.p.ry[j], 0) / k.chunk;
+        k.Cb[qj * k.W + x] =
+            strided_sum(k.Cp + (qj * k.nchunks + ch0) * k.W + x, k.nchunks - ch0, k.W);
     }
 }
 
-// (2) deposits.  Virtual pixel (x', y') holds the deposit at corner c = (W-1-x', H-1-y').
-// For field j the corners that equal c come from at most one pixel per corner type,
-// except where clamping maps a whole range of pixels onto the last column / row; those
-// ranges use Rb, Cb and (for the bottom-right corner) their total K, which the block holding
-// virtual pixel (0, 0) forms cooperatively before use.  The four gathers of a field are
+// (1b) Deposit block: virtual pixel (x', y') holds the deposit at corner c = (W-1-x',
+// H-1-y').  For field j the corners that equal c come from at most one pixel per corner type,
+// except where clamping maps a whole range of pixels onto the last column / row; the last
+// column and row receive nothing else, and (3) writes them.  The four gathers of a field are
 // issued together, branch-free: a corner that does not exist reads a clamped in-image
 // address with weight 0 (such lanes share one cache line).  Rows are wave-uniform.
 // S: the number of fields, fixed at compile time so that the gathers of every field are
 // issued together (a loop with a run-time bound keeps one field's loads in flight at a time).
 template <int S>
-__global__ void __launch_bounds__(kBlock) deposit_kernel(BwdK k) {
-    constexpr int s = S;
-    __shared__ double shK[2][kS];
+__device__ __forceinline__ void deposit_block(const BwdK &k, uint32_t tile) {
     int tx, rg;
-    comb_map(xcd_tile(blockIdx.x, gridDim.x), k.tiles_x, k.p4, k.teeth, tx, rg);
-    if (tx == 0 && rg == 0) {
-        __shared__ double shp[kRows][2 * kS];
-        const int w = wave_id();
-        for (int qj = 0; qj < 2 * s; ++qj) {
-            const int q = qj / s, j = qj % s;
-            const int y0 = max(k.H - 1 - k.p.ry[j], 0);
-            double acc = 0.0;
-            for (int y = y0 + (int)threadIdx.x; y < k.H; y += kBlock)
-                acc += k.Rb[((int64_t)q * s + j) * k.H + y];
-            acc = wave_sum<Acc<kF64>>(acc);
-            if (lane_id() == 0) shp[w][qj] = acc;
-        }
-        __syncthreads();
-        if (threadIdx.x < (unsigned)(2 * s)) {
-            double r = shp[0][threadIdx.x];
-            for (int i = 1; i < kRows; ++i) r += shp[i][threadIdx.x];
-            shK[threadIdx.x / s][threadIdx.x % s] = r;
-        }
-        __syncthreads();
-    }
+    comb_map(tile, k.tiles_x, k.p4, k.teeth, tx, rg);
     const int xv = tx * kWave + lane_id();
     const int yv = rg * kRows + wave_id();
     if (xv >= k.W || yv >= k.H) return;
@@ -288,59 +333,84 @@ __global__ void __launch_bounds__(kBlock) deposit_kernel(BwdK k) {
     }
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-        {
-            const int rx = k.p.rx[j], ry = k.p.ry[j];
-            const int pxp = cx - rx;        // pixel whose x+ corner is cx (cx < W-1)
-            const int pxm = cx + rx + 1;    // pixel whose x- corner is cx
-            const int pyp = cy - ry;
-            const int pym = cy + ry + 1;
-            const bool okxp = !lastx && pxp >= 0, okxm = pxm <= k.W - 1;
-            const bool okyp = !lasty && pyp >= 0, okym = pym <= k.H - 1;
-            const float2 r_pp = rv[j][0], r_mp = rv[j][1], r_pm = rv[j][2], r_mm = rv[j][3];
-            const float g_pp = gw[j][0], g_mp = gw[j][1], g_pm = gw[j][2], g_mm = gw[j][3];
-            const double w_pp = okxp && okyp ? (double)g_pp : 0.0;
-            const double w_mp = okxm && okyp ? -(double)g_mp : 0.0;
-            const double w_pm = okxp && okym ? -(double)g_pm : 0.0;
-            const double w_mm = okxm && okym ? (double)g_mm : 0.0;
-            d0 = __builtin_fma(w_pp, (double)r_pp.x, d0);
-            d1 = __builtin_fma(w_pp, (double)r_pp.y, d1);
-            d0 = __builtin_fma(w_mp, (double)r_mp.x, d0);
-            d1 = __builtin_fma(w_mp, (double)r_mp.y, d1);
-            d0 = __builtin_fma(w_pm, (double)r_pm.x, d0);
-            d1 = __builtin_fma(w_pm, (double)r_pm.y, d1);
-            d0 = __builtin_fma(w_mm, (double)r_mm.x, d0);
-            d1 = __builtin_fma(w_mm, (double)r_mm.y, d1);
-            if (lastx || lasty) {
-                // clamped corners: whole ranges of pixels deposit on the last column / row
-                const double *R0 = k.Rb + (int64_t)j * k.H, *R1 = k.Rb + ((int64_t)s + j) * k.H;
-                const double *C0 = k.Cb + (int64_t)j * k.W, *C1 = k.Cb + ((int64_t)s + j) * k.W;
-                if (lastx && !lasty && pyp >= 0) { d0 += R0[pyp]; d1 += R1[pyp]; }
-                if (lasty && !lastx && pxp >= 0) { d0 += C0[pxp]; d1 += C1[pxp]; }
-                if (lastx && lasty) { d0 += shK[0][j]; d1 += shK[1][j]; }
-                if (lasty && okxm) { d0 -= C0[pxm]; d1 -= C1[pxm]; }
-                if (lastx && okym) { d0 -= R0[pym]; d1 -= R1[pym]; }
-            }
-        }
+        const int rx = k.p.rx[j], ry = k.p.ry[j];
+        const int pxp = cx - rx;        // pixel whose x+ corner is cx (cx < W-1)
+        const int pxm = cx + rx + 1;    // pixel whose x- corner is cx
+        const int pyp = cy - ry;
+        const int pym = cy + ry + 1;
+        const bool okxp = !lastx && pxp >= 0, okxm = pxm <= k.W - 1;
+        const bool okyp = !lasty && pyp >= 0, okym = pym <= k.H - 1;
+        const float2 r_pp = rv[j][0], r_mp = rv[j][1], r_pm = rv[j][2], r_mm = rv[j][3];
+        const double w_pp = okxp && okyp ? (double)gw[j][0] : 0.0;
+        const double w_mp = okxm && okyp ? -(double)gw[j][1] : 0.0;
+        const double w_pm = okxp && okym ? -(double)gw[j][2] : 0.0;
+        const double w_mm = okxm && okym ? (double)gw[j][3] : 0.0;
+        d0 = __builtin_fma(w_pp, (double)r_pp.x, d0);
+        d1 = __builtin_fma(w_pp, (double)r_pp.y, d1);
+        d0 = __builtin_fma(w_mp, (double)r_mp.x, d0);
+        d1 = __builtin_fma(w_mp, (double)r_mp.y, d1);
+        d0 = __builtin_fma(w_pm, (double)r_pm.x, d0);
+        d1 = __builtin_fma(w_pm, (double)r_pm.y, d1);
+        d0 = __builtin_fma(w_mm, (double)r_mm.x, d0);
+        d1 = __builtin_fma(w_mm, (double)r_mm.y, d1);
     }
-    __builtin_nontemporal_store(d0, &k.Dr[(int64_t)yv * k.W + xv].x);
-    __builtin_nontemporal_store(d1, &k.Dr[(int64_t)yv * k.W + xv].y);
+    // one 16-byte non-temporal store per lane (the last column and row get zero here)
+    typedef double dbl2 __attribute__((ext_vector_type(2)));
+    dbl2 d;
+    d.x = d0;
+    d.y = d1;
+    __builtin_nontemporal_store(d, reinterpret_cast<dbl2 *>(k.Dr + (int64_t)yv * k.W + xv));
 }
 
-// (4) scalar gradients: one block adds the per-block partials of (1) in a fixed order.
-__global__ void __launch_bounds__(kBlock) scalar_finalize_kernel(const double *part, int nparts,
-                                                                 double *out) {
-    Sum3 acc{0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < nparts; i += kBlock) {
-        acc.a += part[3 * i];
-        acc.b += part[3 * i + 1];
-        acc.c += part[3 * i + 2];
+// (1) The interleaved launch.  Blocks reach the 8 XCDs round-robin by index; XCD x receives
+// one contiguous range of the deposit tiles (in comb order) and one of the border blocks,
+// and its i-th block is a border block exactly when floor((i+1) nb / t) > floor(i nb / t)
+// (nb border and t blocks in all on that XCD), which spreads the border blocks evenly
+// between the deposit blocks.  The two kinds use different units (arithmetic against memory
+// latency), so each covers the other's stalls.  Every block index maps to one work item or
+// none (the grid is rounded up to whole rounds of 8).
+template <int S>
+__global__ void __launch_bounds__(kBlock) border_deposit_kernel(BwdK k) {
+    constexpr uint32_t kXcd = 8;
+    const uint32_t xcd = blockIdx.x % kXcd, i = blockIdx.x / kXcd;
+    const uint32_t qd = k.ndep / kXcd, rd = k.ndep % kXcd;
+    const uint32_t qb = k.nbor / kXcd, rb = k.nbor % kXcd;
+    const uint32_t cd = qd + (xcd < rd ? 1u : 0u), cb = qb + (xcd < rb ? 1u : 0u);
+    const uint32_t t = cd + cb;
+    if (i >= t) return;
+    const uint32_t nb0 = (uint32_t)((uint64_t)i * cb / t);
+    const uint32_t nb1 = (uint32_t)((uint64_t)(i + 1) * cb / t);
+    if (nb1 > nb0)
+        border_block<S>(k, (int)(xcd * qb + min(xcd, rb) + nb0));
+    else
+        deposit_block<S>(k, xcd * qd + min(xcd, rd) + (i - nb0));
+}
+
+// (3) The last column and row of the deposits (virtual column 0 and row 0): only clamped
+// ranges reach them, through Rb, Cb and (for the bottom-right corner) their total K.
+// Overwrites the zeros that (1) left there.
+template <int S>
+__global__ void __launch_bounds__(kBlock) edge_deposit_kernel(BwdK k) {
+    const int e = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (e >= k.W + k.H - 1) return;
+    const int xv = e < k.W ? e : 0, yv = e < k.W ? 0 : e - k.W + 1;
+    const int cx = k.W - 1 - xv, cy = k.H - 1 - yv;
+    const bool lastx = xv == 0, lasty = yv == 0;
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int rx = k.p.rx[j], ry = k.p.ry[j];
+        const int pxp = cx - rx, pxm = cx + rx + 1, pyp = cy - ry, pym = cy + ry + 1;
+        const bool okxm = pxm <= k.W - 1, okym = pym <= k.H - 1;
+        const double *R0 = k.Rb + (int64_t)j * k.H, *R1 = k.Rb + ((int64_t)S + j) * k.H;
+        const double *C0 = k.Cb + (int64_t)j * k.W, *C1 = k.Cb + ((int64_t)S + j) * k.W;
+        if (lastx && !lasty && pyp >= 0) { d0 += R0[pyp]; d1 += R1[pyp]; }
+        if (lasty && !lastx && pxp >= 0) { d0 += C0[pxp]; d1 += C1[pxp]; }
+        if (lastx && lasty) { d0 += k.K[j]; d1 += k.K[S + j]; }
+        if (lasty && okxm) { d0 -= C0[pxm]; d1 -= C1[pxm]; }
+        if (lastx && okym) { d0 -= R0[pym]; d1 -= R1[pym]; }
     }
-    const Sum3 r = block_sum3(acc);
-    if (threadIdx.x == 0) {
-        out[0] = r.a;
-        out[1] = r.b;
-        out[2] = r.c;
-    }
+    k.Dr[(int64_t)yv * k.W + xv] = make_double2(d0, d1);
 }
 
 size_t round_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
@@ -371,6 +441,7 @@ BwdPlan make_bwd_plan(int H, int W, int n_scales, const int *ry, bool with_resid
     b.Cb = take(2 * (size_t)n_scales * W * sizeof(double));
     b.Dr = take(hw * sizeof(double2));
     b.part = take((size_t)tiles_x * b.nchunks * 3 * sizeof(double));
+    b.K = take(2 * kS * sizeof(double));
     b.scan_plan = make_scan_plan(H, W, kF64, 0, scan_tune_adjoint(H, W));
     b.scan = take(b.scan_plan.total);
     b.total = off;
@@ -395,39 +466,44 @@ hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, voi
     k.Cb = reinterpret_cast<double *>(w + plan.Cb);
     k.Dr = reinterpret_cast<double2 *>(w + plan.Dr);
     k.part = reinterpret_cast<double *>(w + plan.part);
+    k.gp = a.grad_params;
+    k.K = reinterpret_cast<double *>(w + plan.K);
     k.tiles_x = (a.W + kWave - 1) / kWave;
     k.p4 = plan.p4;
     k.teeth = plan.teeth;
     k.nchunks = plan.nchunks;
     k.chunk = plan.chunk;
+    k.ndep = (uint32_t)plan.nblocks;
+    k.nbor = (uint32_t)(k.tiles_x * plan.nchunks);
     const int S = a.p.n_scales;
-    const unsigned nbs = (unsigned)(k.tiles_x * plan.nchunks);
+    // XCD 0 holds the most work items: ceil of each kind's share
+    const uint32_t per_xcd = (k.ndep + 7) / 8 + (k.nbor + 7) / 8;
+    const unsigned nfused = 8u * per_xcd;
     switch (S) {
-#define TM_BORDER(n)                                                                            \
+#define TM_FUSED(n)                                                                             \
     case n:                                                                                    \
-        hipLaunchKernelGGL(border_scalar_kernel<n>, dim3(nbs), dim3(kBlock), 0, s, k);         \
+        hipLaunchKernelGGL(border_deposit_kernel<n>, dim3(nfused), dim3(kBlock), 0, s, k);     \
         break;
-        TM_BORDER(1) TM_BORDER(2) TM_BORDER(3) TM_BORDER(4)
-        TM_BORDER(5) TM_BORDER(6) TM_BORDER(7) TM_BORDER(8)
-#undef TM_BORDER
+        TM_FUSED(1) TM_FUSED(2) TM_FUSED(3) TM_FUSED(4)
+        TM_FUSED(5) TM_FUSED(6) TM_FUSED(7) TM_FUSED(8)
+#undef TM_FUSED
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned nred = (unsigned)(((int64_t)2 * S * (a.H + a.W) + kBlock - 1) / kBlock);
+    const unsigned nred =
+        (unsigned)(((int64_t)2 * S * (a.H + a.W) + kBlock - 1) / kBlock) + 2 * S + 1;
     hipLaunchKernelGGL(border_reduce_kernel, dim3(nred), dim3(kBlock), 0, s, k);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(scalar_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k.part, (int)nbs,
-                       a.grad_params);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned nedge = (unsigned)((a.W + a.H - 1 + kBlock - 1) / kBlock);
     switch (S) {
-#define TM_DEPOSIT(n)                                                                           \
+#define TM_EDGE(n)                                                                              \
     case n:                                                                                    \
-        hipLaunchKernelGGL(deposit_kernel<n>, dim3((unsigned)plan.nblocks), dim3(kBlock), 0, s, k); \
+        hipLaunchKernelGGL(edge_deposit_kernel<n>, dim3(nedge), dim3(kBlock), 0, s, k);        \
         break;
-        TM_DEPOSIT(1) TM_DEPOSIT(2) TM_DEPOSIT(3) TM_DEPOSIT(4)
-        TM_DEPOSIT(5) TM_DEPOSIT(6) TM_DEPOSIT(7) TM_DEPOSIT(8)
-#undef TM_DEPOSIT
+        TM_EDGE(1) TM_EDGE(2) TM_EDGE(3) TM_EDGE(4)
+        TM_EDGE(5) TM_EDGE(6) TM_EDGE(7) TM_EDGE(8)
+#undef TM_EDGE
         default: return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -189,6 +189,29 @@ __device__ __forceinline__ T wave_sum(T v) {
     return readlane(wave_inclusive<Op>(v), kWave - 1);
 }
 
+// FP64 sums over the wave of a and b at once.  gfx950's permlane32_swap trades lanes 32-63 of its
+// first operand for lanes 0-31 of its second, so one exchange (two per FP64 value) and one
+// addition leave the half-sums of a in lanes 0-31 and those of b in lanes 32-63; four row
+// shifts and one row broadcast finish both.  A fixed order of additions; half the steps of
+// two separate wave sums.
+__device__ __forceinline__ void wave_sum2(double a, double b, double &sa, double &sb) {
+    const uint64_t ua = (uint64_t)__double_as_longlong(a);
+    const uint64_t ub = (uint64_t)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    const auto hi =
+        __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+    const double x = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+    const double y = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+    double v = x + y;
+    v += dpp<0x111>(v);
+    v += dpp<0x112>(v);
+    v += dpp<0x114>(v);
+    v += dpp<0x118>(v);
+    v += dpp<0x142, 0xa>(v);
+    sa = readlane(v, 31);
+    sb = readlane(v, 63);
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
 // Index of the calling wave inside its block, as a wave-uniform (scalar) value.

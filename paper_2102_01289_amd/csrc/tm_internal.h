@@ -249,7 +249,7 @@ struct BwdResidArgs {
 struct BwdPlan {
     int64_t nblocks;
     int p4, teeth, nchunks, chunk;
-    size_t resid, Rp, Rb, Cp, Cb, Dr, part, scan, total;
+    size_t resid, Rp, Rb, Cp, Cb, Dr, part, K, scan, total;
     ScanPlan scan_plan;
 };
 // with_resid: also reserve the residual planes (the table-based backward rebuilds them).

@@ -409,8 +409,12 @@ __device__ __forceinline__ void stage1_tile(const ScanK &k, const int tile, int 
                         rt[u * kRtPitch + lane] = s1;
                         rt[(kRtRows + u) * kRtPitch + lane] = s2;
                     } else {
-                        s1 = wave_sum<A>(s1);
-                        s2 = wave_sum<A>(s2);
+                        if constexpr (P == kF64) {
+                            wave_sum2(s1, s2, s1, s2);
+                        } else {
+                            s1 = wave_sum<A>(s1);
+                            s2 = wave_sum<A>(s2);
+                        }
                         t1 = A::add(t1, s1);
                         t2 = A::add(t2, s2);
                         if (lane == u) { k1 = s1; k2 = s2; }
