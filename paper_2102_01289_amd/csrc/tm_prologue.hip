@@ -81,9 +81,11 @@ __device__ void stats_part(const StatsK &k, int part, int nparts) {
             const float *G = R + k.ch_stride;
             const float *B = G + k.ch_stride;
             if (full && k.vec_in) {
-                float4 r = *reinterpret_cast<const float4 *>(R);
-                float4 g = *reinterpret_cast<const float4 *>(G);
-                float4 b = *reinterpret_cast<const float4 *>(B);
+                // read once: non-temporal, so the colour planes do not displace cached tables
+                typedef float f4v __attribute__((ext_vector_type(4)));
+                const f4v r = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(R));
+                const f4v g = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(G));
+                const f4v b = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(B));
                 v[0] = luminance(r.x, g.x, b.x);
                 v[1] = luminance(r.y, g.y, b.y);
                 v[2] = luminance(r.z, g.z, b.z);
