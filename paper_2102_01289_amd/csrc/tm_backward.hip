@@ -396,19 +396,37 @@ __global__ void __launch_bounds__(kBlock) edge_deposit_kernel(BwdK k) {
     const int xv = e < k.W ? e : 0, yv = e < k.W ? 0 : e - k.W + 1;
     const int cx = k.W - 1 - xv, cy = k.H - 1 - yv;
     const bool lastx = xv == 0, lasty = yv == 0;
+    // every load of every field first, at clamped in-range indices (a term that does not
+    // exist is selected away), then the terms in a fixed order
+    double t[S][4][2];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int rx = k.p.rx[j], ry = k.p.ry[j];
+        const int pxp = cx - rx, pxm = cx + rx + 1, pyp = cy - ry, pym = cy + ry + 1;
+        const double *R0 = k.Rb + (int64_t)j * k.H, *R1 = k.Rb + ((int64_t)S + j) * k.H;
+        const double *C0 = k.Cb + (int64_t)j * k.W, *C1 = k.Cb + ((int64_t)S + j) * k.W;
+        const int iy0 = min(max(pyp, 0), k.H - 1), ix0 = min(max(pxp, 0), k.W - 1);
+        const int ix1 = min(pxm, k.W - 1), iy1 = min(pym, k.H - 1);
+        t[j][0][0] = R0[iy0];
+        t[j][0][1] = R1[iy0];
+        t[j][1][0] = C0[ix0];
+        t[j][1][1] = C1[ix0];
+        t[j][2][0] = C0[ix1];
+        t[j][2][1] = C1[ix1];
+        t[j][3][0] = R0[iy1];
+        t[j][3][1] = R1[iy1];
+    }
     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int rx = k.p.rx[j], ry = k.p.ry[j];
         const int pxp = cx - rx, pxm = cx + rx + 1, pyp = cy - ry, pym = cy + ry + 1;
         const bool okxm = pxm <= k.W - 1, okym = pym <= k.H - 1;
-        const double *R0 = k.Rb + (int64_t)j * k.H, *R1 = k.Rb + ((int64_t)S + j) * k.H;
-        const double *C0 = k.Cb + (int64_t)j * k.W, *C1 = k.Cb + ((int64_t)S + j) * k.W;
-        if (lastx && !lasty && pyp >= 0) { d0 += R0[pyp]; d1 += R1[pyp]; }
-        if (lasty && !lastx && pxp >= 0) { d0 += C0[pxp]; d1 += C1[pxp]; }
+        if (lastx && !lasty && pyp >= 0) { d0 += t[j][0][0]; d1 += t[j][0][1]; }
+        if (lasty && !lastx && pxp >= 0) { d0 += t[j][1][0]; d1 += t[j][1][1]; }
         if (lastx && lasty) { d0 += k.K[j]; d1 += k.K[S + j]; }
-        if (lasty && okxm) { d0 -= C0[pxm]; d1 -= C1[pxm]; }
-        if (lastx && okym) { d0 -= R0[pym]; d1 -= R1[pym]; }
+        if (lasty && okxm) { d0 -= t[j][2][0]; d1 -= t[j][2][1]; }
+        if (lastx && okym) { d0 -= t[j][3][0]; d1 -= t[j][3][1]; }
     }
     k.Dr[(int64_t)yv * k.W + xv] = make_double2(d0, d1);
 }

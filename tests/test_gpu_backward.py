@@ -194,3 +194,28 @@ def test_radii_beyond_the_image_act_as_the_image_size(prec):
         outs.append((L, Lt, gv, gp, gt, gq))
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["c32x2", "f64"])
+def test_residual_backward_with_pitched_buffers(prec):
+    # v, g and grad_v as views into wider, offset rows: the same gradient bit for bit, and
+    # nothing written outside grad_v's own columns
+    H, W = 70, 133
+    rgb = to_dev(rgb_case(H, W, 5, seed=29))
+    p = tm.make_params(5, 4, eps=0.1, H=H, W=W)
+    m = tm.ToneMapper(H, W, p, prec)
+    m.run_train(rgb)
+    g = to_dev(np.random.default_rng(8).standard_normal((H, W)).astype(np.float32))
+    gv0, gp0 = (t.clone() for t in m.backward_resid(g))
+    big_v = torch.zeros((H, W + 37), dtype=torch.float32, device="cuda")
+    big_v[:, 5:5 + W] = m.lum
+    big_g = torch.zeros((H, W + 19), dtype=torch.float32, device="cuda")
+    big_g[:, 3:3 + W] = g
+    big_o = torch.full((H, W + 11), float("nan"), dtype=torch.float32, device="cuda")
+    gp = torch.empty(3, dtype=torch.float64, device="cuda")
+    gv_view = big_o[:, 7:7 + W]
+    tm.tm_tonemap_backward_resid(big_v[:, 5:5 + W], p, m.resid, big_g[:, 3:3 + W],
+                                 out=(gv_view, gp))
+    torch.cuda.synchronize()
+    assert torch.equal(gv_view, gv0) and torch.equal(gp, gp0)
+    assert torch.isnan(big_o[:, :7]).all() and torch.isnan(big_o[:, 7 + W:]).all()
