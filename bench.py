@@ -48,6 +48,9 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", choices=["query", "tables", "backward"], default=None,
                     help="launch only that stage in the timed loop (profiling runs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="leave out the batch and stress-set blocks of the default line "
+                         "(profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed loop, copy 1 GiB device-to-device once (a plain copy "
                          "kernel of known size, for calibrating HBM counters) and report its "
@@ -131,6 +134,10 @@ STRESS_RADII = (4, 16, 64)
 
 
 def bench_stress(args):
+    print(json.dumps(stress_line(args)), flush=True)
+
+
+def stress_line(args) -> dict:
     """The stress parameter set (n = 64 bins, fields of radius 4, 16 and 64 on both axes,
     eps = 0.1) on the 4000x3000 image: forward MP/s, per-stage split and each stage's
     algorithmic bytes over its time.  Algorithmic bytes per pixel (every input read once,
@@ -189,7 +196,7 @@ def bench_stress(args):
                      "algorithmic_bytes_per_launch": bpx[dom] * H * W,
                      "avg_kernel_ms": round(stage[dom], 4)},
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def _median_ms(fn, reps=10, warmup=2):
@@ -357,6 +364,56 @@ def bench_batch(args):
         "graph_over_per_image": round(per_ms / graph_ms, 4),
     }
     print(json.dumps(line), flush=True)
+
+
+def batch_extra(args, streams: int = 3, tune=(0, 16, 4)) -> dict:
+    """The 64-image batch in the default bench line: the graph-replayed batched forward with
+    its groups on `streams` internal streams, against per-image launch sequences, both with
+    the scan tiling `tune` (0 = each image's default), no autotuner."""
+    import torch
+
+    import paper_2102_01289_amd as tm
+    from synth import WORKLOADS, gen_batch_shapes, gen_wdr
+
+    cfg = WORKLOADS["wdr_batch64_uneven"]
+    shapes = gen_batch_shapes(cfg["count"], 360, 4000, seed=cfg["shape_seed"])
+    dev = torch.device("cuda:0")
+    imgs = [torch.from_numpy(gen_wdr(h, w, cfg["K"], cfg["lo"], cfg["hi"], cfg["seed"] + i).rgb)
+            .to(dev) for i, (h, w) in enumerate(shapes)]
+    mpx = sum(h * w for h, w in shapes) / 1e6
+    t = tm.tune(*tune)
+    b = tm.Batch(imgs, args.n_bins, args.n_scales, args.eps, prec=args.prec, tune=t)
+    b.set_concurrency(streams, 0)
+    s = torch.cuda.Stream()
+    b.capture(s)
+
+    def timed(fn, stream, steps=5, warmup=2):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        e.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(e) / steps
+
+    graph_ms = timed(lambda: b.replay(s), s)
+    mappers = [tm.ToneMapper(r.shape[1], r.shape[2],
+                             tm.make_params(args.n_bins, args.n_scales, eps=args.eps,
+                                            H=r.shape[1], W=r.shape[2]),
+                             args.prec, tune=tm.image_tune(t, r.shape[1], r.shape[2]), device=dev)
+               for r in imgs]
+    per_ms = timed(lambda: [m.run(r) for m, r in zip(mappers, imgs)],
+                   torch.cuda.current_stream())
+    del b, mappers, imgs
+    torch.cuda.synchronize()
+    return {"workload": "wdr_batch64_uneven", "images": len(shapes), "megapixels": round(mpx, 3),
+            "graph_ms": round(graph_ms, 4), "mp_s": round(mpx / (graph_ms * 1e-3), 3),
+            "per_image_launches_ms": round(per_ms, 4),
+            "graph_over_per_image": round(per_ms / graph_ms, 4), "streams": streams,
+            "tune": list(tune)}
 
 
 def query_bytes_per_px(prec: str, n_bins: int, resid_planes: int = 0) -> int:
@@ -657,6 +714,20 @@ def main():
         torch.cuda.synchronize()
         line["cpu_baseline"] = cpu_baseline(img.rgb, (args.n_bins, args.n_scales, args.eps,
                                                       cfg["seed"] + 1), do_bwd, outs)
+    if (not args.no_extras and args.kernel_only is None and args.image == WORKLOAD
+            and not args.copy_probe):
+        # the secondary workloads, so that every run of the default line records them
+        for key, fn in (("batch", lambda: batch_extra(args)),
+                        ("stress", lambda: stress_line(args))):
+            try:
+                line[key] = fn()
+            except Exception as e:   # a secondary block never loses the headline line
+                line[key] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.synchronize()
+        st = line.get("stress", {})
+        if "value" in st:
+            line["stress"] = {k: st[k] for k in ("value", "unit", "ms_per_step", "stage_ms",
+                                                  "forward_algorithmic_frac", "config")}
     print(json.dumps(line), flush=True)
 
 

@@ -35,6 +35,7 @@ constexpr int kBlock = 256;
 constexpr int kRows = kBlock / kWave;
 constexpr int kS = 8;            // TM_MAX_SCALES
 constexpr int kChunkMax = 64;    // rows per partial of the column sums, at most
+constexpr int kKParts = 8;       // blocks per corner total K
 
 struct BwdK {
     const float *v;
@@ -51,7 +52,8 @@ struct BwdK {
     double2 *Dr;     // [H][W] deposits {D1, D2} in reversed order
     double *part;    // [ncol * nchunks][3] scalar partials
     double *gp;      // [3] scalar gradients
-    double *K;       // [2][s] totals of the row range sums over each field's clamped rows
+    double *K;       // [2][s][kKParts] partial totals of the row range sums over each
+                     // field's clamped rows
     int tiles_x, p4, teeth, nchunks, chunk;
     uint32_t ndep, nbor;  // deposit and border blocks of the interleaved launch
 };
@@ -231,21 +233,35 @@ __device__ __forceinline__ double strided_sum(const double *src, int n, int64_t 
 }
 
 // (2) Rb[q][j][y] = sum over column tiles of Rp and Cb[q][j][x] = sum over row chunks of Cp;
-// 2s blocks form the totals K of the Rb terms over each field's clamped rows (for the
-// bottom-right corner), and the last block adds the border blocks' scalar partials into the
-// three scalar gradients.  All in a fixed order.
+// 2s kKParts blocks form parts of the totals K of the range sums over each field's clamped
+// rows (for the bottom-right corner), and the last block adds the border blocks' scalar
+// partials into the three scalar gradients.  All in a fixed order.
 __global__ void __launch_bounds__(kBlock) border_reduce_kernel(BwdK k) {
     const int s = k.p.n_scales;
     const int ncol = (k.W + kWave - 1) / kWave;
-    const int nK = 2 * s;
+    const int nK = 2 * s * kKParts;
     if (blockIdx.x >= gridDim.x - 1 - nK && blockIdx.x < gridDim.x - 1) {
-        // K[q][j] = sum over y >= H-1-ry_j of Rb[q][j][y], each Rb term formed as below
-        const int qj = (int)(blockIdx.x - (gridDim.x - 1 - nK)), j = qj % s;
+        // part kp of K[q][j] = sum over y >= H-1-ry_j and column tiles ct >= ct0_j of Rp,
+        // the (tile, row) pairs taken in a fixed order, split evenly over kKParts blocks
+        const int kb = (int)(blockIdx.x - (gridDim.x - 1 - nK));
+        const int qj = kb / kKParts, kp = kb % kKParts, j = qj % s;
         const int ct0 = max(k.W - 1 - k.p.rx[j], 0) / kWave;
-        const int y0 = max(k.H - 1 - k.p.ry[j], 0);
+        const int y0 = max(k.H - 1 - k.p.ry[j], 0), ny = k.H - y0;
+        const int64_t n = (int64_t)(ncol - ct0) * ny;
+        const int64_t e0 = n * kp / kKParts, e1 = n * (kp + 1) / kKParts;
+        const double *base = k.Rp + ((int64_t)qj * ncol + ct0) * k.H + y0;
+        constexpr int kB = 8;
         double acc = 0.0;
-        for (int y = y0 + (int)threadIdx.x; y < k.H; y += kBlock)
-            acc += strided_sum(k.Rp + ((int64_t)qj * ncol + ct0) * k.H + y, ncol - ct0, k.H);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)kB * kBlock) {
+            double a[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int64_t f = e + (int64_t)u * kBlock;
+                a[u] = f < e1 ? base[(f / ny) * k.H + f % ny] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) acc += a[u];
+        }
         acc = wave_sum<Acc<kF64>>(acc);
         __shared__ double shp[kRows];
         if (lane_id() == 0) shp[wave_id()] = acc;
@@ -253,7 +269,7 @@ __global__ void __launch_bounds__(kBlock) border_reduce_kernel(BwdK k) {
         if (threadIdx.x == 0) {
             double r = shp[0];
             for (int i = 1; i < kRows; ++i) r += shp[i];
-            k.K[qj] = r;
+            k.K[kb] = r;
         }
         return;
     }
@@ -387,7 +403,7 @@ __global__ void __launch_bounds__(kBlock) border_deposit_kernel(BwdK k) {
 }
 
 // (3) The last column and row of the deposits (virtual column 0 and row 0): only clamped
-// ranges reach them, through Rb, Cb and (for the bottom-right corner) their total K.
+// ranges reach them, through Rb, Cb and (for the bottom-right corner) the total K.
 // Overwrites the zeros that (1) left there.
 template <int S>
 __global__ void __launch_bounds__(kBlock) edge_deposit_kernel(BwdK k) {
@@ -424,7 +440,15 @@ __global__ void __launch_bounds__(kBlock) edge_deposit_kernel(BwdK k) {
         const bool okxm = pxm <= k.W - 1, okym = pym <= k.H - 1;
         if (lastx && !lasty && pyp >= 0) { d0 += t[j][0][0]; d1 += t[j][0][1]; }
         if (lasty && !lastx && pxp >= 0) { d0 += t[j][1][0]; d1 += t[j][1][1]; }
-        if (lastx && lasty) { d0 += k.K[j]; d1 += k.K[S + j]; }
+        if (lastx && lasty) {   // the corner totals from their parts, in a fixed order
+            double k0 = k.K[j * kKParts], k1 = k.K[(S + j) * kKParts];
+            for (int u = 1; u < kKParts; ++u) {
+                k0 += k.K[j * kKParts + u];
+                k1 += k.K[(S + j) * kKParts + u];
+            }
+            d0 += k0;
+            d1 += k1;
+        }
         if (lasty && okxm) { d0 -= t[j][2][0]; d1 -= t[j][2][1]; }
         if (lastx && okym) { d0 -= t[j][3][0]; d1 -= t[j][3][1]; }
     }
@@ -459,7 +483,7 @@ BwdPlan make_bwd_plan(int H, int W, int n_scales, const int *ry, bool with_resid
     b.Cb = take(2 * (size_t)n_scales * W * sizeof(double));
     b.Dr = take(hw * sizeof(double2));
     b.part = take((size_t)tiles_x * b.nchunks * 3 * sizeof(double));
-    b.K = take(2 * kS * sizeof(double));
+    b.K = take(2 * kS * kKParts * sizeof(double));
     b.scan_plan = make_scan_plan(H, W, kF64, 0, scan_tune_adjoint(H, W));
     b.scan = take(b.scan_plan.total);
     b.total = off;
@@ -510,7 +534,7 @@ hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, voi
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nred =
-        (unsigned)(((int64_t)2 * S * (a.H + a.W) + kBlock - 1) / kBlock) + 2 * S + 1;
+        (unsigned)(((int64_t)2 * S * (a.H + a.W) + kBlock - 1) / kBlock) + 2 * S * kKParts + 1;
     hipLaunchKernelGGL(border_reduce_kernel, dim3(nred), dim3(kBlock), 0, s, k);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const unsigned nedge = (unsigned)((a.W + a.H - 1 + kBlock - 1) / kBlock);
