@@ -343,7 +343,7 @@ def bench_batch(args):
         _, H, W = rgb.shape
         mappers.append(tm.ToneMapper(H, W, tm.make_params(args.n_bins, args.n_scales,
                                                           eps=args.eps, H=H, W=W),
-                                     args.prec, tune=tm.image_tune(t, H, W), device=dev))
+                                     args.prec, tune=tm.image_tune(t, H, W, args.n_bins), device=dev))
     per_ms = timed(lambda: [m.run(r) for m, r in zip(mappers, imgs)])
     line = {
         "metric": "aggregate megapixels/s, batched forward (HIP graph) vs per-image launches",
@@ -403,7 +403,8 @@ def batch_extra(args, streams: int = 3, tune=(0, 16, 4)) -> dict:
     mappers = [tm.ToneMapper(r.shape[1], r.shape[2],
                              tm.make_params(args.n_bins, args.n_scales, eps=args.eps,
                                             H=r.shape[1], W=r.shape[2]),
-                             args.prec, tune=tm.image_tune(t, r.shape[1], r.shape[2]), device=dev)
+                             args.prec, tune=tm.image_tune(t, r.shape[1], r.shape[2], args.n_bins),
+                             device=dev)
                for r in imgs]
     per_ms = timed(lambda: [m.run(r) for m, r in zip(mappers, imgs)],
                    torch.cuda.current_stream())

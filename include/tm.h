@@ -117,11 +117,13 @@ typedef struct {
 
 const char *tm_status_string(tm_status s);
 
-/* The scan tiling an H x W image gets when an entry point is passed tune = NULL (host
- * function): 4 columns per lane from width 2048 up, else 2; rows per tile 4 (H < 900),
- * 8 (H < 1800) or 16, halved (not below 4) while the image has fewer than 512 tiles; 4 planes
- * per pass. */
-tm_status tm_default_tune(int32_t H, int32_t W, tm_tune *t);
+/* The scan tiling an H x W image with an n_bins-bin histogram gets when an entry point is
+ * passed tune = NULL (host function; n_bins is the entry point's own n_bins argument, 0 for
+ * an integral image alone): 4 columns per lane from width 2048 up, else 2; rows per tile 4
+ * (H < 900), 8 (H < 1800) or 16, doubled (at most 32) from 33 bins, then halved (not below 4)
+ * while the image has fewer than 512 tiles; 4 planes per pass.  TM_ERR_ARG if t is NULL or
+ * n_bins is outside [0, TM_MAX_BINS]. */
+tm_status tm_default_tune(int32_t H, int32_t W, int32_t n_bins, tm_tune *t);
 
 /* Radii of the receptive-field pyramid (Section II-C): the largest field is the image and
  * each next one is half as wide, rx[j] = W >> (j+1), ry[j] = H >> (j+1) for j < n_scales.

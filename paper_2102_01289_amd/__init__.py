@@ -112,17 +112,18 @@ def tune(tile_w_vec: int, tile_h: int, bin_chunk: int) -> _capi.TmTune:
     return _capi.TmTune(tile_w_vec, tile_h, bin_chunk)
 
 
-def default_tune(H: int, W: int) -> _capi.TmTune:
-    """The scan tiling an H x W image gets by default (tm_default_tune)."""
+def default_tune(H: int, W: int, n_bins: int = 5) -> _capi.TmTune:
+    """The scan tiling an H x W image with an n_bins-bin histogram gets by default
+    (tm_default_tune)."""
     t = _capi.TmTune()
-    _ck("tm_default_tune", _lib().tm_default_tune(H, W, ctypes.byref(t)))
+    _ck("tm_default_tune", _lib().tm_default_tune(H, W, n_bins, ctypes.byref(t)))
     return t
 
 
-def image_tune(t, H: int, W: int) -> _capi.TmTune:
-    """A batch tiling as one image of shape H x W uses it: 0 fields take the image's
-    default."""
-    d = default_tune(H, W)
+def image_tune(t, H: int, W: int, n_bins: int = 5) -> _capi.TmTune:
+    """A batch tiling as one image of shape H x W (n_bins bins) uses it: 0 fields take the
+    image's default."""
+    d = default_tune(H, W, n_bins)
     if t is None:
         return d
     return _capi.TmTune(t.tile_w_vec or d.tile_w_vec, t.tile_h or d.tile_h, t.bin_chunk)

@@ -46,7 +46,7 @@ PI64 = ctypes.POINTER(ctypes.c_int64)
 SIGNATURES = {
     "tm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "tm_paper_radii": (ctypes.c_int, [I32, I32, PP]),
-    "tm_default_tune": (ctypes.c_int, [I32, I32, PT]),
+    "tm_default_tune": (ctypes.c_int, [I32, I32, I32, PT]),
     "tm_table_geometry": (ctypes.c_int, [I32, I32, PI64, PI64, PI64]),
     "tm_luminance": (ctypes.c_int, [P, I64, I64, I32, I32, P, I64, P]),
     "tm_image_stats_workspace_bytes": (SZ, [I32, I32]),

@@ -116,18 +116,19 @@ tm_status check(const tm_image_desc *d, int32_t count, const tm_params *p, tm_sa
 }
 
 // The scan tiling of one image: the batch's, with 0 fields taken from the image's default.
-ScanTune image_tiling(const ScanTune &t, int H, int W) {
-    const ScanTune def = scan_tune_default(H, W);
+ScanTune image_tiling(const ScanTune &t, int H, int W, int n_bins) {
+    const ScanTune def = scan_tune_default(H, W, n_bins);
     return ScanTune{t.vec ? t.vec : def.vec, t.th ? t.th : def.th, t.chunk};
 }
 
 // Processing order: the images sorted (stably) by columns per lane, so that a group of
-// consecutive images shares one compiled scan variant.
+// consecutive images shares one compiled scan variant (columns per lane do not depend on the
+// bin count).
 std::vector<int> processing_order(const tm_image_desc *d, int32_t count, const ScanTune &t) {
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return image_tiling(t, d[a].H, d[a].W).vec < image_tiling(t, d[b].H, d[b].W).vec;
+        return image_tiling(t, d[a].H, d[a].W, 0).vec < image_tiling(t, d[b].H, d[b].W, 0).vec;
     });
     return order;
 }
@@ -172,7 +173,7 @@ size_t layout(const tm_image_desc *d, int32_t count, const tm_params *p, int pre
         const size_t o_part = c.take(sizeof(StatsPartial) * (size_t)stats_blocks(H, W));
         const size_t o_sat = c.take(entry_bytes(prec) * (size_t)elems);
         const size_t o_hist = c.take(4 * (size_t)elems * (size_t)(n > 1 ? n - 1 : 1));
-        const ScanTune ti = image_tiling(t, H, W);
+        const ScanTune ti = image_tiling(t, H, W, n);
         const ScanPlan sp = make_scan_plan(H, W, prec, n - 1, ti);
         const size_t o_scan = c.take(sp.total);
         if (!b) continue;

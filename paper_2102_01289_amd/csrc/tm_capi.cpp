@@ -76,9 +76,9 @@ bool valid_prec(int prec) { return prec == TM_SAT_F32 || prec == TM_SAT_C32X2 ||
 
 tm_status from_hip(hipError_t e) { return e == hipSuccess ? TM_OK : TM_ERR_HIP; }
 
-ScanTune resolve_tune(const tm_tune *t, int H, int W, tm_status *st) {
+ScanTune resolve_tune(const tm_tune *t, int H, int W, int n_bins, tm_status *st) {
     *st = TM_OK;
-    if (!t) return scan_tune_default(H, W);
+    if (!t) return scan_tune_default(H, W, n_bins);
     ScanTune r{t->tile_w_vec, t->tile_h, t->bin_chunk};
     if (!scan_tune_valid(r)) *st = TM_ERR_ARG;
     return r;
@@ -139,10 +139,10 @@ tm_status tm_paper_radii(int32_t H, int32_t W, tm_params *p) {
     return TM_OK;
 }
 
-tm_status tm_default_tune(int32_t H, int32_t W, tm_tune *t) {
-    if (!t) return TM_ERR_ARG;
+tm_status tm_default_tune(int32_t H, int32_t W, int32_t n_bins, tm_tune *t) {
+    if (!t || n_bins < 0 || n_bins > TM_MAX_BINS) return TM_ERR_ARG;
     TM_TRY(check_image(H, W));
-    const ScanTune d = scan_tune_default(H, W);
+    const ScanTune d = scan_tune_default(H, W, n_bins);
     t->tile_w_vec = d.vec;
     t->tile_h = d.th;
     t->bin_chunk = d.chunk;
@@ -280,7 +280,7 @@ size_t tm_tables_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_sat_pr
     if (check_image(H, W) != TM_OK || !valid_prec(prec) || n_bins < 1 || n_bins > TM_MAX_BINS)
         return 0;
     tm_status st;
-    ScanTune t = resolve_tune(tune, H, W, &st);
+    ScanTune t = resolve_tune(tune, H, W, n_bins, &st);
     if (st != TM_OK) return 0;
     return make_scan_plan(H, W, (int)prec, n_bins, t).total;
 }
@@ -311,7 +311,7 @@ tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
         }
     }
     tm_status st;
-    ScanTune t = resolve_tune(tune, H, W, &st);
+    ScanTune t = resolve_tune(tune, H, W, n_bins, &st);
     TM_TRY(st);
     const int sp = sat ? (int)prec : -1;
     ScanPlan plan = make_scan_plan(H, W, sp, n_planes, t);

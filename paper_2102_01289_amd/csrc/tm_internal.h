@@ -69,7 +69,7 @@ struct ScanTune {
     int th;         // rows per tile
     int chunk;      // histogram planes per pass: 2, 4, 8
 };
-ScanTune scan_tune_default(int H, int W);
+ScanTune scan_tune_default(int H, int W, int n_bins);   // n_bins: of the histogram built with it
 ScanTune scan_tune_adjoint(int H, int W);   // the backward's suffix scans
 bool scan_tune_valid(const ScanTune &t);
 

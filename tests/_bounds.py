@@ -28,12 +28,14 @@ import numpy as np
 U = {"f32": 2.0 ** -24, "c32x2": 2.0 ** -44, "f64": 2.0 ** -53}
 
 
-def tiling(H, W, vec=None, th=None):
+def tiling(H, W, vec=None, th=None, n_bins=0):
     """The scan tiling the library picks by default (mirrors scan_tune_default)."""
     if vec is None:
         vec = 4 if W >= 2048 else 2
     if th is None:
         th = 4 if H < 900 else 8 if H < 1800 else 16
+        if n_bins >= 33:
+            th = min(2 * th, 32)
         tx = -(-W // (64 * vec))
         while th > 4 and tx * (-(-H // th)) < 512:
             th //= 2

@@ -147,10 +147,20 @@ def test_table_padded_view_layout_on_host():
 def test_default_tune_matches_the_documented_rule():
     from _bounds import tiling
     for H, W in [(3000, 4000), (1080, 1920), (256, 256), (20, 4100), (1, 1), (4000, 360)]:
-        t = tm.default_tune(H, W)
-        assert (t.tile_w_vec, t.tile_h, t.bin_chunk) == (*tiling(H, W), 4)
+        for n in (0, 5, 32, 33, 64, 256):
+            t = tm.default_tune(H, W, n)
+            assert (t.tile_w_vec, t.tile_h, t.bin_chunk) == (*tiling(H, W, n_bins=n), 4)
+    assert tm.default_tune(3000, 4000, 64).tile_h == 32
+    assert tm.default_tune(1080, 1920, 64).tile_h == 16
+    assert tm.default_tune(1080, 1920, 32).tile_h == 8
     t = tm.image_tune(tm.tune(0, 8, 2), 1080, 1920)
     assert (t.tile_w_vec, t.tile_h, t.bin_chunk) == (2, 8, 2)
+    t = tm.image_tune(tm.tune(0, 0, 4), 1080, 1920, 64)
+    assert (t.tile_w_vec, t.tile_h, t.bin_chunk) == (2, 16, 4)
+    lib = _capi.load()
+    tt = _capi.TmTune()
+    assert lib.tm_default_tune(100, 100, -1, ctypes.byref(tt)) == -1
+    assert lib.tm_default_tune(100, 100, 257, ctypes.byref(tt)) == -1
 
 
 def test_rgb_entry_argument_checks():

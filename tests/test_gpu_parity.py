@@ -151,7 +151,7 @@ def _check_forward(rgb, n, s, rx, ry, eps, prec, ld=(0.0, 1.0), tune=None):
     Lref, Lj, Wj, varj = oracle.forward(lum, e, rx, ry, eps, ld[0], ld[1], per_scale=True)
     vd = lum.astype(np.float64)
     mu = (float(np.float32(vd.mean())), float(np.float32((vd * vd).mean())))
-    vec, th = (tune.tile_w_vec, tune.tile_h) if tune is not None else tiling(H, W)
+    vec, th = (tune.tile_w_vec, tune.tile_h) if tune is not None else tiling(H, W, n_bins=n)
     bound = forward_bound(lum, Lref, Lj, Wj, varj, window_sums(lum, rx, ry), rx, ry, eps,
                           prec, vec, th, *(mu if prec == "c32x2" else (0.0, 0.0)))
     bound *= (ld[1] - ld[0])
