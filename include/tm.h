@@ -311,6 +311,10 @@ tm_status tm_tonemap_forward_train(const float *v, int64_t ld_v, int32_t H, int3
 /* Gradient from the residual planes of tm_tonemap_forward_train: no integral table is read.
  *   dv(q) = sum_j sum_{p: q in w_j(p)} g(p) (R1_j(p) + 2 v(q) R2_j(p)),
  *   grad_params = {sum g E, sum g (1 - Pbar), sum g Pbar}.
+ * v: the luminance the training forward read (pitch ld_v); resid: its residual planes as laid
+ * out above; grad_out: FP32 H x W, pitch ld_g; grad_v: FP32 H x W, pitch ld_gv (only its H x W
+ * entries are written); grad_params: device double[3] = {d/d eps, d/d ld_min, d/d ld_max}.
+ * Every sum is taken in a fixed order (no atomics), so results are bit-reproducible.
  * Workspace: tm_backward_resid_workspace_bytes. */
 size_t tm_backward_resid_workspace_bytes(int32_t H, int32_t W, const tm_params *p);
 tm_status tm_tonemap_backward_resid(const float *v, int64_t ld_v, int32_t H, int32_t W,
