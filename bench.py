@@ -55,13 +55,15 @@ def _parse():
                     help="after the timed loop, copy 1 GiB device-to-device once (a plain copy "
                          "kernel of known size, for calibrating HBM counters) and report its "
                          "bandwidth")
-    ap.add_argument("--workload", choices=["image", "batch", "sweep", "hdr", "stress"],
+    ap.add_argument("--workload", choices=["image", "batch", "sweep", "hdr", "stress", "scan"],
                     default="image",
                     help="image: one image (--image, 4000x3000 by default); batch: 64 images "
                          "of uneven size, launches replayed from a HIP graph; sweep: the "
                          "paper's Table IV grid (n, s in {3, 4, 5} at 480x640, 720x1280, "
                          "1080x1920) with a per-stage split; hdr: the multi-exposure front end "
-                         "at 4000x3000; stress: 64 bins and radii 4/16/64 at 4000x3000")
+                         "at 4000x3000; stress: 64 bins and radii 4/16/64 at 4000x3000; scan: "
+                         "the integral histogram built in three stages and in one look-back "
+                         "pass, at 1080p and 4000x3000")
     ap.add_argument("--image", choices=IMAGES, default=WORKLOAD,
                     help="the image of the image workload (the metric is quoted on "
                          "wdr_4000x3000)")
@@ -366,6 +368,65 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_scan(args):
+    """The integral histogram alone (n = 5, cumulative planes): the three-stage build against
+    the single pass with decoupled look-back, at 1080p and 12 MP, plus the combined table
+    build (integral image and histogram) for reference.  Algorithmic bytes: read v once (4)
+    and write 4 (n - 1) per pixel."""
+    import torch
+
+    import paper_2102_01289_amd as tm
+    from synth import WORKLOADS, gen_wdr
+
+    dev = torch.device("cuda:0")
+    n = args.n_bins
+    rows = []
+    for img in ("wdr_1920x1080", "wdr_4000x3000"):
+        cfg = WORKLOADS[img]
+        H, W = cfg["H"], cfg["W"]
+        rgb = torch.from_numpy(gen_wdr(H, W, cfg["K"], cfg["lo"], cfg["hi"], cfg["seed"]).rgb).to(dev)
+        m = tm.ToneMapper(H, W, tm.make_params(n, 5, eps=args.eps, H=H, W=W), args.prec, device=dev)
+        m.run(rgb)
+        v, edges = m.lum, m.edges
+        hist = tm.Table(H, W, "u32", n - 1, dev)
+        ws3 = torch.empty(max(tm._lib().tm_tables_workspace_bytes(H, W, n, 0, None), 1),
+                          dtype=torch.uint8, device=dev)
+        _, wsl = tm.tm_integral_histogram_lookback(v, edges, n, hist=hist)
+
+        def three():
+            tm._ck("tm_integral_histogram", tm._lib().tm_integral_histogram(
+                tm._vp(v), v.stride(0), H, W, tm._vp(edges), n, 1, tm._vp(hist.ptr), hist.ld,
+                hist.plane_stride, None, tm._vp(ws3), ws3.numel(), None))
+
+        def single():
+            tm.tm_integral_histogram_lookback(v, edges, n, hist=hist, ws=wsl)
+
+        res = {}
+        for name, fn in (("three_stage", three), ("lookback", single), ("tables", m.tables)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.steps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            res[name] = a.elapsed_time(b) / args.steps * 1e3
+        status = int(wsl[4:8].cpu().view(torch.int32)[0])
+        hb = (4 + 4 * (n - 1)) * H * W
+        rows.append({"workload": img, "three_stage_us": round(res["three_stage"], 1),
+                     "lookback_us": round(res["lookback"], 1),
+                     "tables_us": round(res["tables"], 1),
+                     "hist_algorithmic_gb_s": {k: round(hb / (res[k] * 1e-6) / 1e9, 1)
+                                               for k in ("three_stage", "lookback")},
+                     "lookback_status": status})
+        print(f"scan: {img}: three-stage {res['three_stage']:.1f} us, look-back "
+              f"{res['lookback']:.1f} us", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "integral histogram build, three-stage vs single-pass look-back",
+                      "unit": "us", "n_bins": n, "steps": args.steps, "rows": rows}), flush=True)
+
+
 def batch_extra(args, streams: int = 3, tune=(0, 16, 4)) -> dict:
     """The 64-image batch in the default bench line: the graph-replayed batched forward with
     its groups on `streams` internal streams, against per-image launch sequences, both with
@@ -555,6 +616,9 @@ def main():
         return
     if args.workload == "stress":
         bench_stress(args)
+        return
+    if args.workload == "scan":
+        bench_scan(args)
         return
 
     import numpy as np

@@ -216,6 +216,24 @@ tm_status tm_integral_histogram(const float *v, int64_t ld_v, int32_t H, int32_t
                                 const tm_tune *tune, void *ws, size_t ws_bytes,
                                 void *stream);
 
+/* The same integral histogram in one pass over v: each tile's carries come from the tiles
+ * before it by decoupled look-back ({state, count} records published and polled with
+ * agent-scope atomics; exact integers, so the result does not depend on the order they
+ * arrive in and equals tm_integral_histogram's bit for bit).  Up to 8 planes (n_bins <= 8
+ * per bin, <= 9 cumulative) and H < 2^30 (the records hold 30-bit counts);
+ * TM_ERR_UNSUPPORTED beyond.  Tiles of 128 columns by 16 or 32 rows.  Workspace:
+ * tm_lookback_workspace_bytes (0 for an unsupported shape); its first 8 bytes are a header
+ * the call resets: a ticket counter, then a status word that is 0 after the call, or 1 if
+ * some wait for a record ran out (bounded, about a second; the planes are then invalid).
+ * Every wait is bounded, so the call always completes.  Calls that share a workspace must
+ * not overlap. */
+size_t tm_lookback_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_hist_layout layout);
+tm_status tm_integral_histogram_lookback(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                         const float *edges, int32_t n_bins,
+                                         tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,
+                                         int64_t plane_stride, void *ws, size_t ws_bytes,
+                                         void *stream);
+
 /* Both tables in one pass over v (sat or hist may be NULL to skip that table). */
 tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
                              tm_sat_prec prec, const float *offsets, void *sat,

@@ -16,7 +16,7 @@ from . import _capi
 
 __all__ = [
     "TmError", "Table", "table_geometry", "paper_radii", "make_params", "tune", "default_tune",
-    "image_tune",
+    "image_tune", "tm_integral_histogram_lookback",
     "tm_luminance", "tm_image_stats", "tm_prologue", "tm_integral_image",
     "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
@@ -354,6 +354,24 @@ def tm_integral_histogram(v, edges, n_bins: int, layout="cumulative", tune=None,
         _vp(v), ld, H, W, _vp(edges), n_bins, _capi.HIST_LAYOUT[layout], _vp(hist.ptr),
         hist.ld, hist.plane_stride, _tune_ref(tune), _vp(ws), ws.numel(), _stream(stream)))
     return hist
+
+
+def tm_integral_histogram_lookback(v, edges, n_bins: int, layout="cumulative", hist=None,
+                                   ws=None, stream=None):
+    """The integral histogram in one pass with decoupled look-back (up to 8 planes):
+    (hist Table, workspace).  Word 1 of the workspace (its status) reads 0 after the pass, or
+    1 if a wait for another tile's record ran out."""
+    H, W, ld = _img(v, "v")
+    planes = n_bins if layout == "per_bin" else n_bins - 1
+    if hist is None:
+        hist = Table(H, W, "u32", planes, v.device)
+    if ws is None:
+        ws = _ws(_lib().tm_lookback_workspace_bytes(H, W, n_bins, _capi.HIST_LAYOUT[layout]),
+                 v.device)
+    _ck("tm_integral_histogram_lookback", _lib().tm_integral_histogram_lookback(
+        _vp(v), ld, H, W, _vp(edges), n_bins, _capi.HIST_LAYOUT[layout], _vp(hist.ptr),
+        hist.ld, hist.plane_stride, _vp(ws), ws.numel(), _stream(stream)))
+    return hist, ws
 
 
 def tm_tonemap_forward(v, sat: Table, hist: Table | None, edges, params, offsets=None,

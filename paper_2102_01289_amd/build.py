@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libtm355.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["tm_prologue.hip", "tm_scan.hip", "tm_query.hip", "tm_backward.hip", "tm_hdr.hip",
-           "tm_batch.cpp", "tm_capi.cpp"]
+           "tm_lookback.hip", "tm_batch.cpp", "tm_capi.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

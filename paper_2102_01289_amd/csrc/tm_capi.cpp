@@ -356,6 +356,56 @@ tm_status tm_integral_histogram(const float *v, int64_t ld_v, int32_t H, int32_t
                               layout, hist, ld_hist, plane_stride, tune, ws, ws_bytes, stream);
 }
 
+// the single-pass histogram: planes of a layout; counts in its records take 30 bits, so
+// H < 2^30 (row counts are below W <= 2^24)
+namespace {
+int lookback_planes(int32_t n_bins, tm_hist_layout layout) {
+    return layout == TM_HIST_PER_BIN ? n_bins : n_bins - 1;
+}
+}  // namespace
+
+size_t tm_lookback_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_hist_layout layout) {
+    if (check_image(H, W) != TM_OK || n_bins < 1 || n_bins > TM_MAX_BINS) return 0;
+    if (layout != TM_HIST_PER_BIN && layout != TM_HIST_CUMULATIVE) return 0;
+    const int np = lookback_planes(n_bins, layout);
+    if (np < 1 || np > 8 || H >= (1 << 30)) return 0;
+    return make_lookback_plan(H, W, np, lookback_rows(H, W, np)).total;
+}
+
+tm_status tm_integral_histogram_lookback(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                         const float *edges, int32_t n_bins,
+                                         tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,
+                                         int64_t plane_stride, void *ws, size_t ws_bytes,
+                                         void *stream) {
+    TM_TRY(check_image(H, W));
+    if (!v || !hist) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_v));
+    if (n_bins < 1 || n_bins > TM_MAX_BINS) return TM_ERR_ARG;
+    if (layout != TM_HIST_PER_BIN && layout != TM_HIST_CUMULATIVE) return TM_ERR_ARG;
+    const int np = lookback_planes(n_bins, layout);
+    if (np == 0) return TM_OK;
+    if (np > 8 || H >= (1 << 30)) return TM_ERR_UNSUPPORTED;
+    if (n_bins > 1 && !edges) return TM_ERR_ARG;
+    TM_TRY(check_hist(H, W, ld_hist, plane_stride, hist, np));
+    const LookbackPlan plan = make_lookback_plan(H, W, np, lookback_rows(H, W, np));
+    TM_TRY(check_ws(ws, ws_bytes, plan.total));
+    LookbackArgs a{};
+    a.v = v;
+    a.ld_v = ld_v;
+    a.H = H;
+    a.W = W;
+    a.edges = edges;
+    a.n_bins = n_bins;
+    a.n_planes = np;
+    a.layout = layout == TM_HIST_PER_BIN ? 0 : 1;
+    a.hist = hist;
+    a.ld_hist = ld_hist;
+    a.plane_stride = plane_stride;
+    // planes larger than the memory-side cache are written non-temporally, as by the scan
+    a.nt = (int64_t)np * plane_stride * 4 > ((int64_t)256 << 20);
+    return from_hip(launch_lookback_hist(a, plan, ws, static_cast<hipStream_t>(stream)));
+}
+
 // ------------------------------------------------------------------ a4
 tm_status tm_tonemap_forward(const float *v, int64_t ld_v, int32_t H, int32_t W,
                              const void *sat, int64_t ld_sat, tm_sat_prec prec,

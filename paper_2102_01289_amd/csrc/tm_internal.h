@@ -257,4 +257,24 @@ BwdPlan make_bwd_plan(int H, int W, int n_scales, const int *ry, bool with_resid
 hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, void *ws,
                                  hipStream_t s);
 
+// ---------------------------------------------------------------- single-pass histogram
+struct LookbackArgs {
+    const float *v;
+    int64_t ld_v;
+    int H, W;
+    const float *edges;
+    int n_bins, n_planes, layout;   // layout: 0 per bin, 1 cumulative
+    uint32_t *hist;
+    int64_t ld_hist, plane_stride;
+    int nt;                         // non-temporal plane stores
+};
+struct LookbackPlan {
+    int th, tiles_x, tiles_y;
+    size_t rowrec, colrec, cornrec, total;   // byte offsets in the workspace; header at 0
+};
+int lookback_rows(int H, int W, int n_planes);   // rows per look-back tile (16 or 32)
+LookbackPlan make_lookback_plan(int H, int W, int n_planes, int th);
+hipError_t launch_lookback_hist(const LookbackArgs &a, const LookbackPlan &plan, void *ws,
+                                hipStream_t s);
+
 }  // namespace tmo

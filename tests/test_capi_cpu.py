@@ -252,3 +252,37 @@ def test_noalloc_prologue_checks():
                                    null) == -1          # edges missing with n > 1
     assert lib.tm_prologue_noalloc(fake, 50, 10, 10, 10, 5, fake, 10, fake, fake, fake,
                                    null) == -2          # channel stride below H * ld
+
+
+def test_lookback_histogram_workspace_and_argument_checks():
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    cum, per = _capi.HIST_LAYOUT["cumulative"], _capi.HIST_LAYOUT["per_bin"]
+    # header (256 bytes) + 32-bit row and column records and 64-bit corner records of every
+    # tile of 128 columns x 32 rows (each area a whole number of 256-byte blocks)
+    up = lambda b: (b + 255) // 256 * 256
+    ws = lib.tm_lookback_workspace_bytes(3000, 4000, 5, cum)
+    tiles = 32 * ((3000 + 31) // 32)
+    assert ws == 256 + up(tiles * 32 * 4 * 4) + up(tiles * 4 * 128 * 4) + up(tiles * 4 * 8)
+    # 16 rows per tile when 32 would give fewer than 480 tiles
+    tiles = 1 * ((100 + 15) // 16)
+    assert lib.tm_lookback_workspace_bytes(100, 100, 5, cum) == \
+        256 + up(tiles * 16 * 4 * 4) + up(tiles * 4 * 128 * 4) + up(tiles * 4 * 8)
+    # the records hold 30-bit counts: H below 2^30
+    assert lib.tm_lookback_workspace_bytes((1 << 30) - 1, 1, 5, cum) > 0
+    assert lib.tm_lookback_workspace_bytes(1 << 30, 1, 5, cum) == 0
+    assert lib.tm_lookback_workspace_bytes(100, 100, 9, cum) > 0
+    assert lib.tm_lookback_workspace_bytes(100, 100, 10, cum) == 0      # 9 planes
+    assert lib.tm_lookback_workspace_bytes(100, 100, 9, per) == 0       # 9 planes
+    assert lib.tm_lookback_workspace_bytes(100, 100, 0, cum) == 0
+    fake = P(1 << 20)
+    # no pointers, too many planes: rejected before any device work
+    assert lib.tm_integral_histogram_lookback(None, 128, 8, 8, fake, 5, cum, fake, 64, 9 * 64 + 1,
+                                              fake, 1 << 20, None) == -1
+    assert lib.tm_integral_histogram_lookback(fake, 128, 8, 8, fake, 10, cum, fake, 64,
+                                              9 * 64 + 64, fake, 1 << 20, None) == -6
+    assert lib.tm_integral_histogram_lookback(fake, 1, 1 << 30, 1, fake, 5, cum, fake, 64,
+                                              64 * ((1 << 30) + 1), fake, 1 << 20, None) == -6
+    # one bin, cumulative: no planes, nothing to do
+    assert lib.tm_integral_histogram_lookback(fake, 128, 8, 8, None, 1, cum, fake, 64, 0,
+                                              None, 0, None) == 0
