@@ -539,12 +539,20 @@ class ToneMapper:
     allocated once so that run() only enqueues kernels (capturable in a HIP graph).
     variance="log": Eq. 10's window variance is that of the log image l = ln i (its
     integral image is built from tm_log_luminance's plane; the bins still come from i);
-    forward only."""
+    forward only.
+    tune: a TmTune, None for the shape's default tiling, or "cached" for the tiling the
+    autotuner stored for this device, shape bucket, bin count and precision
+    (autotune.tune_image), falling back to the default when none is stored."""
 
     def __init__(self, H: int, W: int, params, prec: str = "c32x2", tune=None,
                  device="cuda", variance: str = "linear"):
         if variance not in VARIANCE_DOMAINS:
             raise ValueError(f"variance must be one of {VARIANCE_DOMAINS}")
+        if isinstance(tune, str):
+            if tune != "cached":
+                raise ValueError('tune must be a TmTune, None or "cached"')
+            from .autotune import cached_image_tune
+            tune = cached_image_tune(H, W, params.n_bins, prec, torch.device(device))
         self.variance = variance
         self.H, self.W, self.params, self.prec, self.tune = H, W, params, prec, tune
         n = params.n_bins

@@ -15,7 +15,7 @@ import torch
 
 from . import Batch, ToneMapper, make_params, tune
 
-__all__ = ["candidates", "tune_image", "tune_batch", "cache_path"]
+__all__ = ["candidates", "tune_image", "tune_batch", "cache_path", "cached_image_tune"]
 
 
 def cache_path() -> str:
@@ -68,8 +68,9 @@ def _time(fn, reps: int, warmup: int = 2) -> float:
     return statistics.median(ts)
 
 
-def _device_key() -> str:
-    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+def _device_key(device=None) -> str:
+    p = torch.cuda.get_device_properties(
+        torch.cuda.current_device() if device is None or device.index is None else device)
     return f"{p.name}|{getattr(p, 'gcnArchName', '')}|cu{p.multi_processor_count}"
 
 
@@ -79,11 +80,22 @@ def _bucket(H: int, W: int) -> str:
     return f"{int(round(2 * math.log2(H)))}x{int(round(2 * math.log2(W)))}"
 
 
+def _image_key(H: int, W: int, n_bins: int, prec: str, device=None) -> str:
+    return f"image|{_device_key(device)}|{_bucket(H, W)}|n{n_bins}|{prec}"
+
+
+def cached_image_tune(H: int, W: int, n_bins: int = 5, prec: str = "c32x2", device=None):
+    """The tiling tune_image stored for this device, shape bucket, bin count and precision,
+    or None (the shape's default) when none is stored.  Looks up only; never times."""
+    hit = _load().get(_image_key(H, W, n_bins, prec, device))
+    return tune(*hit[:3]) if hit else None
+
+
 def tune_image(rgb: torch.Tensor, n_bins: int = 5, prec: str = "c32x2", reps: int = 5,
                use_cache: bool = True, cands=None):
     """Best tiling for the table build of one image shape: (TmTune, ms)."""
     _, H, W = rgb.shape
-    key = f"image|{_device_key()}|{_bucket(H, W)}|n{n_bins}|{prec}"
+    key = _image_key(H, W, n_bins, prec, rgb.device)
     if use_cache and cands is None:
         hit = _load().get(key)
         if hit:

@@ -286,3 +286,10 @@ def test_lookback_histogram_workspace_and_argument_checks():
     # one bin, cumulative: no planes, nothing to do
     assert lib.tm_integral_histogram_lookback(fake, 128, 8, 8, None, 1, cum, fake, 64, 0,
                                               None, 0, None) == 0
+
+
+def test_tone_mapper_tune_argument_checked_on_the_host():
+    # only a TmTune, None or "cached" is accepted; the check runs before any device work
+    p = tm.make_params(5, 1, [1], [1])
+    with pytest.raises(ValueError):
+        tm.ToneMapper(16, 16, p, "c32x2", tune="fastest", device="cpu")

@@ -101,6 +101,14 @@ def test_autotune_picks_a_valid_tiling(tmp_path, monkeypatch):
     assert t2.tile_w_vec in (2, 4, 8)
     t3, _ = autotune.tune_image(imgs[0], reps=2)       # second call is served by the cache
     assert (t3.tile_w_vec, t3.tile_h, t3.bin_chunk) == (t2.tile_w_vec, t2.tile_h, t2.bin_chunk)
+    # the single-image path takes the stored tiling on request, and the default without one
+    _, H, W = imgs[0].shape
+    p = tm.make_params(5, 2, eps=0.1, H=H, W=W)
+    m = tm.ToneMapper(H, W, p, "c32x2", tune="cached")
+    assert (m.tune.tile_w_vec, m.tune.tile_h, m.tune.bin_chunk) == \
+        (t2.tile_w_vec, t2.tile_h, t2.bin_chunk)
+    assert torch.equal(m.run(imgs[0]), tm.ToneMapper(H, W, p, "c32x2", tune=t2).run(imgs[0]))
+    assert tm.ToneMapper(H, W, p, "f64", tune="cached").tune is None   # nothing stored for f64
 
 
 @pytest.mark.parametrize("streams,per_group", [(2, 0), (4, 1), (3, 2), (8, 1)])
