@@ -54,7 +54,7 @@ def lib() -> ctypes.CDLL:
         L.orc_forward.restype = I
         L.orc_forward_direct.argtypes = [P, I64, I64, P, I, I, P, P, D, D, D, I, P, I64, P]
         L.orc_forward_direct.restype = I
-        L.orc_backward.argtypes = [P, I64, I64, P, I, I, P, P, D, D, D, P, P, P]
+        L.orc_backward.argtypes = [P, I64, I64, P, I, I, P, P, D, D, D, I, P, P, P]
         L.orc_backward.restype = I
         L.orc_box_filter.argtypes = [P, I64, I64, ctypes.c_int32, ctypes.c_int32, P]
         L.orc_box_filter.restype = I
@@ -237,8 +237,10 @@ def forward_direct(v, edges, rx, ry, pix, eps=0.1, ldmin=0.0, ldmax=1.0, var_dom
     return L
 
 
-def backward(v, edges, rx, ry, g, eps=0.1, ldmin=0.0, ldmax=1.0):
-    """(dv float64 [H, W], (d eps, d min L_d, d max L_d)) of sum(g * L)."""
+def backward(v, edges, rx, ry, g, eps=0.1, ldmin=0.0, ldmax=1.0, var_domain="linear"):
+    """(dv float64 [H, W], (d eps, d min L_d, d max L_d)) of sum(g * L).  var_domain="log":
+    the gradient of the log-domain variant (forward's var_domain="log"), through
+    l = ln(max(v, FLT_MIN)); zero where the floor is taken."""
     v = _c(v, np.float32)
     edges = _c(edges, np.float32)
     rx, ry = _radii(rx, ry)
@@ -250,7 +252,8 @@ def backward(v, edges, rx, ry, g, eps=0.1, ldmin=0.0, ldmax=1.0):
     gp = np.empty(3, dtype=np.float64)
     rc = lib().orc_backward(_ptr(v), H, W, _ptr(edges) if edges.size else None,
                             edges.size + 1, rx.size, _ptr(rx), _ptr(ry), float(eps),
-                            float(ldmin), float(ldmax), _ptr(g), _ptr(dv), _ptr(gp))
+                            float(ldmin), float(ldmax), _var_log(var_domain), _ptr(g), _ptr(dv),
+                            _ptr(gp))
     if rc != 0:
         raise MemoryError("oracle backward: allocation failed")
     return dv, tuple(float(x) for x in gp)

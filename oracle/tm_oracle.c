@@ -463,15 +463,19 @@ int orc_forward_direct(const float *v, int64_t H, int64_t W, const float *edges,
  * applied to the planes A1_j, A2_j; it is evaluated with a double-double integral image.
  * Scalars: dL/deps = sum_j (L_j - L)/D * (-var_j/(var_j + eps)^2),
  *          dL/dmin L_d = 1 - Pbar, dL/dmax L_d = Pbar, Pbar = sum_j W_j P_j / D.
- * grad_params = {d/deps, d/dmin L_d, d/dmax L_d}.  Returns 0 or -1 (allocation). */
+ * grad_params = {d/deps, d/dmin L_d, d/dmax L_d}.
+ * var_log: the log-domain variant (Eq. 10 of l = ln(max(v, FLT_MIN)); the bins stay those of
+ * v).  The same derivation holds with l in place of v, which gives dL/dl(q); the chain rule
+ * through the logarithm then gives dv(q) = dL/dl(q) / v(q) where v(q) > FLT_MIN, and 0 where
+ * the floor is taken (the floor is a constant there).  Returns 0 or -1 (allocation). */
 int orc_backward(const float *v, int64_t H, int64_t W, const float *edges, int n, int s,
                  const int32_t *rx, const int32_t *ry, double eps, double ldmin, double ldmax,
-                 const double *g, double *grad_v, double *grad_params)
+                 int var_log, const double *g, double *grad_v, double *grad_params)
 {
     tables_t t;
     if (n < 1 || n > 256 || s < 1 || s > 16)
         return -1;
-    if (tables_build(v, H, W, edges, n, 0, &t))
+    if (tables_build(v, H, W, edges, n, var_log, &t))
         return -1;
     const int64_t np = H * W, ld = W + 1, ps = (H + 1) * (W + 1);
     double *A1 = (double *)malloc((size_t)s * (size_t)np * sizeof(double));
@@ -534,11 +538,14 @@ int orc_backward(const float *v, int64_t H, int64_t W, const float *edges, int n
                     dd_t bx = box_dd(sat, ld, w);
                     double val = bx.hi + bx.lo;
                     if (pass == 1)
-                        val *= 2.0 * (double)v[y * W + x];
+                        val *= 2.0 * var_image_px(v[y * W + x], var_log);
                     grad_v[y * W + x] += val;
                 }
         }
     }
+    if (var_log)   /* d l / d v */
+        for (int64_t p = 0; p < np; ++p)
+            grad_v[p] = (double)v[p] > (double)FLT_MIN ? grad_v[p] / (double)v[p] : 0.0;
     grad_params[0] = geps;
     grad_params[1] = gmin;
     grad_params[2] = gmax;

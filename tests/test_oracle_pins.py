@@ -352,6 +352,74 @@ def test_backward_matches_central_differences(orc):
     assert abs(d_eps - geps) <= 1e-6 * (1 + abs(geps))
 
 
+def test_log_backward_matches_central_differences(orc):
+    # the log-domain variant's gradient against central differences of its own forward
+    H, W = 18, 23
+    v = _lum(orc, H, W, K=5, seed=43)
+    rx, ry = orc.paper_radii(H, W, 3)
+    e = _edges(orc, v, 5)
+    g = np.random.default_rng(9).standard_normal((H, W))
+    dv, (geps, gmin, gmax) = orc.backward(v, e, rx, ry, g, var_domain="log")
+    h = 1e-3
+    safe = _safe_mask(v, e, h)
+    rng = np.random.default_rng(10)
+    for _ in range(4):
+        d = rng.standard_normal((H, W)) * safe
+        vp = (v * np.exp(h * d)).astype(np.float32)
+        vm = (v * np.exp(-h * d)).astype(np.float32)
+        assert np.array_equal(orc.bins(vp, e), orc.bins(v, e))
+        fp = np.sum(g * orc.forward(vp, e, rx, ry, var_domain="log"))
+        fm = np.sum(g * orc.forward(vm, e, rx, ry, var_domain="log"))
+        lin = np.sum(dv * (vp.astype(np.float64) - vm.astype(np.float64)))
+        assert abs((fp - fm) - lin) <= 2e-4 * abs(fp - fm) + 1e-12
+    L = orc.forward(v, e, rx, ry, 0.1, 0.0, 1.0, var_domain="log")
+    d_lo = np.sum(g * (orc.forward(v, e, rx, ry, 0.1, 0.5, 1.0, var_domain="log") - L)) / 0.5
+    d_hi = np.sum(g * (orc.forward(v, e, rx, ry, 0.1, 0.0, 2.0, var_domain="log") - L)) / 1.0
+    assert abs(d_lo - gmin) <= 1e-10 * (1 + abs(gmin))
+    assert abs(d_hi - gmax) <= 1e-10 * (1 + abs(gmax))
+    he = 1e-5
+    d_eps = (np.sum(g * orc.forward(v, e, rx, ry, 0.1 + he, var_domain="log"))
+             - np.sum(g * orc.forward(v, e, rx, ry, 0.1 - he, var_domain="log"))) / (2 * he)
+    assert abs(d_eps - geps) <= 1e-6 * (1 + abs(geps))
+
+
+def test_log_backward_follows_the_scale_law(orc):
+    # scaling v and the edges by 2^k leaves the log-domain L unchanged (the log values shift
+    # by k ln 2), so dL/dv at 2^k v is 2^-k times dL/dv at v; the scalar gradients are equal
+    H, W = 15, 19
+    v = _lum(orc, H, W, K=4, seed=47)
+    rx, ry = orc.paper_radii(H, W, 3)
+    e = _edges(orc, v, 5)
+    g = np.random.default_rng(11).standard_normal((H, W))
+    dv, gp = orc.backward(v, e, rx, ry, g, var_domain="log")
+    scale = float(np.abs(dv).max())
+    for k in (-3, 2, 5):
+        f = np.float32(2.0 ** k)
+        dvs, gps = orc.backward(v * f, e * f, rx, ry, g, var_domain="log")
+        assert np.max(np.abs(dvs * float(f) - dv)) <= 1e-9 * scale
+        for a, b in zip(gps, gp):
+            assert abs(a - b) <= 1e-9 * (1 + abs(b))
+
+
+def test_log_backward_is_zero_where_the_floor_is_taken(orc):
+    # below the smallest normal FP32 the log plane is the constant ln(FLT_MIN)
+    H, W = 9, 11
+    v = _lum(orc, H, W, K=3, seed=53)
+    v[2, 3] = 0.0
+    v[5, 7] = np.float32(2.0 ** -140)
+    rx, ry = [3, 1], [2, 1]
+    e = _edges(orc, v[v > 2.0 ** -126], 4)
+    g = np.random.default_rng(12).standard_normal((H, W))
+    dv, _ = orc.backward(v, e, rx, ry, g, var_domain="log")
+    assert dv[2, 3] == 0.0 and dv[5, 7] == 0.0
+    # the same pixels just above the floor do carry a gradient
+    v2 = v.copy()
+    v2[2, 3] = np.float32(2.0 ** -120)
+    v2[5, 7] = np.float32(2.0 ** -110)
+    dv2, _ = orc.backward(v2, e, rx, ry, g, var_domain="log")
+    assert dv2[2, 3] != 0.0 and dv2[5, 7] != 0.0
+
+
 # ---------------------------------------------------------------- Eq. 12 colour restoration
 def _color_case(seed=3, H=7, W=9):
     import oracle
