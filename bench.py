@@ -55,7 +55,8 @@ def _parse():
                     help="after the timed loop, copy 1 GiB device-to-device once (a plain copy "
                          "kernel of known size, for calibrating HBM counters) and report its "
                          "bandwidth")
-    ap.add_argument("--workload", choices=["image", "batch", "sweep", "hdr", "stress", "scan"],
+    ap.add_argument("--workload", choices=["image", "batch", "sweep", "hdr", "stress", "scan",
+                                           "logvar"],
                     default="image",
                     help="image: one image (--image, 4000x3000 by default); batch: 64 images "
                          "of uneven size, launches replayed from a HIP graph; sweep: the "
@@ -63,7 +64,8 @@ def _parse():
                          "1080x1920) with a per-stage split; hdr: the multi-exposure front end "
                          "at 4000x3000; stress: 64 bins and radii 4/16/64 at 4000x3000; scan: "
                          "the integral histogram built in three stages and in one look-back "
-                         "pass, at 1080p and 4000x3000")
+                         "pass, at 1080p and 4000x3000; logvar: the log-domain variance "
+                         "variant's stages (forward and backward) beside the linear form")
     ap.add_argument("--image", choices=IMAGES, default=WORKLOAD,
                     help="the image of the image workload (the metric is quoted on "
                          "wdr_4000x3000)")
@@ -427,6 +429,57 @@ def bench_scan(args):
                       "unit": "us", "n_bins": n, "steps": args.steps, "rows": rows}), flush=True)
 
 
+def bench_logvar(args):
+    """The log-domain variance variant (Eq. 10's window variance of l = ln i, bins of i) beside
+    the linear form, per stage, forward and forward+backward, at 4000x3000 and 1920x1080.
+    The variant's backward is the residual backward given l followed by the chain rule
+    through the logarithm."""
+    import torch
+
+    import paper_2102_01289_amd as tm
+    from synth import WORKLOADS, gen_upstream_grad, gen_wdr
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for img in ("wdr_4000x3000", "wdr_1920x1080"):
+        cfg = WORKLOADS[img]
+        H, W = cfg["H"], cfg["W"]
+        rgb = torch.from_numpy(gen_wdr(H, W, cfg["K"], cfg["lo"], cfg["hi"], cfg["seed"]).rgb).to(dev)
+        g = torch.from_numpy(gen_upstream_grad((H, W), seed=cfg["seed"] + 1)).to(dev)
+        p = tm.make_params(args.n_bins, args.n_scales, eps=args.eps, H=H, W=W)
+        for dom in ("linear", "log"):
+            m = tm.ToneMapper(H, W, p, args.prec, device=dev, variance=dom)
+            m.run_train(rgb)
+            m.backward_resid(g)
+            st = {}
+            for name, fn in (("prologue", lambda: m.prologue(rgb)), ("tables", m.tables),
+                             ("query", m.query), ("query_train", m.query_train),
+                             ("backward", lambda: m.backward_resid(g))):
+                for _ in range(args.warmup):
+                    fn()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(args.steps):
+                    fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                st[name] = round(a.elapsed_time(b) / args.steps, 4)
+            fwd = st["prologue"] + st["tables"] + st["query"]
+            step = fwd - st["query"] + st["query_train"] + st["backward"]
+            mpx = H * W / 1e6
+            rows.append({"workload": img, "variance": dom, "stage_ms": st,
+                         "fwd_ms": round(fwd, 4), "fwd_bwd_ms": round(step, 4),
+                         "fwd_mp_s": round(mpx / (fwd * 1e-3), 1),
+                         "fwd_bwd_mp_s": round(mpx / (step * 1e-3), 1)})
+            print(f"logvar: {img} {dom}: fwd {fwd:.3f} ms, fwd+bwd {step:.3f} ms",
+                  file=sys.stderr, flush=True)
+            del m
+    print(json.dumps({"metric": "log-domain variance variant beside the linear form, per stage",
+                      "unit": "ms", "sat_precision": args.prec, "n_bins": args.n_bins,
+                      "n_scales": args.n_scales, "steps": args.steps, "rows": rows}), flush=True)
+
+
 def batch_extra(args, streams: int = 3, tune=(0, 16, 4)) -> dict:
     """The 64-image batch in the default bench line: the graph-replayed batched forward with
     its groups on `streams` internal streams, against per-image launch sequences, both with
@@ -619,6 +672,9 @@ def main():
         return
     if args.workload == "scan":
         bench_scan(args)
+        return
+    if args.workload == "logvar":
+        bench_logvar(args)
         return
 
     import numpy as np

@@ -191,12 +191,24 @@ tm_status tm_prologue_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rg
  * TM_SAT_C32X2 integral image of l needs, and minmax[2] (device, nullable) = {min l, max l}.
  * The variant is then: tm_integral_image of logv with these offsets, the integral histogram
  * of i as usual, and tm_tonemap_forward (or _maps, _rgb) given i itself (its bins decide
- * Eq. 1) with the table and offsets of l; eps is then in units of l^2.  Forward only: the
- * backward entry points take the variance of the image they are given.
+ * Eq. 1) with the table and offsets of l; eps is then in units of l^2.  Its gradient:
+ * tm_tonemap_forward_train given i with the table and offsets of l, then
+ * tm_tonemap_backward_resid given logv as its image (the residual backward uses the image
+ * only in the final dv = s1 + 2 v s2, so it returns the gradient with respect to l), then
+ * tm_log_luminance_backward.  tm_tonemap_backward (from the tables) has no log form.
  * Deterministic.  Workspace: tm_image_stats_workspace_bytes. */
 tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t W, float *logv,
                            int64_t ld_log, float *offsets, float *minmax, void *ws,
                            size_t ws_bytes, void *stream);
+
+/* The chain rule through l = ln(max(i, FLT_MIN)) for the log-domain variant's gradient:
+ *   grad_i = grad_l / i   where i > FLT_MIN,   0 where the floor constant is taken
+ * (FP32, one correctly rounded division per pixel).  lum is the image i given to
+ * tm_log_luminance; grad_l the gradient with respect to its logv.  grad_i may be grad_l
+ * itself (then with the same pitch); any other overlap is TM_ERR_ARG.  No workspace. */
+tm_status tm_log_luminance_backward(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                                    const float *grad_l, int64_t ld_gl, float *grad_i,
+                                    int64_t ld_gi, void *stream);
 
 /* ---------------------------------------------------------------- stages a2, a3: tables */
 

@@ -16,7 +16,7 @@ from . import _capi
 
 __all__ = [
     "TmError", "Table", "table_geometry", "paper_radii", "make_params", "tune", "default_tune",
-    "image_tune", "tm_integral_histogram_lookback",
+    "image_tune", "tm_integral_histogram_lookback", "tm_log_luminance_backward",
     "tm_luminance", "tm_image_stats", "tm_prologue", "tm_integral_image",
     "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
@@ -217,6 +217,19 @@ def tm_log_luminance(lum: torch.Tensor, stream=None, out=None, offsets=None, min
         _vp(lum), ld, H, W, _vp(out), ldo, _vp(offsets), _vp(minmax), _vp(ws), ws.numel(),
         _stream(stream)))
     return out, offsets, minmax
+
+
+def tm_log_luminance_backward(lum: torch.Tensor, grad_l: torch.Tensor, out=None, stream=None):
+    """Chain rule through l = ln(max(lum, FLT_MIN)): grad_l / lum above the floor, 0 where
+    the floor is taken.  out may be grad_l itself (in place)."""
+    H, W, ld = _img(lum, "lum")
+    _, _, ldg = _img(grad_l, "grad_l")
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=lum.device)
+    _, _, ldo = _img(out, "out")
+    _ck("tm_log_luminance_backward", _lib().tm_log_luminance_backward(
+        _vp(lum), ld, H, W, _vp(grad_l), ldg, _vp(out), ldo, _stream(stream)))
+    return out
 
 
 def _stack(stack: torch.Tensor):
@@ -637,16 +650,17 @@ class ToneMapper:
 
     def _linear_only(self, what):
         if self.variance != "linear":
-            raise ValueError(f"{what}: the log-domain variance variant has a forward only")
+            raise ValueError(f"{what}: the log-domain variance variant's gradient comes from "
+                             "run_train and backward_resid")
 
     def query_train(self, stream=None):
-        """Fused query that also writes the backward's residual planes."""
-        self._linear_only("query_train")
+        """Fused query that also writes the backward's residual planes (those of the log
+        image's window statistics for variance="log")."""
         if not hasattr(self, "resid"):
             self.resid = torch.empty((residual_planes(self.params.n_scales), self.H, self.W),
                                      dtype=torch.float32, device=self.lum.device)
         tm_tonemap_forward_train(self.lum, self.sat, self.hist, self.edges, self.params,
-                                 self.offsets, self.out, self.resid, stream)
+                                 self.sat_offsets, self.out, self.resid, stream)
 
     def run_train(self, rgb, stream=None) -> torch.Tensor:
         self.prologue(rgb, stream)
@@ -661,14 +675,20 @@ class ToneMapper:
             self.grad_params = torch.empty(3, dtype=torch.float64, device=dev)
 
     def backward_resid(self, grad_out: torch.Tensor, stream=None):
-        """Adjoint from the residual planes of the last run_train: (grad_lum, grad_params)."""
-        self._linear_only("backward_resid")
+        """Adjoint from the residual planes of the last run_train: (grad_lum, grad_params).
+        variance="log": the residual backward given the log plane returns the gradient with
+        respect to l, which the chain rule through the logarithm turns into that w.r.t. lum."""
         self._bwd_buffers()
         if not hasattr(self, "ws_bwd_resid"):
             self.ws_bwd_resid = _ws(_lib().tm_backward_resid_workspace_bytes(
                 self.H, self.W, ctypes.byref(self.params)), self.lum.device)
-        return tm_tonemap_backward_resid(self.lum, self.params, self.resid, grad_out, stream,
-                                         self.ws_bwd_resid, (self.grad_v, self.grad_params))
+        log = self.variance == "log"
+        tm_tonemap_backward_resid(self.logv if log else self.lum, self.params, self.resid,
+                                  grad_out, stream, self.ws_bwd_resid,
+                                  (self.grad_v, self.grad_params))
+        if log:
+            tm_log_luminance_backward(self.lum, self.grad_v, self.grad_v, stream)
+        return self.grad_v, self.grad_params
 
     def backward(self, grad_out: torch.Tensor, stream=None):
         """Adjoint of the last forward from its tables: (grad_lum, grad_params)."""

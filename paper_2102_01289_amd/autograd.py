@@ -11,35 +11,56 @@ the integral tables and derives the residual planes from them.
 
 The three scalars reach the kernels through device memory (tm_params.scalars), so neither
 pass synchronises with the host and both can be recorded into a CUDA/HIP graph.
+
+variance="log": Eq. 10's variance is that of l = ln(max(lum, FLT_MIN)) (the bins still come
+from lum).  The residual backward given l returns the gradient with respect to l, and the
+chain rule through the logarithm (tm_log_luminance_backward) gives that w.r.t. lum.  With
+recompute=True the backward rebuilds the log plane and the tables and reruns the training
+query for the residual planes.
 """
 from __future__ import annotations
 
 import torch
 
-from . import (make_params, tm_image_stats, tm_integral_tables, tm_tonemap_backward,
-               tm_tonemap_backward_resid, tm_tonemap_forward, tm_tonemap_forward_train)
+from . import (make_params, tm_image_stats, tm_integral_histogram, tm_integral_image,
+               tm_integral_tables, tm_log_luminance, tm_log_luminance_backward,
+               tm_tonemap_backward, tm_tonemap_backward_resid, tm_tonemap_forward,
+               tm_tonemap_forward_train)
 
 __all__ = ["TonemapFn", "tonemap_luminance"]
+
+
+def _log_tables(lum, prec, edges, n_bins):
+    """The log-domain variant's tables: integral image of l = ln(max(lum, FLT_MIN)) with its
+    offsets, integral histogram of lum.  (l, loff, sat, hist)."""
+    l, loff, _ = tm_log_luminance(lum)
+    sat = tm_integral_image(l, prec, loff)
+    hist = tm_integral_histogram(lum, edges, n_bins, "cumulative") if n_bins > 1 else None
+    return l, loff, sat, hist
 
 
 class TonemapFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, lum, eps, ld_min, ld_max, n_bins: int, rx, ry, prec: str = "c32x2",
-                recompute: bool = True):
+                recompute: bool = True, variance: str = "linear"):
         H, W = lum.shape
         # device copy of (eps, ld_min, ld_max) that the kernels read when they run
         scal = torch.stack([t.detach().reshape(()).to(device=lum.device, dtype=torch.float32)
                             for t in (eps, ld_min, ld_max)]).contiguous()
         p = make_params(n_bins, len(rx), rx, ry, H=H, W=W, scalars=scal)
         edges, offsets, _ = tm_image_stats(lum, n_bins)
-        sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")
+        log = variance == "log"
+        if log:
+            _, offsets, sat, hist = _log_tables(lum, prec, edges, n_bins)
+        else:
+            sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")
         if recompute:
             out = tm_tonemap_forward(lum, sat, hist, edges, p, offsets)
             ctx.resid = None
         else:
             out, ctx.resid = tm_tonemap_forward_train(lum, sat, hist, edges, p, offsets)
         del sat, hist
-        ctx.meta = (p, prec, n_bins, eps.dtype)
+        ctx.meta = (p, prec, n_bins, eps.dtype, log)
         ctx.scal = scal            # p points into it
         ctx.save_for_backward(lum, edges, offsets)
         return out
@@ -47,24 +68,37 @@ class TonemapFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         lum, edges, offsets = ctx.saved_tensors
-        p, prec, n_bins, sdt = ctx.meta
+        p, prec, n_bins, sdt, log = ctx.meta
         g = g.contiguous().float()
-        if ctx.resid is None:
+        if log:
+            l, loff, sat, hist = _log_tables(lum, prec, edges, n_bins)
+            resid = ctx.resid
+            if resid is None:
+                _, resid = tm_tonemap_forward_train(lum, sat, hist, edges, p, loff)
+            del sat, hist
+            gv, gp = tm_tonemap_backward_resid(l, p, resid, g)
+            tm_log_luminance_backward(lum, gv, gv)
+            ctx.resid = None
+        elif ctx.resid is None:
             sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")
             gv, gp = tm_tonemap_backward(lum, sat, hist, edges, p, g, offsets)
         else:
             gv, gp = tm_tonemap_backward_resid(lum, p, ctx.resid, g)
             ctx.resid = None
-        return (gv, gp[0].to(sdt), gp[1].to(sdt), gp[2].to(sdt), None, None, None, None, None)
+        return (gv, gp[0].to(sdt), gp[1].to(sdt), gp[2].to(sdt), None, None, None, None, None,
+                None)
 
 
 def tonemap_luminance(lum, eps, ld_min, ld_max, n_bins=5, rx=None, ry=None, n_scales=5,
-                      prec="c32x2", recompute=True):
+                      prec="c32x2", recompute=True, variance="linear"):
     """Differentiable tone mapping of a luminance image [H, W] (CUDA float32).  eps, ld_min,
-    ld_max are 0-d tensors; radii default to the paper's pyramid."""
+    ld_max are 0-d tensors; radii default to the paper's pyramid; variance "linear" or "log"
+    (Eq. 10's variance of l = ln lum)."""
+    if variance not in ("linear", "log"):
+        raise ValueError('variance must be "linear" or "log"')
     H, W = lum.shape
     if rx is None or ry is None:
         from . import paper_radii
         rx, ry = paper_radii(H, W, n_scales)
     return TonemapFn.apply(lum, eps, ld_min, ld_max, n_bins, tuple(rx), tuple(ry), prec,
-                           recompute)
+                           recompute, variance)

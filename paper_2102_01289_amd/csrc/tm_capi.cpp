@@ -234,6 +234,29 @@ tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t 
                                      static_cast<StatsPartial *>(ws), (hipStream_t)stream));
 }
 
+tm_status tm_log_luminance_backward(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                                    const float *grad_l, int64_t ld_gl, float *grad_i,
+                                    int64_t ld_gi, void *stream) {
+    TM_TRY(check_image(H, W));
+    if (!lum || !grad_l || !grad_i) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_lum));
+    TM_TRY(check_plane(H, W, ld_gl));
+    TM_TRY(check_plane(H, W, ld_gi));
+    // in place (same buffer, same pitch) or disjoint: a partial overlap would let one pixel's
+    // result land on another pixel's unread input
+    if (grad_i != grad_l) {
+        const char *a0 = reinterpret_cast<const char *>(grad_l);
+        const char *a1 = a0 + (((int64_t)H - 1) * ld_gl + W) * 4;
+        const char *b0 = reinterpret_cast<const char *>(grad_i);
+        const char *b1 = b0 + (((int64_t)H - 1) * ld_gi + W) * 4;
+        if (a0 < b1 && b0 < a1) return TM_ERR_ARG;
+    } else if (ld_gi != ld_gl) {
+        return TM_ERR_ARG;
+    }
+    return from_hip(launch_log_chain(lum, ld_lum, grad_l, ld_gl, grad_i, ld_gi, H, W,
+                                     (hipStream_t)stream));
+}
+
 // ------------------------------------------------------------------ exposures
 namespace {
 tm_status check_stack(const uint8_t *stack, int64_t exp_stride, int64_t ch_stride, int64_t ld,

@@ -46,6 +46,8 @@ hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, con
 hipError_t launch_log_stats(const float *lum, int64_t ld_lum, float *logv, int64_t ld_log, int H,
                             int W, float *offsets, float *minmax, StatsPartial *partials,
                             hipStream_t s);
+hipError_t launch_log_chain(const float *lum, int64_t ld_lum, const float *grad_l, int64_t ld_gl,
+                            float *grad_i, int64_t ld_gi, int H, int W, hipStream_t s);
 // launch_stats from RGB with the partials in the library's static per-device scratch array
 // (no workspace).  Fails with hipErrorInvalidValue if the partials would not fit.
 constexpr size_t kPrologueScratchBytes = 32768;

@@ -365,6 +365,33 @@ hipError_t launch_log_stats(const float *lum, int64_t ld_lum, float *logv, int64
     return hipGetLastError();
 }
 
+// The chain rule through the log plane of the log-domain variance variant: from the gradient
+// with respect to l = ln(max(i, FLT_MIN)) the gradient with respect to i, grad_l / i where
+// i > FLT_MIN and 0 where the floor constant is taken.  Elementwise (one correctly rounded
+// FP32 division); gi may be gl itself, so neither is restrict-qualified.
+namespace {
+__global__ void __launch_bounds__(kBlock) log_chain_kernel(const float *lum, int64_t ld_lum,
+                                                           const float *gl, int64_t ld_gl,
+                                                           float *gi, int64_t ld_gi, int H,
+                                                           int W) {
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    if (x >= W) return;
+    for (int64_t y = blockIdx.y; y < H; y += gridDim.y) {
+        const float v = lum[y * ld_lum + x];
+        const float g = gl[y * ld_gl + x];
+        gi[y * ld_gi + x] = v > FLT_MIN ? g / v : 0.f;
+    }
+}
+}  // namespace
+
+hipError_t launch_log_chain(const float *lum, int64_t ld_lum, const float *grad_l, int64_t ld_gl,
+                            float *grad_i, int64_t ld_gi, int H, int W, hipStream_t s) {
+    const dim3 grid((unsigned)((W + kBlock - 1) / kBlock), (unsigned)(H < 4096 ? H : 4096));
+    hipLaunchKernelGGL(log_chain_kernel, grid, dim3(kBlock), 0, s, lum, ld_lum, grad_l, ld_gl,
+                       grad_i, ld_gi, H, W);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- prologue without workspace
 // The reduction partials of tm_prologue_noalloc live in this file-scope device array (one
 // copy per GPU, for the life of the process).  Host code must not pass the array's name to a

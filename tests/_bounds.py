@@ -182,7 +182,7 @@ def measured_entry_errors(table, lum, prec, mu1=0.0, mu2=0.0):
 
 
 def backward_bound(lum, g, Lref, Lj, Wj, varj, S1j, rx, ry, eps, prec, vec, th, mu1=0.0,
-                   mu2=0.0, dv_ref=None, entry_err=None):
+                   mu2=0.0, dv_ref=None, entry_err=None, input_err=None):
     """Per-pixel bound on |dv_gpu - dv_oracle| for the gradient of sum(g L) wrt v.
 
     dv(q) = sum_j sum_{p: q in w_j(p)} g(p) (R1_j(p) + 2 v(q) R2_j(p)) with
@@ -210,7 +210,10 @@ def backward_bound(lum, g, Lref, Lj, Wj, varj, S1j, rx, ry, eps, prec, vec, th, 
     unbounded (infinite).  The count of such pixels p is returned so tests can hold it small.  entry_err = (e1, e2): per-entry error bounds of the integral
     image (measured_entry_errors); by default the depth model of entry_bound.  The window
     moments then also carry the FP64 rounding of m and var (8 * 2^-53 of S2/N + |mu2| +
-    m^2 + |m mu1|)."""
+    m^2 + |m mu1|).  input_err = (d1, d2): per-pixel bounds on how far the device's terms
+    q = v and q = v^2 may lie from the oracle's (as in forward_bound); their window sums join
+    the moments' errors, and d1(q) also enters the final 2 v(q) s2(q) through
+    2 d1(q) sum_j box(|g| |R2_j|)."""
     H, W = lum.shape
     s = len(rx)
     u = 2.0 ** -24
@@ -223,6 +226,9 @@ def backward_bound(lum, g, Lref, Lj, Wj, varj, S1j, rx, ry, eps, prec, vec, th, 
         xm, xp, ym, yp, N = corners(H, W, rx[j], ry[j])
         c1 = e1[ym, xm] + e1[ym, xp] + e1[yp, xm] + e1[yp, xp]
         c2 = e2[ym, xm] + e2[ym, xp] + e2[yp, xm] + e2[yp, xp]
+        if input_err is not None:
+            c1 = c1 + _box(input_err[0], xm, xp, ym, yp)
+            c2 = c2 + _box(input_err[1], xm, xp, ym, yp)
         m = S1j[j] / N
         geo.append((xm, xp, ym, yp, N))
         r64 = 8.0 * 2.0 ** -53 * (np.abs(varj[j]) + 2.0 * m * m + abs(mu2) + np.abs(m * mu1))
@@ -257,6 +263,8 @@ def backward_bound(lum, g, Lref, Lj, Wj, varj, S1j, rx, ry, eps, prec, vec, th, 
             dR2 = dc / N + 2.0 * u * R2
             dR1 = 2.0 * np.abs(m) * dR2 + 2.0 * R2 * dm[j] + 4.0 * u * np.abs(m) * R2
             B += _box(gabs * dR1, xm, xp, ym, yp) + 2.0 * v * _box(gabs * dR2, xm, xp, ym, yp)
+            if input_err is not None:
+                B += 2.0 * input_err[0] * _box(gabs * (R2 + dR2), xm, xp, ym, yp)
             # absolute deposits at the four corners (the -1 border never enters a suffix)
             t1 = gabs * (2.0 * np.abs(m) * R2 + dR1)
             t2 = gabs * (R2 + dR2)

@@ -293,3 +293,15 @@ def test_tone_mapper_tune_argument_checked_on_the_host():
     p = tm.make_params(5, 1, [1], [1])
     with pytest.raises(ValueError):
         tm.ToneMapper(16, 16, p, "c32x2", tune="fastest", device="cpu")
+
+
+def test_log_chain_rule_argument_checks():
+    # no pointers, overlapping gradient buffers, in place with another pitch: rejected on the
+    # host before any device work
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    a = 1 << 20
+    assert lib.tm_log_luminance_backward(None, 64, 8, 8, P(a), 64, P(a), 64, None) == -1
+    assert lib.tm_log_luminance_backward(P(a), 64, 8, 8, P(a), 64, P(a + 256), 64, None) == -1
+    assert lib.tm_log_luminance_backward(P(a), 64, 8, 8, P(a), 64, P(a), 128, None) == -1
+    assert lib.tm_log_luminance_backward(P(a), 4, 8, 8, P(a), 64, P(a), 64, None) == -2

@@ -1,15 +1,17 @@
 """GPU parity of the log-domain variance variant (Eq. 10's window variance taken of the log
 image l = ln i rather than of i, the bins still cut from i) against the oracle's FP64 form:
 the device log plane within 2 ulp of the exact logarithm, histograms bit-exact, the fused
-output within the derived per-pixel bound and a stated envelope."""
+output within the derived per-pixel bound and a stated envelope, and its gradient (the
+residual backward given l, then the chain rule through the logarithm) within the derived
+backward bound."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import paper_2102_01289_amd as tm
-from _bounds import forward_bound, tiling, window_sums
-from _cases import edges_ref, lum_ref, rgb_case, to_dev
+from _bounds import backward_bound, forward_bound, tiling, window_sums
+from _cases import check_scalar_gradients, edges_ref, lum_ref, rgb_case, to_dev
 from synth import WORKLOADS, gen_wdr
 
 pytestmark = pytest.mark.gpu
@@ -120,9 +122,11 @@ def test_log_forward_special_cases():
     b = tm.ToneMapper(H, W, p, "c32x2", variance="log").run(
         to_dev((rgb * np.float32(8.0)).astype(np.float32))).cpu().numpy()
     assert np.max(np.abs(a.astype(np.float64) - b)) <= 1e-5
-    # the backward is defined for the linear variance only
+    # the table-based backward has no log form (the residual one has)
+    m = tm.ToneMapper(H, W, p, "c32x2", variance="log")
+    m.run(to_dev(rgb))
     with pytest.raises(ValueError):
-        tm.ToneMapper(H, W, p, "c32x2", variance="log").query_train()
+        m.backward(to_dev(np.ones((H, W), dtype=np.float32)))
 
 
 def test_log_variance_maps_and_colour():
@@ -172,3 +176,120 @@ def test_log_forward_4000x3000():
     rx, ry = oracle.paper_radii(c["H"], c["W"], 5)
     err = _check_log_forward(rgb, 5, rx, ry, 0.1, "c32x2")
     assert err.max() <= 1e-5 and np.quantile(err, 0.999) <= 2e-6
+
+
+# ------------------------------------------------------------------------ gradient
+def test_log_chain_rule_kernel():
+    # grad_i = grad_l / i (one correctly rounded FP32 division) above the floor, 0 below;
+    # in place too
+    H, W = 37, 301
+    lum = lum_ref(rgb_case(H, W, 5, -3.0, 5.0, seed=71))
+    lum[0, :5] = [0.0, 1e-40, FLT_MIN, 2.0 * FLT_MIN, 1.0]
+    gl = np.random.default_rng(3).standard_normal((H, W)).astype(np.float32)
+    want = np.where(lum > FLT_MIN, gl / np.where(lum > FLT_MIN, lum, 1.0), 0.0).astype(np.float32)
+    got = tm.tm_log_luminance_backward(to_dev(lum), to_dev(gl)).cpu().numpy()
+    assert np.array_equal(got, want)
+    t = to_dev(gl)
+    tm.tm_log_luminance_backward(to_dev(lum), t, t)
+    assert np.array_equal(t.cpu().numpy(), want)
+    assert got[0, 0] == got[0, 1] == got[0, 2] == 0.0 and got[0, 3] != 0.0
+
+
+def _check_log_backward(rgb, n, rx, ry, eps, prec, seed, ld=(0.0, 1.0)):
+    H, W = rgb.shape[1:]
+    p = tm.make_params(n, len(rx), rx, ry, eps, ld[0], ld[1])
+    m = tm.ToneMapper(H, W, p, prec, variance="log")
+    L_plain = m.run(to_dev(rgb)).clone()
+    L_train = m.run_train(to_dev(rgb)).clone()
+    assert torch.equal(L_plain, L_train)       # the training form writes the same L
+    g = np.random.default_rng(seed).standard_normal((H, W)).astype(np.float32)
+    gv, gp = m.backward_resid(to_dev(g))
+    torch.cuda.synchronize()
+    gv = gv.cpu().numpy().astype(np.float64)
+    gp = gp.cpu().numpy()
+    lum = lum_ref(rgb)
+    e = edges_ref(lum, n)
+    g64 = g.astype(np.float64)
+    dv, gref = oracle.backward(lum, e, rx, ry, g64, eps, ld[0], ld[1], var_domain="log")
+    fwd = oracle.forward(lum, e, rx, ry, eps, ld[0], ld[1], per_scale=True, var_domain="log")
+    Lr, Lj, Wj, varj = fwd
+    # the bound of the gradient with respect to l (the variance's image), with the device log
+    # plane's rounding (2 ulp) as input error, then carried through the FP32 division by i
+    lg = _log_ref(lum)
+    i64 = lum.astype(np.float64)
+    above = i64 > FLT_MIN
+    dl_ref = np.where(above, dv * i64, 0.0)
+    mu = (float(np.float32(lg.mean())), float(np.float32((lg * lg).mean())))
+    d1 = 2 * _ulp32(lg)
+    vec, th = tiling(H, W)
+    B, bad = backward_bound(lg, g64, Lr, Lj, Wj, varj, window_sums(lg, rx, ry), rx, ry, eps,
+                            prec, vec, th, *(mu if prec == "c32x2" else (0.0, 0.0)),
+                            dv_ref=dl_ref, input_err=(d1, 2 * np.abs(lg) * d1 + d1 * d1))
+    assert bad <= max(2, H * W // 1000), f"{bad} pixels with uncertain fusion weights"
+    assert np.mean(np.isinf(B)) <= 0.05
+    with np.errstate(invalid="ignore", divide="ignore"):
+        Bv = np.where(above, B / np.where(above, i64, 1.0), 0.0)
+        Bv = Bv + 2.0 ** -24 * (np.abs(dv) + Bv)
+        over = np.where(above, np.abs(gv - dv) / Bv, 0.0)
+    worst = np.unravel_index(int(np.argmax(over)), over.shape)
+    assert np.all(over <= 1.0), (f"gradient outside the derived bound at {int(np.sum(over > 1))} "
+                                 f"pixels; worst {worst}: gpu {gv[worst]:.6e} oracle "
+                                 f"{dv[worst]:.6e} bound {Bv[worst]:.3e}")
+    assert np.all(gv[~above] == 0.0)
+    check_scalar_gradients(gp, gref, g64, fwd, eps, ld)
+    # the variant's gradient differs from the linear-variance one
+    dlin, _ = oracle.backward(lum, e, rx, ry, g64, eps, ld[0], ld[1])
+    assert np.max(np.abs(dlin - dv)) > 1e-3 * np.max(np.abs(dv))
+    return gv, dv
+
+
+@pytest.mark.parametrize("prec", ["c32x2", "f64"])
+@pytest.mark.parametrize("H,W,n,s", [(48, 64, 5, 3), (96, 128, 5, 5), (37, 123, 3, 4),
+                                     (1, 200, 5, 2), (150, 1, 5, 2), (64, 64, 64, 3)])
+def test_log_backward_matches_oracle(prec, H, W, n, s):
+    rgb = rgb_case(H, W, 5, -3.0, 5.0, seed=3 * H + W + n)
+    rx, ry = oracle.paper_radii(H, W, s)
+    _check_log_backward(rgb, n, rx, ry, 0.1, prec, seed=s)
+
+
+@pytest.mark.parametrize("rx,ry", [([0, 3, 100], [0, 7, 100]), ([5, 1], [0, 9]),
+                                   ([30, 15, 8, 4, 2, 1, 0], [20, 10, 5, 2, 1, 0, 1])])
+def test_log_backward_radii_clamping_and_floor(rx, ry):
+    rgb = rgb_case(60, 80, 5, -3.0, 5.0, seed=len(rx) + 30)
+    rgb[:, 7, 9] = 0.0                   # a black pixel: l is the floor, its gradient 0
+    _check_log_backward(rgb, 5, rx, ry, 0.05, "c32x2", seed=5, ld=(0.2, 0.8))
+
+
+def test_log_backward_paper_set_256():
+    rgb = rgb_case(256, 256, 8, -2.0, 4.0, seed=101)
+    rx, ry = oracle.paper_radii(256, 256, 5)
+    _check_log_backward(rgb, 5, rx, ry, 0.1, "c32x2", seed=9)
+
+
+@pytest.mark.parametrize("recompute", [False, True])
+def test_log_backward_through_autograd(recompute):
+    from paper_2102_01289_amd.autograd import tonemap_luminance
+    H, W = 70, 90
+    rgb = rgb_case(H, W, 5, -3.0, 5.0, seed=77)
+    rx, ry = oracle.paper_radii(H, W, 4)
+    p = tm.make_params(5, 4, rx, ry, 0.1, 0.0, 1.0)
+    m = tm.ToneMapper(H, W, p, "c32x2", variance="log")
+    L = m.run_train(to_dev(rgb)).clone()
+    g = to_dev(np.random.default_rng(4).standard_normal((H, W)).astype(np.float32))
+    gv, gp = (t.clone() for t in m.backward_resid(g))
+    lum = m.lum.clone().requires_grad_(True)
+    scal = [torch.tensor(x, dtype=torch.float64, device="cuda", requires_grad=True)
+            for x in (0.1, 0.0, 1.0)]
+    out = tonemap_luminance(lum, *scal, n_bins=5, rx=rx, ry=ry, prec="c32x2",
+                            recompute=recompute, variance="log")
+    assert torch.equal(out, L)
+    (out * g).sum().backward()
+    assert torch.equal(lum.grad, gv)
+    assert [float(t.grad) for t in scal] == gp.cpu().tolist()
+
+
+def test_log_backward_1920x1080():
+    c = WORKLOADS["wdr_1920x1080"]
+    rgb = gen_wdr(c["H"], c["W"], c["K"], c["lo"], c["hi"], c["seed"]).rgb
+    rx, ry = oracle.paper_radii(c["H"], c["W"], 5)
+    _check_log_backward(rgb, 5, rx, ry, 0.1, "c32x2", seed=13)
