@@ -97,7 +97,8 @@ __device__ Sum3 block_sum3(Sum3 v) {
 //                     (chunks that end below H-1-ry_j).
 // Entries of Rp and Cp outside those ranges are never written nor read.  Every sum is in a
 // fixed order.  Rows are wave-uniform (scalar row bases, 32-bit lane offsets), two rows in
-// flight per wave.
+// flight per wave.  The scalar pass keeps the block's g tile in LDS, where every field's pass
+// reads it back instead of streaming g again.
 template <int S>
 __device__ __forceinline__ void border_block(const BwdK &k, int bid) {
     const int ncol = (k.W + kWave - 1) / kWave;
@@ -111,6 +112,7 @@ __device__ __forceinline__ void border_block(const BwdK &k, int bid) {
     const int tile_end = min(ct * kWave + kWave, k.W);
     const uint32_t o4 = (uint32_t)xc * 4u, o8 = (uint32_t)xc * 8u;
     auto grow = [&](int y) { return reinterpret_cast<const char *>(k.g + (int64_t)y * k.ld_g); };
+    __shared__ float shg[kChunkMax][kWave];   // g of the block's rows [y0, y1)
     {
         Sum3 sacc{0.0, 0.0, 0.0};
         float g[2], e[2], pb[2];
@@ -120,24 +122,26 @@ __device__ __forceinline__ void border_block(const BwdK &k, int bid) {
             e[u] = load_at<float>(reinterpret_cast<const char *>(E + ro), o4);
             pb[u] = load_at<float>(reinterpret_cast<const char *>(Pb + ro), o4);
         };
-        auto use = [&](int u) {
+        auto use = [&](int y, int u) {
+            shg[y - y0][lane_id()] = g[u];
             const double gx = in ? (double)g[u] : 0.0;
             const double pv = (double)pb[u];
             sacc.a = __builtin_fma(gx, (double)e[u], sacc.a);
             sacc.b = __builtin_fma(gx, 1.0 - pv, sacc.b);
             sacc.c = __builtin_fma(gx, pv, sacc.c);
         };
-        int y = y0 + w;   // wave-uniform
+        int y = y0 + w;   // wave-uniform; the waves together cover every row of [y0, y1)
         if (y < y1) load(y, 0);
         while (y < y1) {
             if (y + kRows < y1) load(y + kRows, 1);
-            use(0);
+            use(y, 0);
             y += kRows;
             if (y >= y1) break;
             if (y + kRows < y1) load(y + kRows, 0);
-            use(1);
+            use(y, 1);
             y += kRows;
         }
+        // block_sum3 passes two block barriers: the g tile is complete after it
         const Sum3 tot = block_sum3(sacc);
         if (threadIdx.x == 0) {
             k.part[3 * bid] = tot.a;
@@ -157,7 +161,7 @@ __device__ __forceinline__ void border_block(const BwdK &k, int bid) {
         float g[2];
         float2 r[2];
         auto load = [&](int y, int u) {
-            g[u] = load_at<float>(grow(y), o4);
+            g[u] = shg[y - y0][lane_id()];
             r[u] = load_at<float2>(Rj + (int64_t)y * k.W * 8, o8);
         };
         auto use = [&](int y, int u) {
