@@ -16,7 +16,7 @@
 //      column) and along its tile row for the row carries (the counts left of the tile, per
 //      row): it adds aggregates until it meets an "inclusive" record, which already holds
 //      everything before it, and publishes its own inclusive records.  Each poll requests
-//      the records of two tiles at once;
+//      the records of two tiles at once (one with more than four planes);
 //   3. publishes its total column carry and looks back along the tile row for the corner
 //      carry (everything above and to the left of the tile), 16 or 8 tiles per poll;
 //   4. writes every plane entry: the tile's own 2-D prefix (a running column sum of the
@@ -180,6 +180,8 @@ __device__ __forceinline__ void write_rows(const LbK &k, const uint32_t (*ls)[kW
 template <int NP, int TH, bool CUM>
 __device__ void lookback_tile(const LbK &k, int t, uint32_t (*ls)[kWave]) {
     constexpr int NG = NP / 4;                  // groups of four planes
+    // look-back windows in tiles: two with four planes, one with eight (larger windows hold
+    // more words in registers; measured slower through the lower occupancy)
     constexpr int JC = 8 / NP;                  // column look-back window (tiles)
     constexpr int JR = 8 / NP;                  // row look-back window (tiles)
     constexpr int JK = kWave / NP;              // corner look-back window (tiles)
