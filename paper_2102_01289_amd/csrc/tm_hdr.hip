@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(kBlock) hdr_merge_kernel(MergeK k) {
     __shared__ float sh_g[3 * kZ];
     __shared__ float sh_t[16];
     for (int q = threadIdx.x; q < 3 * kZ; q += kBlock) sh_g[q] = k.g[q];
-    if (threadIdx.x < k.P) sh_t[threadIdx.x] = k.log_dt[threadIdx.x];
+    if ((int)threadIdx.x < k.P) sh_t[threadIdx.x] = k.log_dt[threadIdx.x];
     __syncthreads();
     const int64_t item = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t nitems = (int64_t)k.H * k.groups;

@@ -142,7 +142,6 @@ __device__ __forceinline__ void write_rows(const LbK &k, const uint32_t (*ls)[kW
         tp[p][0] = tp[p][1] = 0u;
     }
     TM_GLOBAL uint32_t *out = gptr(k.hist) + (int64_t)y0 * k.ld_hist + xl;
-#pragma unroll 2
     for (int r = 0; r < rows; ++r, out += k.ld_hist) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
