@@ -10,8 +10,11 @@ from _cases import edges_ref, fill_garbage, hist_ref, lum_ref, rgb_case, to_dev
 
 pytestmark = pytest.mark.gpu
 
+# ragged and degenerate shapes, several tiles each way, and two long carry chains: 250 tile
+# rows in one tile column pair (the column look-back) and 71 tiles in one tile row (the row
+# and corner look-backs)
 SHAPES = [(1, 1), (1, 300), (300, 1), (37, 123), (64, 256), (100, 700), (257, 1030),
-          (1000, 777)]
+          (1000, 777), (4000, 130), (8, 9000)]
 
 
 def _status(ws):
