@@ -71,13 +71,13 @@ __global__ void __launch_bounds__(kBlock) hdr_response_kernel(RespK k) {
     }
     if (tid < k.P) sh_t[tid] = (double)k.log_dt[tid];
     if (tid == 0) sh_bad = 0;
+    for (int e = tid; e < kN * kLd; e += kBlock) M[e] = 0.0;   // coalesced, before the rows fill
     __syncthreads();
 
     // ---- assembly: thread z owns row col_of(z) of the reduced normal equations
     const int z = tid;
     if (z != kMid) {
-        double *row = M + (size_t)col_of(z) * kLd;
-        for (int q = 0; q < kN; ++q) row[q] = 0.0;
+        double *row = M + (size_t)col_of(z) * kLd;   // zeroed above
         double r = 0.0;
         for (int i = 0; i < k.N; ++i) {
             const uint8_t *zi = sh_z + i * k.P;
@@ -117,54 +117,136 @@ __global__ void __launch_bounds__(kBlock) hdr_response_kernel(RespK k) {
     }
     __syncthreads();
 
-    // ---- Cholesky M = L L^T in place (lower triangle), right-looking.  A pivot at or below
+    // ---- Cholesky M = L L^T in place (lower triangle), right-looking, in panels of kPb
+    // columns.  Each entry receives the updates of the pivots before it one at a time, in
+    // pivot order, exactly as in the unblocked elimination: a panel is factored in LDS, then
+    // the trailing update applies the panel's pivots to every later entry in turn, reading
+    // the entry from memory once per panel rather than once per pivot.  A pivot at or below
     // kN 2^-52 of the largest diagonal entry marks the system singular (rank-deficient up to
     // rounding).
+    constexpr int kBatch = 16;                   // rows requested per round trip
+    constexpr int kPb = 16;                      // panel width
+    constexpr int kPs = kPb + 1;                 // LDS row pitch of the panel (odd)
     __shared__ double sh_tol;
+    __shared__ double sh_pan[kN * kPs];          // the panel's columns, rows c0 .. kN-1
+    __shared__ double sh_d[kLd];                 // diagonal of L
     if (tid == 0) {
         double mx = 0.0;
         for (int q = 0; q < kN; ++q) mx = fmax(mx, M[(size_t)q * kLd + q]);
         sh_tol = (double)kN * 0x1p-52 * mx;
     }
     __syncthreads();
-    for (int p = 0; p < kN; ++p) {
-        if (tid == 0) {
-            const double d = M[(size_t)p * kLd + p];
-            if (!(d > sh_tol)) sh_bad = 1;
-            sh_v[p] = sqrt(d > 0.0 ? d : 1.0);
-            M[(size_t)p * kLd + p] = sh_v[p];
+    for (int c0 = 0; c0 < kN; c0 += kPb) {
+        const int nc = min(kPb, kN - c0);        // columns of this panel
+        const int nr = kN - c0;                  // its rows: c0 .. kN-1
+        for (int e = tid; e < nr * kPb; e += kBlock) {
+            const int r = e / kPb, q = e % kPb;
+            if (q < nc) sh_pan[r * kPs + q] = M[(size_t)(c0 + r) * kLd + c0 + q];
         }
         __syncthreads();
-        const double piv = sh_v[p];
-        for (int i = p + 1 + tid; i < kN; i += kBlock) {
-            const double l = M[(size_t)i * kLd + p] / piv;
-            M[(size_t)i * kLd + p] = l;
-            sh_v[i] = l;
+        for (int q = 0; q < nc; ++q) {           // pivot p = c0 + q
+            const int p = c0 + q;
+            if (tid == 0) {
+                const double d = sh_pan[q * kPs + q];
+                if (!(d > sh_tol)) sh_bad = 1;
+                const double sq = sqrt(d > 0.0 ? d : 1.0);
+                sh_pan[q * kPs + q] = sq;
+                sh_d[p] = sq;
+            }
+            __syncthreads();
+            const double piv = sh_d[p];
+            for (int r = q + 1 + tid; r < nr; r += kBlock) sh_pan[r * kPs + q] /= piv;
+            __syncthreads();
+            const int rest = nc - q - 1;         // later columns of the panel
+            if (rest > 0) {
+                for (int r = q + 1 + tid; r < nr; r += kBlock) {
+                    const double lr = sh_pan[r * kPs + q];
+                    for (int q2 = q + 1; q2 < nc && q2 <= r; ++q2)
+                        sh_pan[r * kPs + q2] -= lr * sh_pan[q2 * kPs + q];
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        // rows i > p, columns p < j <= i: thread j walks the rows (coalesced along a row)
-        for (int i = p + 1; i < kN; ++i) {
-            const int j = p + 1 + tid;
-            if (j <= i) M[(size_t)i * kLd + j] -= sh_v[i] * sh_v[j];
+        // the factored panel's lower part back to memory (the solves read L there)
+        for (int e = tid; e < nr * kPb; e += kBlock) {
+            const int r = e / kPb, q = e % kPb;
+            if (q < nc && r >= q) M[(size_t)(c0 + r) * kLd + c0 + q] = sh_pan[r * kPs + q];
+        }
+        // trailing update: thread t owns column j = c0 + nc + t (rows i >= j); every thread
+        // walks the rows in the same order, so each LDS read is a broadcast
+        const int j = c0 + nc + tid;
+        if (j < kN) {
+            double lj[kPb];
+#pragma unroll
+            for (int q = 0; q < kPb; ++q) lj[q] = q < nc ? sh_pan[(j - c0) * kPs + q] : 0.0;
+            for (int i0 = c0 + nc; i0 < kN; i0 += kBatch) {
+                // kBatch rows advance together, pivot by pivot (each entry's updates stay in
+                // pivot order); rows past the matrix or above the diagonal are not stored
+                double acc[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int i = i0 + u;
+                    acc[u] = (i < kN && i >= j) ? M[(size_t)i * kLd + j] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < kPb; ++q) {
+                    if (q < nc) {
+#pragma unroll
+                        for (int u = 0; u < kBatch; ++u) {
+                            const int r = min(i0 + u, kN - 1) - c0;
+                            acc[u] -= sh_pan[r * kPs + q] * lj[q];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int i = i0 + u;
+                    if (i < kN && i >= j) M[(size_t)i * kLd + j] = acc[u];
+                }
+            }
         }
         __syncthreads();
     }
 
-    // ---- L y = rhs, then L^T x = y (in sh_v)
+    // ---- L y = rhs, then L^T x = y (in sh_v).  Thread i owns unknown i and requests the
+    // entries of kBatch steps at once: row i of L going forward, column i going back.
     for (int q = tid; q < kN; q += kBlock) sh_v[q] = rhs[q];
     __syncthreads();
-    for (int p = 0; p < kN; ++p) {
-        if (tid == 0) sh_v[p] /= M[(size_t)p * kLd + p];
-        __syncthreads();
-        for (int i = p + 1 + tid; i < kN; i += kBlock) sh_v[i] -= M[(size_t)i * kLd + p] * sh_v[p];
-        __syncthreads();
+    const int ri = tid;   // kBlock >= kN: one unknown per thread
+    for (int p0 = 0; p0 < kN; p0 += kBatch) {
+        double lr[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int p = p0 + u;
+            lr[u] = (ri < kN && p < ri) ? M[(size_t)ri * kLd + p] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int p = p0 + u;
+            if (p >= kN) break;
+            if (ri == p) sh_v[p] /= sh_d[p];
+            __syncthreads();
+            if (ri < kN && ri > p) sh_v[ri] -= lr[u] * sh_v[p];
+        }
     }
-    for (int p = kN - 1; p >= 0; --p) {
-        if (tid == 0) sh_v[p] /= M[(size_t)p * kLd + p];
-        __syncthreads();
-        for (int i = tid; i < p; i += kBlock) sh_v[i] -= M[(size_t)p * kLd + i] * sh_v[p];
-        __syncthreads();
+    __syncthreads();
+    for (int p0 = kN - 1; p0 >= 0; p0 -= kBatch) {
+        double lc[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int p = p0 - u;
+            lc[u] = (p >= 0 && ri < p) ? M[(size_t)p * kLd + ri] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int p = p0 - u;
+            if (p < 0) break;
+            if (ri == p) sh_v[p] /= sh_d[p];
+            __syncthreads();
+            if (ri < p) sh_v[ri] -= lc[u] * sh_v[p];
+        }
     }
+    __syncthreads();
     // a singular system (too few distinct sample values) leaves NaN
     const float nan = __builtin_nanf("");
     k.g[c * kZ + z] = sh_bad ? nan : (z == kMid ? 0.f : (float)sh_v[col_of(z)]);
