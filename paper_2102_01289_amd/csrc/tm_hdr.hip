@@ -79,25 +79,38 @@ __global__ void __launch_bounds__(kBlock) hdr_response_kernel(RespK k) {
     if (z != kMid) {
         double *row = M + (size_t)col_of(z) * kLd;   // zeroed above
         double r = 0.0;
-        for (int i = 0; i < k.N; ++i) {
-            const uint8_t *zi = sh_z + i * k.P;
-            bool hit = false;
-            double S = 0.0;
-            for (int j = 0; j < k.P; ++j) {
-                const double w = (double)hat(zi[j]);
-                S += w * w;
-                hit |= zi[j] == z;
+        // samples in chunks of 32: first the chunk's samples that hold code value z (a bit
+        // mask), then only those, in sample order; a wave then runs as many rounds as its
+        // busiest lane has hits, not one per sample that any lane hits
+        for (int i0 = 0; i0 < k.N; i0 += 32) {
+            const int nch = min(32, k.N - i0);
+            uint32_t hits = 0u;
+            for (int u = 0; u < nch; ++u) {
+                const uint8_t *zu = sh_z + (i0 + u) * k.P;
+                bool h = false;
+                for (int j = 0; j < k.P; ++j) h |= zu[j] == z;
+                hits |= h ? 1u << u : 0u;
             }
-            if (!hit || S == 0.0) continue;
-            for (int j = 0; j < k.P; ++j) {
-                if (zi[j] != z) continue;
-                const double wj = (double)hat(z);
-                const double aj = wj * wj;
-                for (int jj = 0; jj < k.P; ++jj) {
-                    const double wjj = (double)hat(zi[jj]);
-                    const double q = (jj == j ? aj : 0.0) - aj * (wjj * wjj) / S;
-                    if (zi[jj] != kMid) row[col_of(zi[jj])] += q;
-                    r += q * sh_t[jj];
+            while (hits) {
+                const int i = i0 + __builtin_ctz(hits);
+                hits &= hits - 1u;
+                const uint8_t *zi = sh_z + i * k.P;
+                double S = 0.0;
+                for (int j = 0; j < k.P; ++j) {
+                    const double w = (double)hat(zi[j]);
+                    S += w * w;
+                }
+                if (S == 0.0) continue;
+                for (int j = 0; j < k.P; ++j) {
+                    if (zi[j] != z) continue;
+                    const double wj = (double)hat(z);
+                    const double aj = wj * wj;
+                    for (int jj = 0; jj < k.P; ++jj) {
+                        const double wjj = (double)hat(zi[jj]);
+                        const double q = (jj == j ? aj : 0.0) - aj * (wjj * wjj) / S;
+                        if (zi[jj] != kMid) row[col_of(zi[jj])] += q;
+                        r += q * sh_t[jj];
+                    }
                 }
             }
         }
