@@ -240,6 +240,11 @@ tm_status tm_integral_histogram(const float *v, int64_t ld_v, int32_t H, int32_t
  * Every wait is bounded, so the call always completes.  Calls that share a workspace must
  * not overlap. */
 size_t tm_lookback_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_hist_layout layout);
+/* Test hook for the bounded waits of tm_integral_histogram_lookback: the polls of one
+ * look-back window before it counts as timed out (then the status word is raised and the pass
+ * still completes), for the calls made after it in this process; 0 restores the default
+ * (2^20 polls, about a second).  Not thread-safe against concurrent calls. */
+void tm_lookback_set_spin_limit(uint32_t polls);
 tm_status tm_integral_histogram_lookback(const float *v, int64_t ld_v, int32_t H, int32_t W,
                                          const float *edges, int32_t n_bins,
                                          tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,

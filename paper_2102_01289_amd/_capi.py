@@ -54,6 +54,7 @@ SIGNATURES = {
     "tm_prologue": (ctypes.c_int, [P, I64, I64, I32, I32, I32, P, I64, P, P, P, P, SZ, P]),
     "tm_prologue_noalloc": (ctypes.c_int, [P, I64, I64, I32, I32, I32, P, I64, P, P, P, P]),
     "tm_log_luminance": (ctypes.c_int, [P, I64, I32, I32, P, I64, P, P, P, SZ, P]),
+    "tm_lookback_set_spin_limit": (None, [ctypes.c_uint32]),
     "tm_log_luminance_backward": (ctypes.c_int, [P, I64, I32, I32, P, I64, P, I64, P]),
     "tm_hdr_response_workspace_bytes": (SZ, []),
     "tm_hdr_response": (ctypes.c_int, [P, I64, I64, I64, I32, I32, I32, P, I32, P,

@@ -395,6 +395,8 @@ size_t tm_lookback_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_hist
     return make_lookback_plan(H, W, np, lookback_rows(H, W, np)).total;
 }
 
+void tm_lookback_set_spin_limit(uint32_t polls) { set_lookback_spin_limit(polls); }
+
 tm_status tm_integral_histogram_lookback(const float *v, int64_t ld_v, int32_t H, int32_t W,
                                          const float *edges, int32_t n_bins,
                                          tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,

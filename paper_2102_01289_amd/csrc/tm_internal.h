@@ -274,6 +274,7 @@ struct LookbackPlan {
     int th, tiles_x, tiles_y;
     size_t rowrec, colrec, cornrec, total;   // byte offsets in the workspace; header at 0
 };
+void set_lookback_spin_limit(uint32_t polls);   // 0: the default bound
 int lookback_rows(int H, int W, int n_planes);   // rows per look-back tile (16 or 32)
 LookbackPlan make_lookback_plan(int H, int W, int n_planes, int th);
 hipError_t launch_lookback_hist(const LookbackArgs &a, const LookbackPlan &plan, void *ws,

@@ -38,7 +38,6 @@ namespace {
 constexpr int kLbVec = 2;                   // columns per lane
 constexpr int kLbTw = kWave * kLbVec;       // columns per tile
 constexpr int kLbBlock = 128;               // 2 waves, 2 independent tiles
-constexpr uint32_t kSpin = 1u << 20;        // bound on the polls of one window
 constexpr uint32_t kAgg = 1, kIncl = 2;     // record states
 constexpr uint32_t kCountMask = (1u << 30) - 1;
 
@@ -57,6 +56,7 @@ struct LbK {
     uint32_t *colrec;    // [tile][np][kLbTw]
     uint64_t *cornrec;   // [tile][np]
     int nt;              // non-temporal plane stores
+    uint32_t spin;       // bound on the polls of one window (about a second by default)
 };
 
 __device__ __forceinline__ void put32(uint32_t *p, uint32_t state, uint32_t count) {
@@ -107,7 +107,7 @@ __device__ __forceinline__ void poll32(const LbK &k, uint32_t (&w)[J][S], uint32
 #pragma unroll
             for (int s = 0; s < S; ++s) miss = miss || (w[j][s] >> 30) == 0;
         if (!__any(miss)) return;
-        if (it == kSpin) {
+        if (it == k.spin) {
 #pragma unroll
             for (int j = 0; j < J; ++j)
 #pragma unroll
@@ -403,7 +403,7 @@ __device__ void lookback_tile(const LbK &k, int t, uint32_t (*ls)[kWave]) {
             for (uint32_t it = 0;; ++it) {
                 const bool miss = (w >> 32) == 0;
                 if (!__any(miss)) break;
-                if (it == kSpin) {
+                if (it == k.spin) {
                     if (miss) {
                         w = (uint64_t)kIncl << 32;
                         raise_status(k);
@@ -483,7 +483,13 @@ __global__ void __launch_bounds__(kLbBlock) lookback_clear_kernel(uint4 *rec, in
     if (i < 2) hdr[i] = 0u;
 }
 
+// Polls of one look-back window before it counts as timed out (settable for tests of that
+// path; 0 selects the default of 2^20, about a second).
+uint32_t g_lookback_spin = 0;
+
 }  // namespace
+
+void set_lookback_spin_limit(uint32_t polls) { g_lookback_spin = polls; }
 
 // Rows per tile: 32, or 16 while 32 would leave fewer than about two waves per compute unit,
 // and always 16 for more than four planes (their rows take twice the LDS).
@@ -530,6 +536,7 @@ hipError_t launch_lookback_hist(const LookbackArgs &a, const LookbackPlan &plan,
     k.colrec = reinterpret_cast<uint32_t *>(w + plan.colrec);
     k.cornrec = reinterpret_cast<uint64_t *>(w + plan.cornrec);
     k.nt = a.nt;
+    k.spin = g_lookback_spin ? g_lookback_spin : (1u << 20);
     // the record area is a whole number of 256-byte blocks: cleared 16 bytes per thread
     const int64_t n16 = (int64_t)(plan.total - plan.rowrec) / 16;
     hipLaunchKernelGGL(lookback_clear_kernel, dim3((unsigned)((n16 + kLbBlock - 1) / kLbBlock)),

@@ -80,3 +80,29 @@ def test_lookback_histogram_rejects_more_than_eight_planes():
         tm.tm_integral_histogram_lookback(v, edges, 10, "cumulative",
                                           ws=torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
     assert "UNSUPPORTED" in str(e.value) or "-6" in str(e.value)
+
+
+def test_lookback_bounded_waits_end_in_the_status_word():
+    # one poll per window: a wait that finds a record absent gives up almost at once, counts
+    # the record as an inclusive zero and raises the status word, and the pass still completes.
+    # Either no wait gave up (status 0, planes exact) or one did (status 1: planes not to be
+    # used).  With the default bound restored the pass is exact again.
+    H, W, n = 3000, 4000, 5
+    ref = lum_ref(rgb_case(H, W, 16, -3.0, 5.0, seed=47))
+    v = to_dev(ref)
+    edges = to_dev(edges_ref(ref, n))
+    three = tm.tm_integral_histogram(v, edges, n)
+    lib = tm._lib()
+    try:
+        lib.tm_lookback_set_spin_limit(1)
+        for _ in range(3):
+            h, ws = tm.tm_integral_histogram_lookback(v, edges, n)
+            st = _status(ws)
+            assert st in (0, 1)
+            if st == 0:
+                assert torch.equal(three.raw_region(), h.raw_region())
+    finally:
+        lib.tm_lookback_set_spin_limit(0)
+    h, ws = tm.tm_integral_histogram_lookback(v, edges, n)
+    assert _status(ws) == 0
+    assert torch.equal(three.raw_region(), h.raw_region())
