@@ -262,6 +262,20 @@ tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
 size_t tm_tables_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_sat_prec prec,
                                  const tm_tune *tune);
 
+/* Both tables in one pass, each of its own plane of the same H x W: the integral images
+ * (Eq. 5) of v_sat and the integral histogram (Eq. 7-8) of v_hist's bins under edges.  For
+ * the log-domain variant, whose local statistics are those of l = ln i (tm_log_luminance)
+ * while the bins stay those of i (Eq. 9).  Results equal tm_integral_image of v_sat and
+ * tm_integral_histogram of v_hist bit for bit; sat and hist are both required (else
+ * TM_ERR_ARG), other arguments as for tm_integral_tables, whose workspace size applies. */
+tm_status tm_integral_tables_split(const float *v_sat, int64_t ld_v_sat, const float *v_hist,
+                                   int64_t ld_v_hist, int32_t H, int32_t W, tm_sat_prec prec,
+                                   const float *offsets, void *sat, int64_t ld_sat,
+                                   const float *edges, int32_t n_bins, tm_hist_layout layout,
+                                   uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
+                                   const tm_tune *tune, void *ws, size_t ws_bytes,
+                                   void *stream);
+
 /* ---------------------------------------------------------------- stage a4: forward */
 
 /* Tone-mapped luminance (Eq. 1-4, 6, 9, 10 and the fusion of Eq. 3) of v, from its

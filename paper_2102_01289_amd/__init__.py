@@ -18,7 +18,8 @@ __all__ = [
     "TmError", "Table", "table_geometry", "paper_radii", "make_params", "tune", "default_tune",
     "image_tune", "tm_integral_histogram_lookback", "tm_log_luminance_backward",
     "tm_luminance", "tm_image_stats", "tm_prologue", "tm_integral_image",
-    "tm_integral_histogram", "tm_integral_tables", "tm_tonemap_forward",
+    "tm_integral_histogram", "tm_integral_tables", "tm_integral_tables_split",
+    "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
     "residual_planes", "residual_pairs", "ToneMapper", "tonemap", "Batch",
     "tm_tonemap_forward_rgb", "tonemap_rgb", "tm_tonemap_forward_maps", "tm_prologue_noalloc",
@@ -346,6 +347,33 @@ def tm_integral_tables(v: torch.Tensor, prec: str | None = "c32x2", offsets=None
     return sat, hist
 
 
+def tm_integral_tables_split(v_sat: torch.Tensor, v_hist: torch.Tensor, prec: str = "c32x2",
+                             offsets=None, edges=None, n_bins: int = 5,
+                             layout: str = "cumulative", tune=None, stream=None,
+                             sat: Table | None = None, hist: Table | None = None):
+    """Integral image of v_sat (prec) and integral histogram of v_hist's bins (layout) in one
+    pass: the log-domain variant's tables (statistics of ln i, bins of i).  Returns (sat,
+    hist); n_bins must leave at least one plane."""
+    H, W, ld = _img(v_sat, "v_sat")
+    Hh, Wh, ldh = _img(v_hist, "v_hist")
+    if (Hh, Wh) != (H, W):
+        raise ValueError("v_sat and v_hist must have the same shape")
+    dev = v_sat.device
+    sat = sat if sat is not None else Table(H, W, prec, 1, dev)
+    planes = n_bins if layout == "per_bin" else n_bins - 1
+    if hist is None:
+        if planes < 1:
+            raise ValueError("the histogram needs at least one plane")
+        hist = Table(H, W, "u32", planes, dev)
+    pcode = _capi.SAT_PREC[prec]
+    ws = _ws(_lib().tm_tables_workspace_bytes(H, W, n_bins, pcode, _tune_ref(tune)), dev)
+    _ck("tm_integral_tables_split", _lib().tm_integral_tables_split(
+        _vp(v_sat), ld, _vp(v_hist), ldh, H, W, pcode, _vp(offsets), _vp(sat.ptr), sat.ld,
+        _vp(edges), n_bins, _capi.HIST_LAYOUT[layout], _vp(hist.ptr), hist.ld,
+        hist.plane_stride, _tune_ref(tune), _vp(ws), ws.numel(), _stream(stream)))
+    return sat, hist
+
+
 def tm_integral_image(v, prec="c32x2", offsets=None, tune=None, stream=None) -> Table:
     H, W, ld = _img(v, "v")
     sat = Table(H, W, prec, 1, v.device)
@@ -600,15 +628,20 @@ class ToneMapper:
         if self.variance == "log":
             tm_log_luminance(self.lum, stream, self.logv, self.log_offsets, self.log_minmax,
                              self.ws_stats)
-            _ck("tm_integral_image", _lib().tm_integral_image(
-                _vp(self.logv), self.logv.stride(0), self.H, self.W, _capi.SAT_PREC[self.prec],
-                _vp(self.log_offsets), _vp(self.sat.ptr), self.sat.ld, self.tune_ref,
-                _vp(self.ws_tab), self.ws_tab.numel(), _stream(stream)))
-            if h is not None:
-                _ck("tm_integral_histogram", _lib().tm_integral_histogram(
-                    _vp(self.lum), self.lum.stride(0), self.H, self.W, _vp(self.edges),
-                    self.params.n_bins, 1, _vp(h.ptr), h.ld, h.plane_stride, self.tune_ref,
-                    _vp(self.ws_tab), self.ws_tab.numel(), _stream(stream)))
+            if h is None:
+                _ck("tm_integral_image", _lib().tm_integral_image(
+                    _vp(self.logv), self.logv.stride(0), self.H, self.W,
+                    _capi.SAT_PREC[self.prec], _vp(self.log_offsets), _vp(self.sat.ptr),
+                    self.sat.ld, self.tune_ref, _vp(self.ws_tab), self.ws_tab.numel(),
+                    _stream(stream)))
+                return
+            # statistics of l and bins of i in one three-stage pass
+            _ck("tm_integral_tables_split", _lib().tm_integral_tables_split(
+                _vp(self.logv), self.logv.stride(0), _vp(self.lum), self.lum.stride(0), self.H,
+                self.W, _capi.SAT_PREC[self.prec], _vp(self.log_offsets), _vp(self.sat.ptr),
+                self.sat.ld, _vp(self.edges), self.params.n_bins, 1, _vp(h.ptr), h.ld,
+                h.plane_stride, self.tune_ref, _vp(self.ws_tab), self.ws_tab.numel(),
+                _stream(stream)))
             return
         _ck("tm_integral_tables", _lib().tm_integral_tables(
             _vp(self.lum), self.lum.stride(0), self.H, self.W, _capi.SAT_PREC[self.prec],

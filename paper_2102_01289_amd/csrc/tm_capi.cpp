@@ -308,15 +308,17 @@ size_t tm_tables_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_sat_pr
     return make_scan_plan(H, W, (int)prec, n_bins, t).total;
 }
 
-tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
-                             tm_sat_prec prec, const float *offsets, void *sat,
-                             int64_t ld_sat, const float *edges, int32_t n_bins,
-                             tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,
-                             int64_t plane_stride, const tm_tune *tune, void *ws,
-                             size_t ws_bytes, void *stream) {
+// v_hist: the plane the histogram bins (null: v)
+static tm_status run_tables(const float *v, int64_t ld_v, const float *v_hist,
+                            int64_t ld_v_hist, int32_t H, int32_t W, tm_sat_prec prec,
+                            const float *offsets, void *sat, int64_t ld_sat,
+                            const float *edges, int32_t n_bins, tm_hist_layout layout,
+                            uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
+                            const tm_tune *tune, void *ws, size_t ws_bytes, void *stream) {
     TM_TRY(check_image(H, W));
     if (!v) return TM_ERR_ARG;
     TM_TRY(check_plane(H, W, ld_v));
+    if (v_hist) TM_TRY(check_plane(H, W, ld_v_hist));
     if (!sat && !hist) return TM_ERR_ARG;
     int n_planes = 0;
     if (sat) {
@@ -344,6 +346,8 @@ tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
     ScanArgs a{};
     a.v = v;
     a.ld_v = ld_v;
+    a.v_hist = v_hist;
+    a.ld_v_hist = ld_v_hist;
     a.H = H;
     a.W = W;
     a.sat_prec = sp;
@@ -358,6 +362,29 @@ tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
     a.ld_hist = ld_hist;
     a.plane_stride = plane_stride;
     return from_hip(launch_tables(a, plan, ws, (hipStream_t)stream));
+}
+
+tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                             tm_sat_prec prec, const float *offsets, void *sat,
+                             int64_t ld_sat, const float *edges, int32_t n_bins,
+                             tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,
+                             int64_t plane_stride, const tm_tune *tune, void *ws,
+                             size_t ws_bytes, void *stream) {
+    return run_tables(v, ld_v, nullptr, 0, H, W, prec, offsets, sat, ld_sat, edges, n_bins,
+                      layout, hist, ld_hist, plane_stride, tune, ws, ws_bytes, stream);
+}
+
+tm_status tm_integral_tables_split(const float *v_sat, int64_t ld_v_sat, const float *v_hist,
+                                   int64_t ld_v_hist, int32_t H, int32_t W, tm_sat_prec prec,
+                                   const float *offsets, void *sat, int64_t ld_sat,
+                                   const float *edges, int32_t n_bins, tm_hist_layout layout,
+                                   uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
+                                   const tm_tune *tune, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    if (!v_sat || !v_hist || !sat || !hist) return TM_ERR_ARG;
+    return run_tables(v_sat, ld_v_sat, v_hist, ld_v_hist, H, W, prec, offsets, sat, ld_sat,
+                      edges, n_bins, layout, hist, ld_hist, plane_stride, tune, ws, ws_bytes,
+                      stream);
 }
 
 tm_status tm_integral_image(const float *v, int64_t ld_v, int32_t H, int32_t W,

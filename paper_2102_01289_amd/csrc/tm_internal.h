@@ -94,6 +94,10 @@ struct ScanK {
     int64_t ld_v;
     int H, W, th, tiles_x, tiles_y;
     int vec_load;                 // rows of v are 16-byte aligned
+    // the plane the histogram items bin (v itself unless the caller gives another one)
+    const float *vh;
+    int64_t ld_vh;
+    int vec_load_h;
     const float *offsets;
     void *sat;
     int64_t ld_sat;
@@ -117,6 +121,8 @@ struct ScanK {
 struct ScanArgs {
     const float *v;
     int64_t ld_v;
+    const float *v_hist;     // plane the histogram bins; null: v
+    int64_t ld_v_hist;
     int H, W;
     int sat_prec;            // -1 none
     const float *offsets;    // C32X2

@@ -1037,7 +1037,10 @@ __host__ __device__ __forceinline__ int items_per_tile(const ScanK &k) {
     return (SAT ? 1 : 0) + (HIST ? k.hist_items : 0);
 }
 
-template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ, bool THIRD>
+// HSRC: histogram items bin k.vh (single-image launches); the batch bins each image's own
+// luminance (vh == v) and reads its parameters from global memory, where a modified copy
+// would cost registers.
+template <int P, int VEC, int CHUNK, bool SAT, bool HIST, bool ADJ, bool THIRD, bool HSRC = true>
 __device__ __forceinline__ void tile_item(const ScanK &k, int item) {
     const int ipt = items_per_tile<SAT, HIST>(k);
     const int tile = item / ipt, r = item - tile * ipt;
@@ -1051,8 +1054,18 @@ __device__ __forceinline__ void tile_item(const ScanK &k, int item) {
     if constexpr (HIST) {
         const int h = r - (SAT ? 1 : 0);
         const int cb = h * k.hist_chunks, ce = cb + k.hist_chunks;
-        if (THIRD) stage3_tile<P, VEC, CHUNK, false, true, ADJ>(k, tile, cb, ce);
-        else stage1_tile<P, VEC, CHUNK, false, true, ADJ>(k, tile, cb, ce);
+        if constexpr (HSRC) {
+            // histogram items bin their own source plane (the same one unless given another)
+            ScanK kh = k;
+            kh.v = k.vh;
+            kh.ld_v = k.ld_vh;
+            kh.vec_load = k.vec_load_h;
+            if (THIRD) stage3_tile<P, VEC, CHUNK, false, true, ADJ>(kh, tile, cb, ce);
+            else stage1_tile<P, VEC, CHUNK, false, true, ADJ>(kh, tile, cb, ce);
+        } else {
+            if (THIRD) stage3_tile<P, VEC, CHUNK, false, true, ADJ>(k, tile, cb, ce);
+            else stage1_tile<P, VEC, CHUNK, false, true, ADJ>(k, tile, cb, ce);
+        }
     }
 }
 
@@ -1092,7 +1105,7 @@ __global__ void __launch_bounds__(kBlock) scan_tiles_batch(const ScanK *__restri
     int i = g < total ? __builtin_amdgcn_readfirstlane(find_image(prefix, count, g)) : 0;
     for (; g < total; g += step) {
         while (g >= prefix[i + 1]) ++i;
-        tile_item<P, VEC, CHUNK, SAT, HIST, false, THIRD>(ks[i], (int)(g - prefix[i]));
+        tile_item<P, VEC, CHUNK, SAT, HIST, false, THIRD, false>(ks[i], (int)(g - prefix[i]));
     }
 }
 
@@ -1279,6 +1292,9 @@ ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws) {
     k.tiles_x = plan.tiles_x;
     k.tiles_y = plan.tiles_y;
     k.vec_load = (((uintptr_t)a.v & 15u) == 0) && (a.ld_v % 4 == 0);
+    k.vh = a.v_hist ? a.v_hist : a.v;
+    k.ld_vh = a.v_hist ? a.ld_v_hist : a.ld_v;
+    k.vec_load_h = (((uintptr_t)k.vh & 15u) == 0) && (k.ld_vh % 4 == 0);
     k.offsets = a.offsets;
     k.sat = a.sat;
     k.ld_sat = a.ld_sat;
@@ -1336,6 +1352,8 @@ hipError_t launch_suffix_adjoint(const double2 *d, int64_t ld_d, const float *v,
     char *w = static_cast<char *>(ws);
     k.v = v;
     k.ld_v = ld_v;
+    k.vh = v;
+    k.ld_vh = ld_v;
     k.H = H;
     k.W = W;
     k.th = plan.th;

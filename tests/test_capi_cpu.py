@@ -305,3 +305,23 @@ def test_log_chain_rule_argument_checks():
     assert lib.tm_log_luminance_backward(P(a), 64, 8, 8, P(a), 64, P(a + 256), 64, None) == -1
     assert lib.tm_log_luminance_backward(P(a), 64, 8, 8, P(a), 64, P(a), 128, None) == -1
     assert lib.tm_log_luminance_backward(P(a), 4, 8, 8, P(a), 64, P(a), 64, None) == -2
+
+
+def test_split_tables_argument_checks():
+    # both planes and both tables are required; the histogram plane's pitch is checked like
+    # the other's; all before any device work
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    a = P(1 << 20)
+    ok = dict(prec=0, ws=1 << 20)
+
+    def call(vs, ldvs, vh, ldvh, sat, hist, ld_hist=64):
+        return lib.tm_integral_tables_split(vs, ldvs, vh, ldvh, 10, 10, ok["prec"], None, sat,
+                                            64, a, 5, 1, hist, ld_hist, 1 << 12, None, a,
+                                            ok["ws"], None)
+    assert call(None, 10, a, 10, a, a) == -1
+    assert call(a, 10, None, 10, a, a) == -1
+    assert call(a, 10, a, 10, None, a) == -1
+    assert call(a, 10, a, 10, a, None) == -1
+    assert call(a, 10, a, 9, a, a) == -2          # histogram plane's pitch below W
+    assert call(a, 9, a, 10, a, a) == -2

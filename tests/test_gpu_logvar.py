@@ -11,7 +11,8 @@ import torch
 import oracle
 import paper_2102_01289_amd as tm
 from _bounds import backward_bound, forward_bound, tiling, window_sums
-from _cases import check_scalar_gradients, edges_ref, lum_ref, rgb_case, to_dev
+from _cases import (check_scalar_gradients, edges_ref, fill_garbage, lum_ref, rgb_case,
+                    to_dev)
 from synth import WORKLOADS, gen_wdr
 
 pytestmark = pytest.mark.gpu
@@ -179,6 +180,45 @@ def test_log_forward_4000x3000():
 
 
 # ------------------------------------------------------------------------ gradient
+@pytest.mark.parametrize("H,W,n,layout", [(1, 1, 2, "cumulative"), (37, 123, 5, "cumulative"),
+                                           (130, 1030, 9, "cumulative"), (256, 256, 5, "per_bin"),
+                                           (61, 517, 3, "per_bin"), (1080, 1920, 5, "cumulative")])
+@pytest.mark.parametrize("prec", ["c32x2", "f64"])
+def test_split_tables_equal_the_two_single_builds(H, W, n, layout, prec):
+    # one three-stage pass with the integral image of l and the histogram of i: bit-identical
+    # to the separate builds, and the histogram exact against the oracle's (Eq. 7-8).  The
+    # luminance plane has a pitch of W+3 (rows not 16-byte aligned) while l's rows are.
+    lum = lum_ref(rgb_case(H, W, 5, -3.0, 5.0, seed=H * 7 + W))
+    big = torch.zeros((H, W + 3), dtype=torch.float32, device="cuda")
+    big[:, :W] = to_dev(lum)
+    lum_d = big[:, :W]
+    l, loff, _ = tm.tm_log_luminance(lum_d)
+    e = edges_ref(lum, n)
+    edges = to_dev(e)
+    sat = tm.Table(H, W, prec, 1)
+    hist = tm.Table(H, W, "u32", n if layout == "per_bin" else n - 1)
+    fill_garbage(sat)
+    fill_garbage(hist)         # the border zeros must be written too
+    tm.tm_integral_tables_split(l, lum_d, prec, loff, edges, n, layout, sat=sat, hist=hist)
+    sat1 = tm.tm_integral_image(l, prec, loff)
+    hist1 = tm.tm_integral_histogram(lum_d, edges, n, layout)
+    torch.cuda.synchronize()
+    assert torch.equal(sat.raw_region(), sat1.raw_region())
+    assert torch.equal(hist.raw_region(), hist1.raw_region())
+    G = hist.padded()[..., 0]
+    if H * W <= 256 * 256:
+        want = oracle.integral_histogram(oracle.bins(lum, e), n,
+                                         cumulative=layout == "cumulative")
+        assert np.array_equal(G.numpy().astype(np.uint64), want)
+
+
+def test_split_tables_shape_mismatch_rejected():
+    a = torch.zeros((8, 8), device="cuda")
+    with pytest.raises(ValueError):
+        tm.tm_integral_tables_split(a, torch.zeros((8, 9), device="cuda"), "f64", None,
+                                    torch.zeros(4, device="cuda"), 5)
+
+
 def test_log_chain_rule_kernel():
     # grad_i = grad_l / i (one correctly rounded FP32 division) above the floor, 0 below;
     # in place too
