@@ -182,9 +182,9 @@ tm_status tm_prologue_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rg
                               int32_t W, int32_t n_bins, float *lum, int64_t ld_lum,
                               float *edges, float *offsets, float *minmax, void *stream);
 
-/* Log-domain variance variant.  Section II-A builds the integral images "of i and i^2"
- * (Eq. 5) for Eq. 10's window variance; the method is also defined with that variance taken
- * of the logarithmic image l the bins are cut from.  This call writes
+/* Log-domain variance variant.  Section II-A builds the integral images of the image and of
+ * its square (Eq. 5) for Eq. 10's window variance; the method is also defined with that
+ * variance taken of the logarithmic image l the bins are cut from.  This call writes
  *   logv = ln(max(i, FLT_MIN))   (FP32, the device logf, within 2 ulp of the exact value)
  * (H x W, pitch ld_log; must not overlap lum) and, in the same pass, the statistics of l:
  * offsets[2] (device, nullable) = FP32-rounded means of l and l^2 (FP64 sums), the offsets a
@@ -193,9 +193,10 @@ tm_status tm_prologue_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rg
  * of i as usual, and tm_tonemap_forward (or _maps, _rgb) given i itself (its bins decide
  * Eq. 1) with the table and offsets of l; eps is then in units of l^2.  Its gradient:
  * tm_tonemap_forward_train given i with the table and offsets of l, then
- * tm_tonemap_backward_resid given logv as its image (the residual backward uses the image
- * only in the final dv = s1 + 2 v s2, so it returns the gradient with respect to l), then
- * tm_log_luminance_backward.  tm_tonemap_backward (from the tables) has no log form.
+ * tm_tonemap_backward_resid_log given i (or, in two steps, tm_tonemap_backward_resid given
+ * logv as its image, which returns the gradient with respect to l since the residual
+ * backward uses its image only in the final dv = s1 + 2 v s2, then
+ * tm_log_luminance_backward).  tm_tonemap_backward (from the tables) has no log form.
  * Deterministic.  Workspace: tm_image_stats_workspace_bytes. */
 tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t W, float *logv,
                            int64_t ld_log, float *offsets, float *minmax, void *ws,
@@ -371,6 +372,20 @@ tm_status tm_tonemap_backward_resid(const float *v, int64_t ld_v, int32_t H, int
                                     const float *grad_out, int64_t ld_g, float *grad_v,
                                     int64_t ld_gv, double *grad_params, void *ws,
                                     size_t ws_bytes, void *stream);
+
+/* The same residual backward for the log-domain variance variant (tm_log_luminance), given
+ * the image i itself: the last scan pass forms l = ln max(i, FLT_MIN) with the expression
+ * tm_log_luminance uses and writes the gradient with respect to i,
+ *   grad_lum = (s1 + 2 l s2) / i  where i > FLT_MIN,  0 where the floor constant is taken,
+ * which equals tm_tonemap_backward_resid given logv followed by tm_log_luminance_backward
+ * bit for bit, without the log plane and without the extra pass.  resid from
+ * tm_tonemap_forward_train given i with l's table and offsets; other arguments, workspace
+ * (tm_backward_resid_workspace_bytes) and errors as for tm_tonemap_backward_resid. */
+tm_status tm_tonemap_backward_resid_log(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                                        const tm_params *p, const float *resid,
+                                        const float *grad_out, int64_t ld_g, float *grad_lum,
+                                        int64_t ld_gl, double *grad_params, void *ws,
+                                        size_t ws_bytes, void *stream);
 
 
 /* Gradient of sum_p g(p) L(p) (g = grad_out) with respect to v and to (eps, ld_min,

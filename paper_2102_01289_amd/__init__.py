@@ -21,6 +21,7 @@ __all__ = [
     "tm_integral_histogram", "tm_integral_tables", "tm_integral_tables_split",
     "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
+    "tm_tonemap_backward_resid_log",
     "residual_planes", "residual_pairs", "ToneMapper", "tonemap", "Batch",
     "tm_tonemap_forward_rgb", "tonemap_rgb", "tm_tonemap_forward_maps", "tm_prologue_noalloc",
 ]
@@ -542,6 +543,26 @@ def tm_tonemap_backward_resid(v, params, resid, grad_out, stream=None, ws=None, 
     return gv, gp
 
 
+def tm_tonemap_backward_resid_log(lum, params, resid, grad_out, stream=None, ws=None,
+                                  out=None):
+    """Log-domain variant's gradient from residual planes, given the image i itself (the
+    chain rule through l = ln max(i, FLT_MIN) is applied in the last scan pass):
+    (grad_lum [H, W] float32, grad_params [3] float64)."""
+    H, W, ld = _img(lum, "lum")
+    _, _, ldg = _img(grad_out, "grad_out")
+    if out is None:
+        out = (torch.empty((H, W), dtype=torch.float32, device=lum.device),
+               torch.empty(3, dtype=torch.float64, device=lum.device))
+    gv, gp = out
+    if ws is None:
+        ws = _ws(_lib().tm_backward_resid_workspace_bytes(H, W, ctypes.byref(params)),
+                 lum.device)
+    _ck("tm_tonemap_backward_resid_log", _lib().tm_tonemap_backward_resid_log(
+        _vp(lum), ld, H, W, ctypes.byref(params), _vp(resid), _vp(grad_out), ldg, _vp(gv),
+        gv.stride(0), _vp(gp), _vp(ws), ws.numel(), _stream(stream)))
+    return gv, gp
+
+
 def tm_tonemap_backward(v, sat: Table, hist: Table | None, edges, params, grad_out,
                         offsets=None, stream=None):
     """(grad_v [H, W] float32, grad_params [3] float64 = d/d(eps, ld_min, ld_max))."""
@@ -709,18 +730,16 @@ class ToneMapper:
 
     def backward_resid(self, grad_out: torch.Tensor, stream=None):
         """Adjoint from the residual planes of the last run_train: (grad_lum, grad_params).
-        variance="log": the residual backward given the log plane returns the gradient with
-        respect to l, which the chain rule through the logarithm turns into that w.r.t. lum."""
+        variance="log": the residual backward forms l from lum in its last pass and applies
+        the chain rule through the logarithm there, returning the gradient w.r.t. lum."""
         self._bwd_buffers()
         if not hasattr(self, "ws_bwd_resid"):
             self.ws_bwd_resid = _ws(_lib().tm_backward_resid_workspace_bytes(
                 self.H, self.W, ctypes.byref(self.params)), self.lum.device)
-        log = self.variance == "log"
-        tm_tonemap_backward_resid(self.logv if log else self.lum, self.params, self.resid,
-                                  grad_out, stream, self.ws_bwd_resid,
-                                  (self.grad_v, self.grad_params))
-        if log:
-            tm_log_luminance_backward(self.lum, self.grad_v, self.grad_v, stream)
+        bwd = (tm_tonemap_backward_resid_log if self.variance == "log"
+               else tm_tonemap_backward_resid)
+        bwd(self.lum, self.params, self.resid, grad_out, stream, self.ws_bwd_resid,
+            (self.grad_v, self.grad_params))
         return self.grad_v, self.grad_params
 
     def backward(self, grad_out: torch.Tensor, stream=None):

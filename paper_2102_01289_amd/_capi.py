@@ -90,6 +90,8 @@ SIGNATURES = {
     "tm_backward_resid_workspace_bytes": (SZ, [I32, I32, PP]),
     "tm_tonemap_backward_resid": (ctypes.c_int, [P, I64, I32, I32, PP, P, P, I64, P, I64, P, P,
                                                  SZ, P]),
+    "tm_tonemap_backward_resid_log": (ctypes.c_int, [P, I64, I32, I32, PP, P, P, I64, P, I64,
+                                                     P, P, SZ, P]),
     "tm_batch_workspace_bytes": (SZ, [ctypes.POINTER(TmImageDesc), I32, PP, ctypes.c_int, PT]),
     "tm_batch_create": (ctypes.c_int, [ctypes.POINTER(TmImageDesc), I32, PP, ctypes.c_int, PT, P,
                                        SZ, P, ctypes.POINTER(P)]),

@@ -13,18 +13,18 @@ The three scalars reach the kernels through device memory (tm_params.scalars), s
 pass synchronises with the host and both can be recorded into a CUDA/HIP graph.
 
 variance="log": Eq. 10's variance is that of l = ln(max(lum, FLT_MIN)) (the bins still come
-from lum).  The residual backward given l returns the gradient with respect to l, and the
-chain rule through the logarithm (tm_log_luminance_backward) gives that w.r.t. lum.  With
-recompute=True the backward rebuilds the log plane and the tables and reruns the training
-query for the residual planes.
+from lum).  The residual backward given lum forms l in its last pass and applies the chain
+rule through the logarithm there (tm_tonemap_backward_resid_log).  With recompute=True the
+backward rebuilds the log plane and the tables and reruns the training query for the
+residual planes.
 """
 from __future__ import annotations
 
 import torch
 
 from . import (make_params, tm_image_stats, tm_integral_image, tm_integral_tables_split,
-               tm_integral_tables, tm_log_luminance, tm_log_luminance_backward,
-               tm_tonemap_backward, tm_tonemap_backward_resid, tm_tonemap_forward,
+               tm_integral_tables, tm_log_luminance, tm_tonemap_backward,
+               tm_tonemap_backward_resid, tm_tonemap_backward_resid_log, tm_tonemap_forward,
                tm_tonemap_forward_train)
 
 __all__ = ["TonemapFn", "tonemap_luminance"]
@@ -73,13 +73,12 @@ class TonemapFn(torch.autograd.Function):
         p, prec, n_bins, sdt, log = ctx.meta
         g = g.contiguous().float()
         if log:
-            l, loff, sat, hist = _log_tables(lum, prec, edges, n_bins)
+            _, loff, sat, hist = _log_tables(lum, prec, edges, n_bins)
             resid = ctx.resid
             if resid is None:
                 _, resid = tm_tonemap_forward_train(lum, sat, hist, edges, p, loff)
             del sat, hist
-            gv, gp = tm_tonemap_backward_resid(l, p, resid, g)
-            tm_log_luminance_backward(lum, gv, gv)
+            gv, gp = tm_tonemap_backward_resid_log(lum, p, resid, g)
             ctx.resid = None
         elif ctx.resid is None:
             sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")

@@ -554,7 +554,7 @@ hipError_t launch_backward_resid(const BwdResidArgs &a, const BwdPlan &plan, voi
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_suffix_adjoint(k.Dr, a.W, a.v, a.ld_v, a.H, a.W, a.grad_v, a.ld_gv,
-                                 plan.scan_plan, w + plan.scan, s);
+                                 plan.scan_plan, w + plan.scan, s, a.log_chain);
 }
 
 }  // namespace tmo

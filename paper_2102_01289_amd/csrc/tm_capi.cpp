@@ -646,7 +646,7 @@ static tm_status run_backward_resid(const float *v, int64_t ld_v, int32_t H, int
                                     const tm_params *p, const float *resid,
                                     const float *grad_out, int64_t ld_g, float *grad_v,
                                     int64_t ld_gv, double *grad_params, const BwdPlan &plan,
-                                    void *ws, hipStream_t s) {
+                                    void *ws, hipStream_t s, bool log_chain = false) {
     BwdResidArgs a{};
     a.v = v;
     a.ld_v = ld_v;
@@ -659,6 +659,7 @@ static tm_status run_backward_resid(const float *v, int64_t ld_v, int32_t H, int
     a.grad_v = grad_v;
     a.ld_gv = ld_gv;
     a.grad_params = grad_params;
+    a.log_chain = log_chain;
     return from_hip(launch_backward_resid(a, plan, ws, s));
 }
 
@@ -687,6 +688,20 @@ tm_status tm_tonemap_backward_resid(const float *v, int64_t ld_v, int32_t H, int
     TM_TRY(check_ws(ws, ws_bytes, plan.total));
     return run_backward_resid(v, ld_v, H, W, p, resid, grad_out, ld_g, grad_v, ld_gv,
                               grad_params, plan, ws, (hipStream_t)stream);
+}
+
+tm_status tm_tonemap_backward_resid_log(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                                        const tm_params *p, const float *resid,
+                                        const float *grad_out, int64_t ld_g, float *grad_lum,
+                                        int64_t ld_gl, double *grad_params, void *ws,
+                                        size_t ws_bytes, void *stream) {
+    TM_TRY(check_bwd_common(lum, ld_lum, H, W, p, grad_out, ld_g, grad_lum, ld_gl, grad_params));
+    if (!resid) return TM_ERR_ARG;
+    if (!aligned(resid, 8)) return TM_ERR_ALIGN;
+    BwdPlan plan = make_bwd_plan(H, W, p->n_scales, to_query(p, H, W).ry, false);
+    TM_TRY(check_ws(ws, ws_bytes, plan.total));
+    return run_backward_resid(lum, ld_lum, H, W, p, resid, grad_out, ld_g, grad_lum, ld_gl,
+                              grad_params, plan, ws, (hipStream_t)stream, true);
 }
 
 tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W,

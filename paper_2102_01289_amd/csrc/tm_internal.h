@@ -116,6 +116,10 @@ struct ScanK {
     int64_t ld_d;
     float *gv;
     int64_t ld_gv;
+    // adjoint mode, log-domain variant: v is the image i whose log plane l = ln max(i,
+    // FLT_MIN) the moments were taken of; the pass forms l itself and writes the gradient
+    // with respect to i, (s1 + 2 l s2) / i, or 0 where the floor constant is taken
+    int log_chain;
 };
 
 struct ScanArgs {
@@ -239,7 +243,7 @@ hipError_t launch_forward(const float *v, int64_t ld_v, int H, int W, const void
 // dv = s1 + 2 v s2 in forward order: the suffix sums of the backward.
 hipError_t launch_suffix_adjoint(const double2 *d, int64_t ld_d, const float *v, int64_t ld_v,
                                  int H, int W, float *gv, int64_t ld_gv, const ScanPlan &plan,
-                                 void *ws, hipStream_t s);
+                                 void *ws, hipStream_t s, bool log_chain = false);
 
 // ---------------------------------------------------------------- backward (a5)
 struct BwdResidArgs {
@@ -253,6 +257,7 @@ struct BwdResidArgs {
     float *grad_v;
     int64_t ld_gv;
     double *grad_params;
+    bool log_chain;          // v is the image i of the log-domain variant (see ScanK)
 };
 struct BwdPlan {
     int64_t nblocks;

@@ -17,6 +17,9 @@
 // aggregates are 1/th and 1/(64 VEC) of the image.  Histogram counts are exact uint32; the
 // integral image accumulates in the precision's own arithmetic (FP32, compensated FP32
 // pairs, or FP64), in a fixed order, so results are bit-reproducible.
+#include <float.h>
+#include <math.h>
+
 #include "tm_device.h"
 #include "tm_internal.h"
 
@@ -730,6 +733,17 @@ __device__ __forceinline__ void stage2_item(const ScanK &k, int64_t idx) {
 }
 
 // ================================================================ stage 3
+// Adjoint output of one pixel from its suffix sums s1, s2: dv = s1 + 2 v s2.  In the
+// log-domain variant v is the image i, the moments were those of l = ln max(i, FLT_MIN) (the
+// same expression as the log pass), so the gradient w.r.t. l is s1 + 2 l s2 and the chain
+// rule gives (s1 + 2 l s2) / i, or 0 where the floor constant is taken.
+__device__ __forceinline__ float adj_grad(const ScanK &k, float v, double s1, double s2) {
+    if (!k.log_chain) return (float)(s1 + 2.0 * (double)v * s2);
+    const float l = logf(fmaxf(v, FLT_MIN));
+    const float gl = (float)(s1 + 2.0 * (double)l * s2);
+    return v > FLT_MIN ? gl / v : 0.f;
+}
+
 // Column carries at the top of the tile for the lane's VEC columns, for every quantity of
 // the pass:  sum_{ty'<ty} TTE[ty'][tx] + inclusive prefix over the tile of CSE[ty][.].
 // All loads are issued before the first sum (one memory round trip per 256 tile rows above,
@@ -930,8 +944,7 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile, int 
                             // staged so that each store covers 64 consecutive outputs
                             float *sv = reinterpret_cast<float *>(sh_adj + wave_id() * (kWave * VEC));
 #pragma unroll
-                            for (int i = 0; i < VEC; ++i)
-                                sv[lane * VEC + i] = (float)(c1[i] + 2.0 * (double)cur.v[i] * c2[i]);
+                            for (int i = 0; i < VEC; ++i) sv[lane * VEC + i] = adj_grad(k, cur.v[i], c1[i], c2[i]);
                             wave_lds_sync();
 #pragma unroll
                             for (int i = 0; i < VEC; ++i)
@@ -941,7 +954,7 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile, int 
 #pragma unroll
                             for (int i = 0; i < VEC; ++i) {
                                 const int xo = k.W - 1 - (xl + i);
-                                if (xo >= 0) gr[xo] = (float)(c1[i] + 2.0 * (double)cur.v[i] * c2[i]);
+                                if (xo >= 0) gr[xo] = adj_grad(k, cur.v[i], c1[i], c2[i]);
                             }
                         }
                     } else {
@@ -1347,7 +1360,7 @@ hipError_t launch_tables(const ScanArgs &a, const ScanPlan &plan, void *ws, hipS
 
 hipError_t launch_suffix_adjoint(const double2 *d, int64_t ld_d, const float *v, int64_t ld_v,
                                  int H, int W, float *gv, int64_t ld_gv, const ScanPlan &plan,
-                                 void *ws, hipStream_t s) {
+                                 void *ws, hipStream_t s, bool log_chain) {
     ScanK k{};
     char *w = static_cast<char *>(ws);
     k.v = v;
@@ -1370,6 +1383,7 @@ hipError_t launch_suffix_adjoint(const double2 *d, int64_t ld_d, const float *v,
     k.ld_d = ld_d;
     k.gv = gv;
     k.ld_gv = ld_gv;
+    k.log_chain = log_chain ? 1 : 0;
     switch (plan.vec) {
         case 2: return run3<kF64, 2, 2, true, false, true>(k, s);
         case 4: return run3<kF64, 4, 2, true, false, true>(k, s);

@@ -325,3 +325,20 @@ def test_split_tables_argument_checks():
     assert call(a, 10, a, 10, a, None) == -1
     assert call(a, 10, a, 9, a, a) == -2          # histogram plane's pitch below W
     assert call(a, 9, a, 10, a, a) == -2
+
+
+def test_log_residual_backward_argument_checks():
+    # the fused log-domain residual backward checks its arguments like the plain one
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    a = P(1 << 20)
+    prm = tm.make_params(5, 2, [1, 2], [1, 2], 0.1)
+    pr = ctypes.byref(prm)
+    assert lib.tm_tonemap_backward_resid_log(None, 64, 8, 8, pr, a, a, 64, a, 64, a, a, 1 << 20,
+                                             None) == -1
+    assert lib.tm_tonemap_backward_resid_log(a, 64, 8, 8, pr, None, a, 64, a, 64, a, a, 1 << 20,
+                                             None) == -1
+    assert lib.tm_tonemap_backward_resid_log(a, 64, 8, 8, pr, P((1 << 20) + 4), a, 64, a, 64, a,
+                                             a, 1 << 20, None) == -3
+    assert lib.tm_tonemap_backward_resid_log(a, 4, 8, 8, pr, a, a, 64, a, 64, a, a, 1 << 20,
+                                             None) == -2

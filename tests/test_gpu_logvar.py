@@ -244,7 +244,13 @@ def _check_log_backward(rgb, n, rx, ry, eps, prec, seed, ld=(0.0, 1.0)):
     assert torch.equal(L_plain, L_train)       # the training form writes the same L
     g = np.random.default_rng(seed).standard_normal((H, W)).astype(np.float32)
     gv, gp = m.backward_resid(to_dev(g))
+    gv, gp = gv.clone(), gp.clone()
+    # the fused chain rule equals the two-step form (residual backward given the log plane,
+    # then the chain-rule pass) bit for bit
+    gl, gp2 = tm.tm_tonemap_backward_resid(m.logv, p, m.resid, to_dev(g))
+    tm.tm_log_luminance_backward(m.lum, gl, gl)
     torch.cuda.synchronize()
+    assert torch.equal(gv, gl) and torch.equal(gp, gp2)
     gv = gv.cpu().numpy().astype(np.float64)
     gp = gp.cpu().numpy()
     lum = lum_ref(rgb)
@@ -298,6 +304,25 @@ def test_log_backward_radii_clamping_and_floor(rx, ry):
     rgb = rgb_case(60, 80, 5, -3.0, 5.0, seed=len(rx) + 30)
     rgb[:, 7, 9] = 0.0                   # a black pixel: l is the floor, its gradient 0
     _check_log_backward(rgb, 5, rx, ry, 0.05, "c32x2", seed=5, ld=(0.2, 0.8))
+
+
+@pytest.mark.parametrize("H,W,s", [(1, 1, 1), (3, 700, 2), (1080, 1920, 5), (3000, 4000, 5)])
+def test_log_backward_fused_chain_rule_equals_the_two_steps(H, W, s):
+    # ragged, tiny and full-size shapes (the adjoint tiling changes with the shape), pixels at
+    # and around the floor: the fused pass equals residual backward given l + chain rule
+    rgb = rgb_case(H, W, 5, -3.0, 5.0, seed=H + 3 * W)
+    rgb[:, 0, :min(W, 6)] = np.float32([0.0, 1e-40, 1.1754944e-38, 2.4e-38, 1.0, 5.0])[:min(W, 6)]
+    rx, ry = oracle.paper_radii(H, W, s)
+    p = tm.make_params(5, s, rx, ry, 0.05)
+    m = tm.ToneMapper(H, W, p, "c32x2", variance="log")
+    m.run_train(to_dev(rgb))
+    g = to_dev(np.random.default_rng(W).standard_normal((H, W)).astype(np.float32))
+    gv, gp = (t.clone() for t in m.backward_resid(g))
+    gl, gp2 = tm.tm_tonemap_backward_resid(m.logv, p, m.resid, g)
+    tm.tm_log_luminance_backward(m.lum, gl, gl)
+    torch.cuda.synchronize()
+    assert torch.equal(gv, gl) and torch.equal(gp, gp2)
+    assert torch.all(gv[m.lum <= FLT_MIN] == 0)
 
 
 def test_log_backward_paper_set_256():
