@@ -202,6 +202,18 @@ tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t 
                            int64_t ld_log, float *offsets, float *minmax, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* tm_prologue and tm_log_luminance in one pass over the colour planes: lum (Eq. 11), edges
+ * and minmax of lum exactly as tm_prologue writes them, and logv and log_offsets (means of l
+ * and l^2) exactly as tm_log_luminance of that lum writes its plane and offsets, bit for bit.
+ * The log plane's range and the luminance's offsets are not produced.  lum and logv must be
+ * disjoint (else TM_ERR_ARG); other arguments and errors as for tm_prologue.  Workspace:
+ * tm_image_stats_workspace_bytes.  The log-domain variant's forward is then
+ * tm_integral_tables_split (l, lum) and the fused query. */
+tm_status tm_prologue_log(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                          int32_t W, int32_t n_bins, float *lum, int64_t ld_lum, float *logv,
+                          int64_t ld_log, float *edges, float *log_offsets, float *minmax,
+                          void *ws, size_t ws_bytes, void *stream);
+
 /* The chain rule through l = ln(max(i, FLT_MIN)) for the log-domain variant's gradient:
  *   grad_i = grad_l / i   where i > FLT_MIN,   0 where the floor constant is taken
  * (FP32, one correctly rounded division per pixel).  lum is the image i given to

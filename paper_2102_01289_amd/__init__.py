@@ -17,7 +17,7 @@ from . import _capi
 __all__ = [
     "TmError", "Table", "table_geometry", "paper_radii", "make_params", "tune", "default_tune",
     "image_tune", "tm_integral_histogram_lookback", "tm_log_luminance_backward",
-    "tm_luminance", "tm_image_stats", "tm_prologue", "tm_integral_image",
+    "tm_luminance", "tm_image_stats", "tm_prologue", "tm_prologue_log", "tm_integral_image",
     "tm_integral_histogram", "tm_integral_tables", "tm_integral_tables_split",
     "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
@@ -294,6 +294,25 @@ def tm_prologue(rgb: torch.Tensor, n_bins: int, stream=None):
                                           _vp(lum), lum.stride(0), _vp(edges), _vp(offsets),
                                           _vp(minmax), _vp(ws), ws.numel(), _stream(stream)))
     return lum, edges[:n_bins - 1], offsets, minmax
+
+
+def tm_prologue_log(rgb: torch.Tensor, n_bins: int, stream=None):
+    """Log-domain variant's prologue in one pass: (lum, logv, edges, log_offsets, minmax),
+    equal to tm_prologue's lum, edges, minmax and tm_log_luminance's plane and offsets."""
+    _check_rgb(rgb)
+    _, H, W = rgb.shape
+    dev = rgb.device
+    lum = torch.empty((H, W), dtype=torch.float32, device=dev)
+    logv = torch.empty((H, W), dtype=torch.float32, device=dev)
+    edges = torch.empty(max(n_bins - 1, 1), dtype=torch.float32, device=dev)
+    offsets = torch.empty(2, dtype=torch.float32, device=dev)
+    minmax = torch.empty(2, dtype=torch.float32, device=dev)
+    ws = _ws(_lib().tm_image_stats_workspace_bytes(H, W), dev)
+    _ck("tm_prologue_log", _lib().tm_prologue_log(
+        _vp(rgb), rgb.stride(0), rgb.stride(1), H, W, n_bins, _vp(lum), lum.stride(0),
+        _vp(logv), logv.stride(0), _vp(edges), _vp(offsets), _vp(minmax), _vp(ws), ws.numel(),
+        _stream(stream)))
+    return lum, logv, edges[:n_bins - 1], offsets, minmax
 
 
 def tm_prologue_noalloc(rgb: torch.Tensor, n_bins: int, lum=None, edges=None, offsets=None,
@@ -599,9 +618,9 @@ class ToneMapper:
     """Preallocated forward path for one image shape: prologue (Eq. 11 + statistics),
     integral tables (Eq. 5, 8), fused query (Eq. 1-4).  All buffers and workspaces are
     allocated once so that run() only enqueues kernels (capturable in a HIP graph).
-    variance="log": Eq. 10's window variance is that of the log image l = ln i (its
-    integral image is built from tm_log_luminance's plane; the bins still come from i);
-    forward only.
+    variance="log": Eq. 10's window variance is that of the log image l = ln i (the
+    prologue also writes l and its offsets, the tables pass scans l and bins i); run,
+    run_train and backward_resid (not the table-based backward).
     tune: a TmTune, None for the shape's default tiling, or "cached" for the tiling the
     autotuner stored for this device, shape bucket, bin count and precision
     (autotune.tune_image), falling back to the default when none is stored."""
@@ -635,10 +654,17 @@ class ToneMapper:
         if variance == "log":
             self.logv = torch.empty((H, W), dtype=torch.float32, device=dev)
             self.log_offsets = torch.empty(2, dtype=torch.float32, device=dev)
-            self.log_minmax = torch.empty(2, dtype=torch.float32, device=dev)
             self.sat_offsets = self.log_offsets
 
     def prologue(self, rgb, stream=None):
+        if self.variance == "log":
+            # luminance, its log plane, the bin edges and l's offsets in one pass
+            _ck("tm_prologue_log", _lib().tm_prologue_log(
+                _vp(rgb), rgb.stride(0), rgb.stride(1), self.H, self.W, self.params.n_bins,
+                _vp(self.lum), self.lum.stride(0), _vp(self.logv), self.logv.stride(0),
+                _vp(self.edges), _vp(self.log_offsets), _vp(self.minmax), _vp(self.ws_stats),
+                self.ws_stats.numel(), _stream(stream)))
+            return
         _ck("tm_prologue", _lib().tm_prologue(
             _vp(rgb), rgb.stride(0), rgb.stride(1), self.H, self.W, self.params.n_bins,
             _vp(self.lum), self.lum.stride(0), _vp(self.edges), _vp(self.offsets),
@@ -647,8 +673,7 @@ class ToneMapper:
     def tables(self, stream=None):
         h = self.hist
         if self.variance == "log":
-            tm_log_luminance(self.lum, stream, self.logv, self.log_offsets, self.log_minmax,
-                             self.ws_stats)
+            # the log plane and its offsets come from the prologue
             if h is None:
                 _ck("tm_integral_image", _lib().tm_integral_image(
                     _vp(self.logv), self.logv.stride(0), self.H, self.W,

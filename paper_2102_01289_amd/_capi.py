@@ -52,6 +52,8 @@ SIGNATURES = {
     "tm_image_stats_workspace_bytes": (SZ, [I32, I32]),
     "tm_image_stats": (ctypes.c_int, [P, I64, I32, I32, I32, P, P, P, P, SZ, P]),
     "tm_prologue": (ctypes.c_int, [P, I64, I64, I32, I32, I32, P, I64, P, P, P, P, SZ, P]),
+    "tm_prologue_log": (ctypes.c_int, [P, I64, I64, I32, I32, I32, P, I64, P, I64, P, P, P, P,
+                                       SZ, P]),
     "tm_prologue_noalloc": (ctypes.c_int, [P, I64, I64, I32, I32, I32, P, I64, P, P, P, P]),
     "tm_log_luminance": (ctypes.c_int, [P, I64, I32, I32, P, I64, P, P, P, SZ, P]),
     "tm_lookback_set_spin_limit": (None, [ctypes.c_uint32]),

@@ -222,6 +222,30 @@ tm_status tm_prologue_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rg
                                          edges, offsets, minmax, (hipStream_t)stream));
 }
 
+tm_status tm_prologue_log(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
+                          int32_t W, int32_t n_bins, float *lum, int64_t ld_lum, float *logv,
+                          int64_t ld_log, float *edges, float *log_offsets, float *minmax,
+                          void *ws, size_t ws_bytes, void *stream) {
+    TM_TRY(check_image(H, W));
+    if (!rgb || !lum || !logv || n_bins < 1 || n_bins > TM_MAX_BINS) return TM_ERR_ARG;
+    if (n_bins > 1 && !edges) return TM_ERR_ARG;
+    TM_TRY(check_plane(H, W, ld_rgb));
+    TM_TRY(check_plane(H, W, ld_lum));
+    TM_TRY(check_plane(H, W, ld_log));
+    if (ch_stride < (int64_t)H * ld_rgb) return TM_ERR_SHAPE;
+    {   // the two output planes must be disjoint
+        const char *a0 = reinterpret_cast<const char *>(lum);
+        const char *a1 = a0 + (((int64_t)H - 1) * ld_lum + W) * 4;
+        const char *b0 = reinterpret_cast<const char *>(logv);
+        const char *b1 = b0 + (((int64_t)H - 1) * ld_log + W) * 4;
+        if (a0 < b1 && b0 < a1) return TM_ERR_ARG;
+    }
+    TM_TRY(check_ws(ws, ws_bytes, tm_image_stats_workspace_bytes(H, W)));
+    return from_hip(launch_stats_log(rgb, ch_stride, ld_rgb, lum, ld_lum, logv, ld_log, H, W,
+                                     n_bins, edges, log_offsets, minmax,
+                                     static_cast<StatsPartial *>(ws), (hipStream_t)stream));
+}
+
 tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t W, float *logv,
                            int64_t ld_log, float *offsets, float *minmax, void *ws,
                            size_t ws_bytes, void *stream) {

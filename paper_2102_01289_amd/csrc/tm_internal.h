@@ -24,6 +24,11 @@ struct StatsK {
     int H, W, vec_in, vec_out, nparts, n_bins;
     StatsPartial *partials;
     float *edges, *offsets, *minmax;
+    // colour input, log-domain variant: also write l = ln max(lum, FLT_MIN) here; the sums
+    // (offsets) are then those of l, the range (edges, minmax) still that of lum
+    float *log_out;
+    int64_t ld_log;
+    int vec_log;
 };
 constexpr int kStatsMaxBlocks = 1024;
 int stats_blocks(int H, int W);
@@ -43,6 +48,11 @@ hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, con
                         int n_bins, float *edges, float *offsets, float *minmax,
                         StatsPartial *partials, hipStream_t s);
 // logv = ln(max(lum, FLT_MIN)) and the statistics (offsets, minmax) of logv.
+// tm_prologue and tm_log_luminance in one pass over the colour planes (see StatsK::log_out).
+hipError_t launch_stats_log(const float *rgb, int64_t ch_stride, int64_t ld_rgb, float *lum,
+                            int64_t ld_lum, float *logv, int64_t ld_log, int H, int W, int n_bins,
+                            float *edges, float *offsets, float *minmax, StatsPartial *partials,
+                            hipStream_t s);
 hipError_t launch_log_stats(const float *lum, int64_t ld_lum, float *logv, int64_t ld_log, int H,
                             int W, float *offsets, float *minmax, StatsPartial *partials,
                             hipStream_t s);

@@ -40,6 +40,15 @@ __device__ __forceinline__ void stat_add(Stat &a, float v) {
     a.s2 += d * d;
 }
 
+// Range of v, sums of l (the log-domain variant's prologue).
+__device__ __forceinline__ void stat_add_split(Stat &a, float v, float l) {
+    a.mn = fminf(a.mn, v);
+    a.mx = fmaxf(a.mx, v);
+    double d = (double)l;
+    a.s1 += d;
+    a.s2 += d * d;
+}
+
 __device__ __forceinline__ Stat stat_merge(Stat a, Stat b) {
     return Stat{fminf(a.mn, b.mn), fmaxf(a.mx, b.mx), a.s1 + b.s1, a.s2 + b.s2};
 }
@@ -62,8 +71,9 @@ __device__ Stat block_reduce(Stat st) {
 
 // One reduction part of one image: row segments part, part + nparts, ... (so the partials,
 // and hence the statistics, do not depend on how parts are scheduled).
-// LOG (luminance input only): the pass writes l = ln(max(v, FLT_MIN)) to lum_out and the
-// statistics are those of l.
+// LOG, luminance input: the pass writes l = ln(max(v, FLT_MIN)) to lum_out and the
+// statistics are those of l.  LOG, colour input: the pass writes the luminance to lum_out and
+// l to log_out; the range is the luminance's, the sums are l's.
 template <bool FROM_RGB, bool STATS, bool LOG = false>
 __device__ void stats_part(const StatsK &k, int part, int nparts) {
     Stat st{INFINITY, -INFINITY, 0.0, 0.0};
@@ -100,6 +110,22 @@ __device__ void stats_part(const StatsK &k, int part, int nparts) {
             } else {
                 for (int i = 0; i < 4; ++i)
                     if (x + i < W) o[i] = v[i];
+            }
+            if (LOG) {
+                float l[4];
+                for (int i = 0; i < 4; ++i) l[i] = logf(fmaxf(v[i], FLT_MIN));
+                float *ol = k.log_out + (int64_t)y * k.ld_log + x;
+                if (full && k.vec_log) {
+                    *reinterpret_cast<float4 *>(ol) = make_float4(l[0], l[1], l[2], l[3]);
+                } else {
+                    for (int i = 0; i < 4; ++i)
+                        if (x + i < W) ol[i] = l[i];
+                }
+                if (STATS) {
+                    for (int i = 0; i < 4; ++i)
+                        if (x + i < W) stat_add_split(st, v[i], l[i]);
+                }
+                continue;
             }
         } else {
             const float *L = k.lum_in + (int64_t)y * k.ld_in + x;
@@ -346,6 +372,23 @@ hipError_t launch_stats(const float *rgb, int64_t ch_stride, int64_t ld_rgb, con
         hipLaunchKernelGGL((lum_stats_kernel<true, true>), dim3(k.nparts), dim3(kBlock), 0, s, k);
     else
         hipLaunchKernelGGL((lum_stats_kernel<false, true>), dim3(k.nparts), dim3(kBlock), 0, s, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_log(const float *rgb, int64_t ch_stride, int64_t ld_rgb, float *lum,
+                            int64_t ld_lum, float *logv, int64_t ld_log, int H, int W, int n_bins,
+                            float *edges, float *offsets, float *minmax, StatsPartial *partials,
+                            hipStream_t s) {
+    StatsK k = make_statsk(rgb, ch_stride, ld_rgb, nullptr, 0, lum, ld_lum, H, W, n_bins, edges,
+                           offsets, minmax, partials);
+    k.log_out = logv;
+    k.ld_log = ld_log;
+    k.vec_log = aligned16(logv) && ld_log % 4 == 0;
+    hipLaunchKernelGGL((lum_stats_kernel<true, true, true>), dim3(k.nparts), dim3(kBlock), 0, s,
+                       k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kBlock), 0, s, k);

@@ -342,3 +342,18 @@ def test_log_residual_backward_argument_checks():
                                              a, 1 << 20, None) == -3
     assert lib.tm_tonemap_backward_resid_log(a, 4, 8, 8, pr, a, a, 64, a, 64, a, a, 1 << 20,
                                              None) == -2
+
+
+def test_log_prologue_argument_checks():
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    a, b = P(1 << 20), P(1 << 24)
+    W = 8
+
+    def call(lum, logv, ld_log=64, n=5, edges=a):
+        return lib.tm_prologue_log(a, 64 * 8, 64, 8, W, n, lum, 64, logv, ld_log, edges, a, a, a,
+                                   1 << 20, None)
+    assert call(b, None) == -1                      # no log plane
+    assert call(b, P((1 << 24) + 64)) == -1         # log plane overlaps the luminance
+    assert call(b, a, n=5, edges=None) == -1        # edges needed for more than one bin
+    assert call(b, a, ld_log=4) == -2               # pitch below W

@@ -219,6 +219,24 @@ def test_split_tables_shape_mismatch_rejected():
                                     torch.zeros(4, device="cuda"), 5)
 
 
+@pytest.mark.parametrize("H,W,n", [(1, 1, 1), (37, 123, 5), (130, 1030, 9), (1080, 1920, 5),
+                                   (3000, 4000, 5)])
+def test_log_prologue_equals_prologue_then_log_pass(H, W, n):
+    # one pass over the colour planes gives the luminance, edges and range of tm_prologue and
+    # the log plane and offsets of tm_log_luminance, bit for bit (black and subnormal pixels
+    # included: they take the floor constant)
+    rgb = rgb_case(H, W, 5, -3.0, 5.0, seed=H + 5 * W)
+    rgb[:, 0, :min(W, 3)] = np.float32([0.0, 1e-40, 1.0])[:min(W, 3)]
+    d = to_dev(rgb)
+    lum, logv, edges, loff, mm = tm.tm_prologue_log(d, n)
+    lum1, edges1, _, mm1 = tm.tm_prologue(d, n)
+    logv1, loff1, _ = tm.tm_log_luminance(lum1)
+    torch.cuda.synchronize()
+    assert torch.equal(lum, lum1) and torch.equal(mm, mm1)
+    assert torch.equal(edges, edges1)
+    assert torch.equal(logv, logv1) and torch.equal(loff, loff1)
+
+
 def test_log_chain_rule_kernel():
     # grad_i = grad_l / i (one correctly rounded FP32 division) above the floor, 0 below;
     # in place too
