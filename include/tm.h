@@ -205,10 +205,11 @@ tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t 
 /* tm_prologue and tm_log_luminance in one pass over the colour planes: lum (Eq. 11), edges
  * and minmax of lum exactly as tm_prologue writes them, and logv and log_offsets (means of l
  * and l^2) exactly as tm_log_luminance of that lum writes its plane and offsets, bit for bit.
- * The log plane's range and the luminance's offsets are not produced.  lum and logv must be
- * disjoint (else TM_ERR_ARG); other arguments and errors as for tm_prologue.  Workspace:
- * tm_image_stats_workspace_bytes.  The log-domain variant's forward is then
- * tm_integral_tables_split (l, lum) and the fused query. */
+ * The log plane's range and the luminance's offsets are not produced.  logv may be NULL
+ * (then only its offsets are formed); else lum and logv must be disjoint (else TM_ERR_ARG).
+ * Other arguments and errors as for tm_prologue.  Workspace: tm_image_stats_workspace_bytes.
+ * The log-domain variant's forward is then tm_integral_tables_log of lum (which needs no
+ * log plane) and the fused query. */
 tm_status tm_prologue_log(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int32_t H,
                           int32_t W, int32_t n_bins, float *lum, int64_t ld_lum, float *logv,
                           int64_t ld_log, float *edges, float *log_offsets, float *minmax,
@@ -274,6 +275,20 @@ tm_status tm_integral_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
 
 size_t tm_tables_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_sat_prec prec,
                                  const tm_tune *tune);
+
+/* The log-domain variant's two tables from the image i alone: the integral images (Eq. 5)
+ * of l = ln max(i, FLT_MIN), formed as each pixel is read with tm_log_luminance's own
+ * expression, and the integral histogram (Eq. 7-8) of i's bins.  log_offsets as
+ * tm_log_luminance or tm_prologue_log write them (required for TM_SAT_C32X2).  Results equal
+ * tm_integral_tables_split of (tm_log_luminance's plane, i) bit for bit, without reading a
+ * log plane.  sat is required (else TM_ERR_ARG); hist may be NULL; other arguments,
+ * workspace and errors as for tm_integral_tables. */
+tm_status tm_integral_tables_log(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                                 tm_sat_prec prec, const float *log_offsets, void *sat,
+                                 int64_t ld_sat, const float *edges, int32_t n_bins,
+                                 tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,
+                                 int64_t plane_stride, const tm_tune *tune, void *ws,
+                                 size_t ws_bytes, void *stream);
 
 /* Both tables in one pass, each of its own plane of the same H x W: the integral images
  * (Eq. 5) of v_sat and the integral histogram (Eq. 7-8) of v_hist's bins under edges.  For

@@ -19,6 +19,7 @@ __all__ = [
     "image_tune", "tm_integral_histogram_lookback", "tm_log_luminance_backward",
     "tm_luminance", "tm_image_stats", "tm_prologue", "tm_prologue_log", "tm_integral_image",
     "tm_integral_histogram", "tm_integral_tables", "tm_integral_tables_split",
+    "tm_integral_tables_log",
     "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
     "tm_tonemap_backward_resid_log",
@@ -296,22 +297,23 @@ def tm_prologue(rgb: torch.Tensor, n_bins: int, stream=None):
     return lum, edges[:n_bins - 1], offsets, minmax
 
 
-def tm_prologue_log(rgb: torch.Tensor, n_bins: int, stream=None):
+def tm_prologue_log(rgb: torch.Tensor, n_bins: int, stream=None, write_log: bool = True):
     """Log-domain variant's prologue in one pass: (lum, logv, edges, log_offsets, minmax),
-    equal to tm_prologue's lum, edges, minmax and tm_log_luminance's plane and offsets."""
+    equal to tm_prologue's lum, edges, minmax and tm_log_luminance's plane and offsets
+    (logv is None when write_log is False: only its offsets are formed)."""
     _check_rgb(rgb)
     _, H, W = rgb.shape
     dev = rgb.device
     lum = torch.empty((H, W), dtype=torch.float32, device=dev)
-    logv = torch.empty((H, W), dtype=torch.float32, device=dev)
+    logv = torch.empty((H, W), dtype=torch.float32, device=dev) if write_log else None
     edges = torch.empty(max(n_bins - 1, 1), dtype=torch.float32, device=dev)
     offsets = torch.empty(2, dtype=torch.float32, device=dev)
     minmax = torch.empty(2, dtype=torch.float32, device=dev)
     ws = _ws(_lib().tm_image_stats_workspace_bytes(H, W), dev)
     _ck("tm_prologue_log", _lib().tm_prologue_log(
         _vp(rgb), rgb.stride(0), rgb.stride(1), H, W, n_bins, _vp(lum), lum.stride(0),
-        _vp(logv), logv.stride(0), _vp(edges), _vp(offsets), _vp(minmax), _vp(ws), ws.numel(),
-        _stream(stream)))
+        _vp(logv), logv.stride(0) if write_log else 0, _vp(edges), _vp(offsets), _vp(minmax),
+        _vp(ws), ws.numel(), _stream(stream)))
     return lum, logv, edges[:n_bins - 1], offsets, minmax
 
 
@@ -391,6 +393,29 @@ def tm_integral_tables_split(v_sat: torch.Tensor, v_hist: torch.Tensor, prec: st
         _vp(v_sat), ld, _vp(v_hist), ldh, H, W, pcode, _vp(offsets), _vp(sat.ptr), sat.ld,
         _vp(edges), n_bins, _capi.HIST_LAYOUT[layout], _vp(hist.ptr), hist.ld,
         hist.plane_stride, _tune_ref(tune), _vp(ws), ws.numel(), _stream(stream)))
+    return sat, hist
+
+
+def tm_integral_tables_log(lum: torch.Tensor, prec: str = "c32x2", log_offsets=None,
+                           edges=None, n_bins: int = 5, layout: str | None = "cumulative",
+                           tune=None, stream=None, sat: Table | None = None,
+                           hist: Table | None = None):
+    """The log-domain variant's tables from lum alone: integral image of
+    l = ln max(lum, FLT_MIN) (formed on load) and integral histogram of lum's bins (layout,
+    or None to skip).  Returns (sat, hist | None)."""
+    H, W, ld = _img(lum, "lum")
+    dev = lum.device
+    sat = sat if sat is not None else Table(H, W, prec, 1, dev)
+    if hist is None and layout is not None:
+        planes = n_bins if layout == "per_bin" else n_bins - 1
+        hist = Table(H, W, "u32", planes, dev) if planes > 0 else None
+    pcode = _capi.SAT_PREC[prec]
+    ws = _ws(_lib().tm_tables_workspace_bytes(H, W, n_bins, pcode, _tune_ref(tune)), dev)
+    _ck("tm_integral_tables_log", _lib().tm_integral_tables_log(
+        _vp(lum), ld, H, W, pcode, _vp(log_offsets), _vp(sat.ptr), sat.ld, _vp(edges), n_bins,
+        _capi.HIST_LAYOUT[layout or "cumulative"], _vp(hist.ptr if hist else None),
+        hist.ld if hist else 0, hist.plane_stride if hist else 0, _tune_ref(tune), _vp(ws),
+        ws.numel(), _stream(stream)))
     return sat, hist
 
 
@@ -619,8 +644,9 @@ class ToneMapper:
     integral tables (Eq. 5, 8), fused query (Eq. 1-4).  All buffers and workspaces are
     allocated once so that run() only enqueues kernels (capturable in a HIP graph).
     variance="log": Eq. 10's window variance is that of the log image l = ln i (the
-    prologue also writes l and its offsets, the tables pass scans l and bins i); run,
-    run_train and backward_resid (not the table-based backward).
+    prologue forms l's offsets, the tables pass scans l formed as it reads i and bins i, the
+    residual backward forms l the same way); run, run_train and backward_resid (not the
+    table-based backward).
     tune: a TmTune, None for the shape's default tiling, or "cached" for the tiling the
     autotuner stored for this device, shape bucket, bin count and precision
     (autotune.tune_image), falling back to the default when none is stored."""
@@ -652,17 +678,18 @@ class ToneMapper:
         # the integral image's offsets: those of the luminance, or of its log plane
         self.sat_offsets = self.offsets
         if variance == "log":
-            self.logv = torch.empty((H, W), dtype=torch.float32, device=dev)
+            # no log plane is kept: the prologue forms l's offsets, the tables pass and the
+            # backward form l from lum as they read it
             self.log_offsets = torch.empty(2, dtype=torch.float32, device=dev)
             self.sat_offsets = self.log_offsets
 
     def prologue(self, rgb, stream=None):
         if self.variance == "log":
-            # luminance, its log plane, the bin edges and l's offsets in one pass
+            # luminance, bin edges and l's offsets in one pass
             _ck("tm_prologue_log", _lib().tm_prologue_log(
                 _vp(rgb), rgb.stride(0), rgb.stride(1), self.H, self.W, self.params.n_bins,
-                _vp(self.lum), self.lum.stride(0), _vp(self.logv), self.logv.stride(0),
-                _vp(self.edges), _vp(self.log_offsets), _vp(self.minmax), _vp(self.ws_stats),
+                _vp(self.lum), self.lum.stride(0), None, 0, _vp(self.edges),
+                _vp(self.log_offsets), _vp(self.minmax), _vp(self.ws_stats),
                 self.ws_stats.numel(), _stream(stream)))
             return
         _ck("tm_prologue", _lib().tm_prologue(
@@ -673,21 +700,13 @@ class ToneMapper:
     def tables(self, stream=None):
         h = self.hist
         if self.variance == "log":
-            # the log plane and its offsets come from the prologue
-            if h is None:
-                _ck("tm_integral_image", _lib().tm_integral_image(
-                    _vp(self.logv), self.logv.stride(0), self.H, self.W,
-                    _capi.SAT_PREC[self.prec], _vp(self.log_offsets), _vp(self.sat.ptr),
-                    self.sat.ld, self.tune_ref, _vp(self.ws_tab), self.ws_tab.numel(),
-                    _stream(stream)))
-                return
-            # statistics of l and bins of i in one three-stage pass
-            _ck("tm_integral_tables_split", _lib().tm_integral_tables_split(
-                _vp(self.logv), self.logv.stride(0), _vp(self.lum), self.lum.stride(0), self.H,
-                self.W, _capi.SAT_PREC[self.prec], _vp(self.log_offsets), _vp(self.sat.ptr),
-                self.sat.ld, _vp(self.edges), self.params.n_bins, 1, _vp(h.ptr), h.ld,
-                h.plane_stride, self.tune_ref, _vp(self.ws_tab), self.ws_tab.numel(),
-                _stream(stream)))
+            # integral image of l (formed on load) and histogram of lum in one pass
+            _ck("tm_integral_tables_log", _lib().tm_integral_tables_log(
+                _vp(self.lum), self.lum.stride(0), self.H, self.W, _capi.SAT_PREC[self.prec],
+                _vp(self.log_offsets), _vp(self.sat.ptr), self.sat.ld, _vp(self.edges),
+                self.params.n_bins, 1, _vp(h.ptr if h else None), h.ld if h else 0,
+                h.plane_stride if h else 0, self.tune_ref, _vp(self.ws_tab),
+                self.ws_tab.numel(), _stream(stream)))
             return
         _ck("tm_integral_tables", _lib().tm_integral_tables(
             _vp(self.lum), self.lum.stride(0), self.H, self.W, _capi.SAT_PREC[self.prec],

@@ -71,6 +71,8 @@ SIGNATURES = {
     "tm_integral_tables_split": (ctypes.c_int, [P, I64, P, I64, I32, I32, ctypes.c_int, P, P,
                                                 I64, P, I32, ctypes.c_int, P, I64, I64, PT, P,
                                                 SZ, P]),
+    "tm_integral_tables_log": (ctypes.c_int, [P, I64, I32, I32, ctypes.c_int, P, P, I64, P,
+                                              I32, ctypes.c_int, P, I64, I64, PT, P, SZ, P]),
     "tm_tables_workspace_bytes": (SZ, [I32, I32, I32, ctypes.c_int, PT]),
     "tm_lookback_workspace_bytes": (SZ, [I32, I32, I32, ctypes.c_int]),
     "tm_integral_histogram_lookback": (ctypes.c_int, [P, I64, I32, I32, P, I32, ctypes.c_int, P,

@@ -22,10 +22,9 @@ from __future__ import annotations
 
 import torch
 
-from . import (make_params, tm_image_stats, tm_integral_image, tm_integral_tables_split,
-               tm_integral_tables, tm_log_luminance, tm_tonemap_backward,
-               tm_tonemap_backward_resid, tm_tonemap_backward_resid_log, tm_tonemap_forward,
-               tm_tonemap_forward_train)
+from . import (make_params, tm_image_stats, tm_integral_tables, tm_integral_tables_log,
+               tm_log_luminance, tm_tonemap_backward, tm_tonemap_backward_resid,
+               tm_tonemap_backward_resid_log, tm_tonemap_forward, tm_tonemap_forward_train)
 
 __all__ = ["TonemapFn", "tonemap_luminance"]
 
@@ -34,10 +33,8 @@ def _log_tables(lum, prec, edges, n_bins):
     """The log-domain variant's tables: integral image of l = ln(max(lum, FLT_MIN)) with its
     offsets, integral histogram of lum.  (l, loff, sat, hist)."""
     l, loff, _ = tm_log_luminance(lum)
-    if n_bins > 1:
-        sat, hist = tm_integral_tables_split(l, lum, prec, loff, edges, n_bins, "cumulative")
-    else:
-        sat, hist = tm_integral_image(l, prec, loff), None
+    sat, hist = tm_integral_tables_log(lum, prec, loff, edges, n_bins,
+                                       "cumulative" if n_bins > 1 else None)
     return l, loff, sat, hist
 
 

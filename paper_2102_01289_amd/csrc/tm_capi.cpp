@@ -227,13 +227,13 @@ tm_status tm_prologue_log(const float *rgb, int64_t ch_stride, int64_t ld_rgb, i
                           int64_t ld_log, float *edges, float *log_offsets, float *minmax,
                           void *ws, size_t ws_bytes, void *stream) {
     TM_TRY(check_image(H, W));
-    if (!rgb || !lum || !logv || n_bins < 1 || n_bins > TM_MAX_BINS) return TM_ERR_ARG;
+    if (!rgb || !lum || n_bins < 1 || n_bins > TM_MAX_BINS) return TM_ERR_ARG;
     if (n_bins > 1 && !edges) return TM_ERR_ARG;
     TM_TRY(check_plane(H, W, ld_rgb));
     TM_TRY(check_plane(H, W, ld_lum));
-    TM_TRY(check_plane(H, W, ld_log));
+    if (logv) TM_TRY(check_plane(H, W, ld_log));
     if (ch_stride < (int64_t)H * ld_rgb) return TM_ERR_SHAPE;
-    {   // the two output planes must be disjoint
+    if (logv) {   // the two output planes must be disjoint
         const char *a0 = reinterpret_cast<const char *>(lum);
         const char *a1 = a0 + (((int64_t)H - 1) * ld_lum + W) * 4;
         const char *b0 = reinterpret_cast<const char *>(logv);
@@ -332,13 +332,15 @@ size_t tm_tables_workspace_bytes(int32_t H, int32_t W, int32_t n_bins, tm_sat_pr
     return make_scan_plan(H, W, (int)prec, n_bins, t).total;
 }
 
-// v_hist: the plane the histogram bins (null: v)
+// v_hist: the plane the histogram bins (null: v); log_src: the integral image is of
+// ln max(v, FLT_MIN)
 static tm_status run_tables(const float *v, int64_t ld_v, const float *v_hist,
                             int64_t ld_v_hist, int32_t H, int32_t W, tm_sat_prec prec,
                             const float *offsets, void *sat, int64_t ld_sat,
                             const float *edges, int32_t n_bins, tm_hist_layout layout,
                             uint32_t *hist, int64_t ld_hist, int64_t plane_stride,
-                            const tm_tune *tune, void *ws, size_t ws_bytes, void *stream) {
+                            const tm_tune *tune, void *ws, size_t ws_bytes, void *stream,
+                            bool log_src = false) {
     TM_TRY(check_image(H, W));
     if (!v) return TM_ERR_ARG;
     TM_TRY(check_plane(H, W, ld_v));
@@ -372,6 +374,7 @@ static tm_status run_tables(const float *v, int64_t ld_v, const float *v_hist,
     a.ld_v = ld_v;
     a.v_hist = v_hist;
     a.ld_v_hist = ld_v_hist;
+    a.log_src = log_src ? 1 : 0;
     a.H = H;
     a.W = W;
     a.sat_prec = sp;
@@ -409,6 +412,18 @@ tm_status tm_integral_tables_split(const float *v_sat, int64_t ld_v_sat, const f
     return run_tables(v_sat, ld_v_sat, v_hist, ld_v_hist, H, W, prec, offsets, sat, ld_sat,
                       edges, n_bins, layout, hist, ld_hist, plane_stride, tune, ws, ws_bytes,
                       stream);
+}
+
+tm_status tm_integral_tables_log(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                                 tm_sat_prec prec, const float *log_offsets, void *sat,
+                                 int64_t ld_sat, const float *edges, int32_t n_bins,
+                                 tm_hist_layout layout, uint32_t *hist, int64_t ld_hist,
+                                 int64_t plane_stride, const tm_tune *tune, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    if (!sat) return TM_ERR_ARG;
+    return run_tables(lum, ld_lum, nullptr, 0, H, W, prec, log_offsets, sat, ld_sat, edges,
+                      n_bins, layout, hist, ld_hist, plane_stride, tune, ws, ws_bytes, stream,
+                      true);
 }
 
 tm_status tm_integral_image(const float *v, int64_t ld_v, int32_t H, int32_t W,

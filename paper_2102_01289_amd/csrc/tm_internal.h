@@ -108,6 +108,9 @@ struct ScanK {
     const float *vh;
     int64_t ld_vh;
     int vec_load_h;
+    // the integral image is of l = ln max(v, FLT_MIN), formed as each pixel is read (the
+    // log-domain variant; the histogram items still bin v)
+    int log_src;
     const float *offsets;
     void *sat;
     int64_t ld_sat;
@@ -137,6 +140,7 @@ struct ScanArgs {
     int64_t ld_v;
     const float *v_hist;     // plane the histogram bins; null: v
     int64_t ld_v_hist;
+    int log_src;             // integral image of ln max(v, FLT_MIN) (see ScanK)
     int H, W;
     int sat_prec;            // -1 none
     const float *offsets;    // C32X2

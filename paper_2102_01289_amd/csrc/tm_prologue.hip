@@ -73,7 +73,7 @@ __device__ Stat block_reduce(Stat st) {
 // and hence the statistics, do not depend on how parts are scheduled).
 // LOG, luminance input: the pass writes l = ln(max(v, FLT_MIN)) to lum_out and the
 // statistics are those of l.  LOG, colour input: the pass writes the luminance to lum_out and
-// l to log_out; the range is the luminance's, the sums are l's.
+// l to log_out (when given); the range is the luminance's, the sums are l's.
 template <bool FROM_RGB, bool STATS, bool LOG = false>
 __device__ void stats_part(const StatsK &k, int part, int nparts) {
     Stat st{INFINITY, -INFINITY, 0.0, 0.0};
@@ -114,12 +114,14 @@ __device__ void stats_part(const StatsK &k, int part, int nparts) {
             if (LOG) {
                 float l[4];
                 for (int i = 0; i < 4; ++i) l[i] = logf(fmaxf(v[i], FLT_MIN));
-                float *ol = k.log_out + (int64_t)y * k.ld_log + x;
-                if (full && k.vec_log) {
-                    *reinterpret_cast<float4 *>(ol) = make_float4(l[0], l[1], l[2], l[3]);
-                } else {
-                    for (int i = 0; i < 4; ++i)
-                        if (x + i < W) ol[i] = l[i];
+                if (k.log_out) {   // the plane is optional: the sums are always formed
+                    float *ol = k.log_out + (int64_t)y * k.ld_log + x;
+                    if (full && k.vec_log) {
+                        *reinterpret_cast<float4 *>(ol) = make_float4(l[0], l[1], l[2], l[3]);
+                    } else {
+                        for (int i = 0; i < 4; ++i)
+                            if (x + i < W) ol[i] = l[i];
+                    }
                 }
                 if (STATS) {
                     for (int i = 0; i < 4; ++i)

@@ -186,11 +186,18 @@ __device__ __forceinline__ void sat_terms(const ScanK &k, int xl, const RowIn<VE
             q2[i] = in.d[i].y;
         }
     } else {
+        float x[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) x[i] = in.v[i];
+        if (k.log_src) {   // the log plane's own expression
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) x[i] = logf(fmaxf(x[i], FLT_MIN));
+        }
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             const bool ok = xl + i < k.W;
-            q1[i] = ok ? A::of_v(in.v[i], mu1) : A::zero();
-            q2[i] = ok ? A::of_v2(in.v[i], mu2) : A::zero();
+            q1[i] = ok ? A::of_v(x[i], mu1) : A::zero();
+            q2[i] = ok ? A::of_v2(x[i], mu2) : A::zero();
         }
     }
 }
@@ -1308,6 +1315,7 @@ ScanK make_scank(const ScanArgs &a, const ScanPlan &plan, void *ws) {
     k.vh = a.v_hist ? a.v_hist : a.v;
     k.ld_vh = a.v_hist ? a.ld_v_hist : a.ld_v;
     k.vec_load_h = (((uintptr_t)k.vh & 15u) == 0) && (k.ld_vh % 4 == 0);
+    k.log_src = a.log_src;
     k.offsets = a.offsets;
     k.sat = a.sat;
     k.ld_sat = a.ld_sat;

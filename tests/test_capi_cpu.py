@@ -353,7 +353,20 @@ def test_log_prologue_argument_checks():
     def call(lum, logv, ld_log=64, n=5, edges=a):
         return lib.tm_prologue_log(a, 64 * 8, 64, 8, W, n, lum, 64, logv, ld_log, edges, a, a, a,
                                    1 << 20, None)
-    assert call(b, None) == -1                      # no log plane
+    assert call(None, a) == -1                      # no luminance plane
     assert call(b, P((1 << 24) + 64)) == -1         # log plane overlaps the luminance
     assert call(b, a, n=5, edges=None) == -1        # edges needed for more than one bin
     assert call(b, a, ld_log=4) == -2               # pitch below W
+
+
+def test_log_tables_argument_checks():
+    lib = _capi.load()
+    P = ctypes.c_void_p
+    a = P(1 << 20)
+    # no integral image, missing offsets for C32X2, pitch below W
+    assert lib.tm_integral_tables_log(a, 64, 8, 8, 1, a, None, 64, a, 5, 1, a, 64, 1 << 12, None,
+                                      a, 1 << 20, None) == -1
+    assert lib.tm_integral_tables_log(a, 64, 8, 8, 1, None, a, 64, a, 5, 1, a, 64, 1 << 12, None,
+                                      a, 1 << 20, None) == -1
+    assert lib.tm_integral_tables_log(a, 4, 8, 8, 1, a, a, 64, a, 5, 1, a, 64, 1 << 12, None,
+                                      a, 1 << 20, None) == -2

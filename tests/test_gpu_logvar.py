@@ -205,11 +205,35 @@ def test_split_tables_equal_the_two_single_builds(H, W, n, layout, prec):
     torch.cuda.synchronize()
     assert torch.equal(sat.raw_region(), sat1.raw_region())
     assert torch.equal(hist.raw_region(), hist1.raw_region())
+    # and from lum alone, l formed as each pixel is read
+    sat2 = tm.Table(H, W, prec, 1)
+    hist2 = tm.Table(H, W, "u32", n if layout == "per_bin" else n - 1)
+    fill_garbage(sat2)
+    fill_garbage(hist2)
+    tm.tm_integral_tables_log(lum_d, prec, loff, edges, n, layout, sat=sat2, hist=hist2)
+    torch.cuda.synchronize()
+    assert torch.equal(sat2.raw_region(), sat1.raw_region())
+    assert torch.equal(hist2.raw_region(), hist1.raw_region())
     G = hist.padded()[..., 0]
     if H * W <= 256 * 256:
         want = oracle.integral_histogram(oracle.bins(lum, e), n,
                                          cumulative=layout == "cumulative")
         assert np.array_equal(G.numpy().astype(np.uint64), want)
+
+
+@pytest.mark.parametrize("prec", ["f32", "c32x2", "f64"])
+def test_log_tables_without_histogram(prec):
+    # one bin: only the integral image of l (formed on load), equal to that of the log plane
+    H, W = 45, 333
+    lum = lum_ref(rgb_case(H, W, 5, -3.0, 5.0, seed=9))
+    lum[3, :4] = [0.0, 1e-40, 1.1754944e-38, 7.0]
+    d = to_dev(lum)
+    l, loff, _ = tm.tm_log_luminance(d)
+    sat, hist = tm.tm_integral_tables_log(d, prec, loff, None, 1, None)
+    assert hist is None
+    ref = tm.tm_integral_image(l, prec, loff)
+    torch.cuda.synchronize()
+    assert torch.equal(sat.raw_region(), ref.raw_region())
 
 
 def test_split_tables_shape_mismatch_rejected():
@@ -235,6 +259,11 @@ def test_log_prologue_equals_prologue_then_log_pass(H, W, n):
     assert torch.equal(lum, lum1) and torch.equal(mm, mm1)
     assert torch.equal(edges, edges1)
     assert torch.equal(logv, logv1) and torch.equal(loff, loff1)
+    # without the plane: the same offsets and luminance
+    lum2, none, edges2, loff2, _ = tm.tm_prologue_log(d, n, write_log=False)
+    torch.cuda.synchronize()
+    assert none is None
+    assert torch.equal(lum2, lum1) and torch.equal(edges2, edges1) and torch.equal(loff2, loff1)
 
 
 def test_log_chain_rule_kernel():
@@ -265,7 +294,8 @@ def _check_log_backward(rgb, n, rx, ry, eps, prec, seed, ld=(0.0, 1.0)):
     gv, gp = gv.clone(), gp.clone()
     # the fused chain rule equals the two-step form (residual backward given the log plane,
     # then the chain-rule pass) bit for bit
-    gl, gp2 = tm.tm_tonemap_backward_resid(m.logv, p, m.resid, to_dev(g))
+    gl, gp2 = tm.tm_tonemap_backward_resid(tm.tm_log_luminance(m.lum)[0], p, m.resid,
+                                           to_dev(g))
     tm.tm_log_luminance_backward(m.lum, gl, gl)
     torch.cuda.synchronize()
     assert torch.equal(gv, gl) and torch.equal(gp, gp2)
@@ -336,7 +366,7 @@ def test_log_backward_fused_chain_rule_equals_the_two_steps(H, W, s):
     m.run_train(to_dev(rgb))
     g = to_dev(np.random.default_rng(W).standard_normal((H, W)).astype(np.float32))
     gv, gp = (t.clone() for t in m.backward_resid(g))
-    gl, gp2 = tm.tm_tonemap_backward_resid(m.logv, p, m.resid, g)
+    gl, gp2 = tm.tm_tonemap_backward_resid(tm.tm_log_luminance(m.lum)[0], p, m.resid, g)
     tm.tm_log_luminance_backward(m.lum, gl, gl)
     torch.cuda.synchronize()
     assert torch.equal(gv, gl) and torch.equal(gp, gp2)
