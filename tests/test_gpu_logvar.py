@@ -236,6 +236,26 @@ def test_log_tables_without_histogram(prec):
     assert torch.equal(sat.raw_region(), ref.raw_region())
 
 
+@pytest.mark.parametrize("t", [(2, 4, 4), (4, 16, 2), (8, 32, 8), (8, 8, 2)])
+@pytest.mark.parametrize("prec", ["c32x2", "f64"])
+def test_log_tables_every_tiling(t, prec):
+    # every scan variant (columns per lane, tile height, planes per item) forms l on load
+    # exactly as the log pass does: equal to the tables of the stored plane and of i
+    H, W = 203, 1301
+    lum = lum_ref(rgb_case(H, W, 5, -3.0, 5.0, seed=sum(t)))
+    lum[5, :3] = [0.0, 1e-40, 1.1754944e-38]
+    d = to_dev(lum)
+    e = to_dev(edges_ref(lum, 9))
+    l, loff, _ = tm.tm_log_luminance(d)
+    tn = tm.tune(*t)
+    sat, hist = tm.tm_integral_tables_log(d, prec, loff, e, 9, "cumulative", tune=tn)
+    ref = tm.tm_integral_image(l, prec, loff, tune=tn)
+    href = tm.tm_integral_histogram(d, e, 9, "cumulative", tune=tn)
+    torch.cuda.synchronize()
+    assert torch.equal(sat.raw_region(), ref.raw_region())
+    assert torch.equal(hist.raw_region(), href.raw_region())
+
+
 def test_split_tables_shape_mismatch_rejected():
     a = torch.zeros((8, 8), device="cuda")
     with pytest.raises(ValueError):
