@@ -190,8 +190,10 @@ tm_status tm_prologue_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rg
  * offsets[2] (device, nullable) = FP32-rounded means of l and l^2 (FP64 sums), the offsets a
  * TM_SAT_C32X2 integral image of l needs, and minmax[2] (device, nullable) = {min l, max l}.
  * The variant is then: tm_integral_image of logv with these offsets, the integral histogram
- * of i as usual, and tm_tonemap_forward (or _maps, _rgb) given i itself (its bins decide
- * Eq. 1) with the table and offsets of l; eps is then in units of l^2.  Its gradient:
+ * of i as usual (or both from i alone: tm_integral_tables_log), and tm_tonemap_forward (or
+ * _maps, _rgb) given i itself (its bins decide Eq. 1) with the table and offsets of l; eps
+ * is then in units of l^2.  From colour input tm_prologue_log forms the offsets in the
+ * prologue's own pass, with no log plane needed.  Its gradient:
  * tm_tonemap_forward_train given i with the table and offsets of l, then
  * tm_tonemap_backward_resid_log given i (or, in two steps, tm_tonemap_backward_resid given
  * logv as its image, which returns the gradient with respect to l since the residual
