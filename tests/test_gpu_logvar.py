@@ -286,6 +286,34 @@ def test_log_prologue_equals_prologue_then_log_pass(H, W, n):
     assert torch.equal(lum2, lum1) and torch.equal(edges2, edges1) and torch.equal(loff2, loff1)
 
 
+@pytest.mark.parametrize("pad_lum,pad_log", [(3, 1), (0, 5), (2, 0)])
+def test_log_prologue_with_pitched_planes(pad_lum, pad_log):
+    # rows of the luminance and log planes that are not 16-byte aligned take the element
+    # stores; the results equal the contiguous call's
+    import ctypes
+    from paper_2102_01289_amd import _capi
+    H, W, n = 37, 517, 5
+    d = to_dev(rgb_case(H, W, 5, -3.0, 5.0, seed=pad_lum * 7 + pad_log))
+    lum, logv, edges, loff, mm = tm.tm_prologue_log(d, n)
+    lb = torch.full((H, W + pad_lum), -7.0, device="cuda")
+    gb = torch.full((H, W + pad_log), -7.0, device="cuda")
+    e2 = torch.empty(n - 1, device="cuda")
+    o2 = torch.empty(2, device="cuda")
+    m2 = torch.empty(2, device="cuda")
+    lib = _capi.load()
+    ws = torch.empty(max(int(lib.tm_image_stats_workspace_bytes(H, W)), 1), dtype=torch.uint8,
+                     device="cuda")
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = lib.tm_prologue_log(vp(d), d.stride(0), d.stride(1), H, W, n, vp(lb), lb.stride(0),
+                             vp(gb), gb.stride(0), vp(e2), vp(o2), vp(m2), vp(ws), ws.numel(),
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert st == 0
+    assert torch.equal(lb[:, :W], lum) and torch.equal(gb[:, :W], logv)
+    assert torch.all(lb[:, W:] == -7.0) and torch.all(gb[:, W:] == -7.0)   # padding untouched
+    assert torch.equal(e2, edges) and torch.equal(o2, loff) and torch.equal(m2, mm)
+
+
 def test_log_chain_rule_kernel():
     # grad_i = grad_l / i (one correctly rounded FP32 division) above the floor, 0 below;
     # in place too
