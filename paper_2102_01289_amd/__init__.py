@@ -862,6 +862,14 @@ class Batch:
         _ck("tm_batch_set_concurrency", _lib().tm_batch_set_concurrency(
             self.handle, int(streams), int(images_per_group)))
 
+    def set_variance(self, variance: str = "linear", stream=None):
+        """Variance domain of the following forwards ("linear" or "log", as ToneMapper's);
+        a graph captured before must be captured again."""
+        if variance not in VARIANCE_DOMAINS:
+            raise ValueError(f"variance must be one of {VARIANCE_DOMAINS}")
+        _ck("tm_batch_set_variance", _lib().tm_batch_set_variance(
+            self.handle, 1 if variance == "log" else 0, _stream(stream)))
+
     def forward(self, stream=None):
         _ck("tm_batch_forward", _lib().tm_batch_forward(self.handle, _stream(stream)))
         return self.outs

@@ -101,6 +101,7 @@ SIGNATURES = {
                                        SZ, P, ctypes.POINTER(P)]),
     "tm_batch_forward": (ctypes.c_int, [P, P]),
     "tm_batch_set_concurrency": (ctypes.c_int, [P, I32, I32]),
+    "tm_batch_set_variance": (ctypes.c_int, [P, I32, P]),
     "tm_batch_capture": (ctypes.c_int, [P, P]),
     "tm_batch_replay": (ctypes.c_int, [P, P]),
     "tm_batch_destroy": (ctypes.c_int, [P]),

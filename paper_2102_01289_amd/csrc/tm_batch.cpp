@@ -44,6 +44,7 @@ struct tm_batch {
     };
     std::vector<Group> groups;
     bool h32 = true;   // every image's histogram offsets fit the 32-bit query addressing
+    bool log = false;  // log-domain variance variant (tm_batch_set_variance)
     struct Bufs {
         float *lum, *edges, *offsets;
         int64_t ld_lum;
@@ -370,6 +371,22 @@ tm_status tm_batch_set_concurrency(tm_batch *b, int32_t streams, int32_t images_
     return TM_OK;
 }
 
+tm_status tm_batch_set_variance(tm_batch *b, int32_t log_domain, void *stream) {
+    if (!b || (log_domain != 0 && log_domain != 1)) return TM_ERR_ARG;
+    b->log = log_domain != 0;
+    for (ScanK &k : b->ck) k.log_src = log_domain;
+    // the scan descriptors on the device follow (the host vector outlives the copy)
+    if (hipMemcpyAsync(b->d_ck, b->ck.data(), sizeof(ScanK) * b->count, hipMemcpyHostToDevice,
+                       (hipStream_t)stream) != hipSuccess)
+        return TM_ERR_HIP;
+    // a graph captured before holds the other variant's prologue: it must be captured again
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    return TM_OK;
+}
+
 tm_status tm_batch_forward(tm_batch *b, void *stream) {
     if (!b) return TM_ERR_ARG;
     hipStream_t s0 = (hipStream_t)stream;
@@ -383,7 +400,8 @@ tm_status tm_batch_forward(tm_batch *b, void *stream) {
         const tm_batch::Group &g = b->groups[gi];
         hipStream_t s = fork ? b->streams[b->group_stream[gi]] : s0;
         const int n = g.i1 - g.i0;
-        hipError_t e = launch_stats_batch(b->d_sk + g.i0, b->d_parts + g.i0, n, g.g_stats, s);
+        hipError_t e =
+            launch_stats_batch(b->d_sk + g.i0, b->d_parts + g.i0, n, g.g_stats, s, b->log);
         if (e != hipSuccess) return TM_ERR_HIP;
         BatchScan bs{b->d_ck + g.i0, b->d_tiles + g.i0, b->d_items + g.i0, n, b->prec,
                      g.vec, b->tune.chunk, g.g_tiles, g.g_items};

@@ -38,7 +38,7 @@ StatsK make_statsk(const float *rgb, int64_t ch_stride, int64_t ld_rgb, const fl
 // Prologue of a batch: the parts of images [0, count) in one launch, then one finalize
 // block per image (device arrays ks[count], part_prefix[count+1]).
 hipError_t launch_stats_batch(const StatsK *ks, const int64_t *part_prefix, int count,
-                              unsigned grid, hipStream_t s);
+                              unsigned grid, hipStream_t s, bool log = false);
 
 hipError_t launch_luminance(const float *rgb, int64_t ch_stride, int64_t ld_rgb, int H, int W,
                             float *lum, int64_t ld_lum, hipStream_t s);

@@ -173,7 +173,9 @@ __global__ void __launch_bounds__(kBlock) lum_stats_kernel(StatsK k) {
 }
 
 // Batched prologue over images [0, count) of ks: item g in [prefix[0], prefix[count]) is part
-// (g - prefix[i]) of image i.
+// (g - prefix[i]) of image i.  LOG: the log-domain variant's statistics (range of the
+// luminance, sums of its log plane; no plane is written).
+template <bool LOG>
 __global__ void __launch_bounds__(kBlock) lum_stats_batch(const StatsK *__restrict__ ks,
                                                           const int64_t *__restrict__ prefix,
                                                           int count) {
@@ -182,7 +184,7 @@ __global__ void __launch_bounds__(kBlock) lum_stats_batch(const StatsK *__restri
     int i = g < total ? find_image(prefix, count, g) : 0;   // advances with g
     for (; g < total; g += gridDim.x) {
         while (g >= prefix[i + 1]) ++i;
-        stats_part<true, true>(ks[i], (int)(g - prefix[i]), ks[i].nparts);
+        stats_part<true, true, LOG>(ks[i], (int)(g - prefix[i]), ks[i].nparts);
         __syncthreads();
     }
 }
@@ -485,8 +487,13 @@ hipError_t launch_stats_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_
 }
 
 hipError_t launch_stats_batch(const StatsK *ks, const int64_t *part_prefix, int count,
-                              unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL(lum_stats_batch, dim3(grid), dim3(kBlock), 0, s, ks, part_prefix, count);
+                              unsigned grid, hipStream_t s, bool log) {
+    if (log)
+        hipLaunchKernelGGL(lum_stats_batch<true>, dim3(grid), dim3(kBlock), 0, s, ks,
+                           part_prefix, count);
+    else
+        hipLaunchKernelGGL(lum_stats_batch<false>, dim3(grid), dim3(kBlock), 0, s, ks,
+                           part_prefix, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned fg = (unsigned)(count < 4096 ? count : 4096);

@@ -370,3 +370,9 @@ def test_log_tables_argument_checks():
                                       a, 1 << 20, None) == -1
     assert lib.tm_integral_tables_log(a, 4, 8, 8, 1, a, a, 64, a, 5, 1, a, 64, 1 << 12, None,
                                       a, 1 << 20, None) == -2
+
+
+def test_batch_set_variance_argument_checks():
+    lib = _capi.load()
+    assert lib.tm_batch_set_variance(None, 0, None) == -1
+    assert lib.tm_batch_set_variance(None, 2, None) == -1

@@ -150,3 +150,40 @@ def test_batch_concurrency_arguments():
     for bad in ((0, 0), (9, 0), (2, -1)):
         with pytest.raises(tm.TmError):
             b.set_concurrency(*bad)
+
+
+@pytest.mark.parametrize("prec", ["c32x2", "f64"])
+@pytest.mark.parametrize("t", [(4, 16, 4), (2, 5, 2)])
+def test_batch_log_variance_equals_per_image(prec, t):
+    # the log-domain variant over a batch: every image equals ToneMapper(variance="log"),
+    # eagerly and from a graph captured after the switch; switching back restores the
+    # linear outputs
+    imgs = _images(seed=5)
+    imgs[0][:, 3, :4] = 0.0                       # black pixels take the floor constant
+    b = tm.Batch(imgs, 5, 5, prec=prec, tune=tm.tune(*t))
+    lin = [o.clone() for o in b.forward()]
+    b.set_variance("log")
+    outs = [o.clone() for o in b.forward()]
+    torch.cuda.synchronize()
+    for i, rgb in enumerate(imgs):
+        _, H, W = rgb.shape
+        p = tm.make_params(5, 5, eps=0.1, H=H, W=W)
+        ref = tm.ToneMapper(H, W, p, prec, tune=tm.tune(*t), variance="log").run(rgb)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], ref), i
+    assert any(not torch.equal(a, c) for a, c in zip(lin, outs))
+    s = torch.cuda.Stream()
+    b.capture(s)
+    for rep in range(3):
+        for o in b.outs:
+            o.zero_()
+        b.replay(s)
+        s.synchronize()
+        assert all(torch.equal(o, r) for o, r in zip(b.outs, outs)), rep
+        _ = torch.randn(4096, device="cuda").sum().item()
+    b.set_variance("linear")
+    with pytest.raises(tm.TmError):
+        b.replay(s)                               # the earlier graph was released
+    back = [o.clone() for o in b.forward()]
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, c) for a, c in zip(lin, back))
