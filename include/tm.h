@@ -198,7 +198,7 @@ tm_status tm_prologue_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rg
  * tm_tonemap_backward_resid_log given i (or, in two steps, tm_tonemap_backward_resid given
  * logv as its image, which returns the gradient with respect to l since the residual
  * backward uses its image only in the final dv = s1 + 2 v s2, then
- * tm_log_luminance_backward).  tm_tonemap_backward (from the tables) has no log form.
+ * tm_log_luminance_backward); from the tables, tm_tonemap_backward_log.
  * Deterministic.  Workspace: tm_image_stats_workspace_bytes. */
 tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t W, float *logv,
                            int64_t ld_log, float *offsets, float *minmax, void *ws,
@@ -436,6 +436,21 @@ tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W
                               const tm_params *p, const float *grad_out, int64_t ld_g,
                               float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
                               size_t ws_bytes, void *stream);
+
+/* The same table-based backward for the log-domain variance variant: lum is the image i,
+ * sat and log_offsets the integral image of l and its offsets (tm_integral_tables_log,
+ * tm_prologue_log), hist_cum and edges those of i.  The residual planes are rebuilt from
+ * these tables, then tm_tonemap_backward_resid_log gives the gradient with respect to i.
+ * Equal bit for bit to tm_tonemap_forward_train of the same tables followed by
+ * tm_tonemap_backward_resid_log.  Workspace, arguments and errors as for
+ * tm_tonemap_backward. */
+tm_status tm_tonemap_backward_log(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                                  const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                                  const float *log_offsets, const uint32_t *hist_cum,
+                                  int64_t ld_hist, int64_t plane_stride, const float *edges,
+                                  const tm_params *p, const float *grad_out, int64_t ld_g,
+                                  float *grad_lum, int64_t ld_gl, double *grad_params, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------- multi-exposure input */
 

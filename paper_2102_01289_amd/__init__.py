@@ -22,7 +22,7 @@ __all__ = [
     "tm_integral_tables_log",
     "tm_tonemap_forward",
     "tm_tonemap_backward", "tm_tonemap_forward_train", "tm_tonemap_backward_resid",
-    "tm_tonemap_backward_resid_log",
+    "tm_tonemap_backward_resid_log", "tm_tonemap_backward_log",
     "residual_planes", "residual_pairs", "ToneMapper", "tonemap", "Batch",
     "tm_tonemap_forward_rgb", "tonemap_rgb", "tm_tonemap_forward_maps", "tm_prologue_noalloc",
 ]
@@ -607,6 +607,23 @@ def tm_tonemap_backward_resid_log(lum, params, resid, grad_out, stream=None, ws=
     return gv, gp
 
 
+def tm_tonemap_backward_log(lum, sat: Table, hist: Table | None, edges, params, grad_out,
+                            log_offsets=None, stream=None):
+    """The log-domain variant's backward from its tables (integral image and offsets of l,
+    histogram of lum): (grad_lum [H, W] float32, grad_params [3] float64)."""
+    H, W, ld = _img(lum, "lum")
+    _, _, ldg = _img(grad_out, "grad_out")
+    gv = torch.empty((H, W), dtype=torch.float32, device=lum.device)
+    gp = torch.empty(3, dtype=torch.float64, device=lum.device)
+    ws = _ws(_lib().tm_backward_workspace_bytes(H, W, ctypes.byref(params)), lum.device)
+    _ck("tm_tonemap_backward_log", _lib().tm_tonemap_backward_log(
+        _vp(lum), ld, H, W, _vp(sat.ptr), sat.ld, _capi.SAT_PREC[sat.kind], _vp(log_offsets),
+        _vp(hist.ptr if hist else None), hist.ld if hist else 0,
+        hist.plane_stride if hist else 0, _vp(edges), ctypes.byref(params), _vp(grad_out), ldg,
+        _vp(gv), gv.stride(0), _vp(gp), _vp(ws), ws.numel(), _stream(stream)))
+    return gv, gp
+
+
 def tm_tonemap_backward(v, sat: Table, hist: Table | None, edges, params, grad_out,
                         offsets=None, stream=None):
     """(grad_v [H, W] float32, grad_params [3] float64 = d/d(eps, ld_min, ld_max))."""
@@ -746,11 +763,6 @@ class ToneMapper:
         self.tables(stream)
         return self.query_rgb(rgb, saturation, stream)
 
-    def _linear_only(self, what):
-        if self.variance != "linear":
-            raise ValueError(f"{what}: the log-domain variance variant's gradient comes from "
-                             "run_train and backward_resid")
-
     def query_train(self, stream=None):
         """Fused query that also writes the backward's residual planes (those of the log
         image's window statistics for variance="log")."""
@@ -788,7 +800,6 @@ class ToneMapper:
 
     def backward(self, grad_out: torch.Tensor, stream=None):
         """Adjoint of the last forward from its tables: (grad_lum, grad_params)."""
-        self._linear_only("backward")
         self._bwd_buffers()
         if not hasattr(self, "ws_bwd"):
             self.ws_bwd = _ws(_lib().tm_backward_workspace_bytes(self.H, self.W,
@@ -796,9 +807,11 @@ class ToneMapper:
                               self.lum.device)
         h = self.hist
         _, _, ldg = _img(grad_out, "grad_out")
-        _ck("tm_tonemap_backward", _lib().tm_tonemap_backward(
+        log = self.variance == "log"    # the tables and offsets of l, the chain rule to lum
+        name = "tm_tonemap_backward_log" if log else "tm_tonemap_backward"
+        _ck(name, getattr(_lib(), name)(
             _vp(self.lum), self.lum.stride(0), self.H, self.W, _vp(self.sat.ptr), self.sat.ld,
-            _capi.SAT_PREC[self.prec], _vp(self.offsets), _vp(h.ptr if h else None),
+            _capi.SAT_PREC[self.prec], _vp(self.sat_offsets), _vp(h.ptr if h else None),
             h.ld if h else 0, h.plane_stride if h else 0, _vp(self.edges),
             ctypes.byref(self.params), _vp(grad_out), ldg, _vp(self.grad_v),
             self.grad_v.stride(0), _vp(self.grad_params), _vp(self.ws_bwd), self.ws_bwd.numel(),

@@ -109,6 +109,8 @@ SIGNATURES = {
                                [ctypes.POINTER(P)] * 3 + [PI64, ctypes.POINTER(P), PI64, PI64]),
     "tm_tonemap_backward": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P, I64,
                                            I64, P, PP, P, I64, P, I64, P, P, SZ, P]),
+    "tm_tonemap_backward_log": (ctypes.c_int, [P, I64, I32, I32, P, I64, ctypes.c_int, P, P,
+                                               I64, I64, P, PP, P, I64, P, I64, P, P, SZ, P]),
 }
 
 _LIB = None

@@ -15,16 +15,17 @@ pass synchronises with the host and both can be recorded into a CUDA/HIP graph.
 variance="log": Eq. 10's variance is that of l = ln(max(lum, FLT_MIN)) (the bins still come
 from lum).  The residual backward given lum forms l in its last pass and applies the chain
 rule through the logarithm there (tm_tonemap_backward_resid_log).  With recompute=True the
-backward rebuilds the log plane and the tables and reruns the training query for the
-residual planes.
+backward rebuilds l's integral image (l formed on load, with the offsets the forward kept)
+and lum's histogram, then runs the table-based form (tm_tonemap_backward_log).
 """
 from __future__ import annotations
 
 import torch
 
 from . import (make_params, tm_image_stats, tm_integral_tables, tm_integral_tables_log,
-               tm_log_luminance, tm_tonemap_backward, tm_tonemap_backward_resid,
-               tm_tonemap_backward_resid_log, tm_tonemap_forward, tm_tonemap_forward_train)
+               tm_log_luminance, tm_tonemap_backward, tm_tonemap_backward_log,
+               tm_tonemap_backward_resid, tm_tonemap_backward_resid_log, tm_tonemap_forward,
+               tm_tonemap_forward_train)
 
 __all__ = ["TonemapFn", "tonemap_luminance"]
 
@@ -69,13 +70,14 @@ class TonemapFn(torch.autograd.Function):
         lum, edges, offsets = ctx.saved_tensors
         p, prec, n_bins, sdt, log = ctx.meta
         g = g.contiguous().float()
-        if log:
-            _, loff, sat, hist = _log_tables(lum, prec, edges, n_bins)
-            resid = ctx.resid
-            if resid is None:
-                _, resid = tm_tonemap_forward_train(lum, sat, hist, edges, p, loff)
-            del sat, hist
-            gv, gp = tm_tonemap_backward_resid_log(lum, p, resid, g)
+        if log and ctx.resid is None:
+            # offsets saved by the forward are l's: rebuild l's table (formed on load) and
+            # lum's histogram, then the table-based backward with the chain rule to lum
+            sat, hist = tm_integral_tables_log(lum, prec, offsets, edges, n_bins,
+                                               "cumulative" if n_bins > 1 else None)
+            gv, gp = tm_tonemap_backward_log(lum, sat, hist, edges, p, g, offsets)
+        elif log:
+            gv, gp = tm_tonemap_backward_resid_log(lum, p, ctx.resid, g)
             ctx.resid = None
         elif ctx.resid is None:
             sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")

@@ -743,13 +743,13 @@ tm_status tm_tonemap_backward_resid_log(const float *lum, int64_t ld_lum, int32_
                               grad_params, plan, ws, (hipStream_t)stream, true);
 }
 
-tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W,
-                              const void *sat, int64_t ld_sat, tm_sat_prec prec,
-                              const float *offsets, const uint32_t *hist_cum,
-                              int64_t ld_hist, int64_t plane_stride, const float *edges,
-                              const tm_params *p, const float *grad_out, int64_t ld_g,
-                              float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
-                              size_t ws_bytes, void *stream) {
+static tm_status run_backward_tables(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                                     const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                                     const float *offsets, const uint32_t *hist_cum,
+                                     int64_t ld_hist, int64_t plane_stride, const float *edges,
+                                     const tm_params *p, const float *grad_out, int64_t ld_g,
+                                     float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
+                                     size_t ws_bytes, void *stream, bool log_chain) {
     TM_TRY(check_bwd_common(v, ld_v, H, W, p, grad_out, ld_g, grad_v, ld_gv, grad_params));
     if (!valid_prec(prec)) return TM_ERR_ARG;
     TM_TRY(check_table(H, W, ld_sat, sat));
@@ -769,7 +769,31 @@ tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W
                                            W, resid, s));
     if (st != TM_OK) return st;
     return run_backward_resid(v, ld_v, H, W, p, resid, grad_out, ld_g, grad_v, ld_gv,
-                              grad_params, plan, ws, s);
+                              grad_params, plan, ws, s, log_chain);
+}
+
+tm_status tm_tonemap_backward(const float *v, int64_t ld_v, int32_t H, int32_t W,
+                              const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                              const float *offsets, const uint32_t *hist_cum,
+                              int64_t ld_hist, int64_t plane_stride, const float *edges,
+                              const tm_params *p, const float *grad_out, int64_t ld_g,
+                              float *grad_v, int64_t ld_gv, double *grad_params, void *ws,
+                              size_t ws_bytes, void *stream) {
+    return run_backward_tables(v, ld_v, H, W, sat, ld_sat, prec, offsets, hist_cum, ld_hist,
+                               plane_stride, edges, p, grad_out, ld_g, grad_v, ld_gv,
+                               grad_params, ws, ws_bytes, stream, false);
+}
+
+tm_status tm_tonemap_backward_log(const float *lum, int64_t ld_lum, int32_t H, int32_t W,
+                                  const void *sat, int64_t ld_sat, tm_sat_prec prec,
+                                  const float *log_offsets, const uint32_t *hist_cum,
+                                  int64_t ld_hist, int64_t plane_stride, const float *edges,
+                                  const tm_params *p, const float *grad_out, int64_t ld_g,
+                                  float *grad_lum, int64_t ld_gl, double *grad_params, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    return run_backward_tables(lum, ld_lum, H, W, sat, ld_sat, prec, log_offsets, hist_cum,
+                               ld_hist, plane_stride, edges, p, grad_out, ld_g, grad_lum, ld_gl,
+                               grad_params, ws, ws_bytes, stream, true);
 }
 
 }  // extern "C"

@@ -123,11 +123,16 @@ def test_log_forward_special_cases():
     b = tm.ToneMapper(H, W, p, "c32x2", variance="log").run(
         to_dev((rgb * np.float32(8.0)).astype(np.float32))).cpu().numpy()
     assert np.max(np.abs(a.astype(np.float64) - b)) <= 1e-5
-    # the table-based backward has no log form (the residual one has)
+    # the table-based backward of the variant equals the residual one bit for bit
     m = tm.ToneMapper(H, W, p, "c32x2", variance="log")
-    m.run(to_dev(rgb))
-    with pytest.raises(ValueError):
-        m.backward(to_dev(np.ones((H, W), dtype=np.float32)))
+    g = to_dev(np.random.default_rng(4).standard_normal((H, W)).astype(np.float32))
+    m.run_train(to_dev(rgb))
+    gr, pr = (t.clone() for t in m.backward_resid(g))
+    gt, pt = (t.clone() for t in m.backward(g))
+    gf, pf = tm.tm_tonemap_backward_log(m.lum, m.sat, m.hist, m.edges, p, g, m.log_offsets)
+    torch.cuda.synchronize()
+    assert torch.equal(gt, gr) and torch.equal(pt, pr)
+    assert torch.equal(gf, gr) and torch.equal(pf, pr)
 
 
 def test_log_variance_maps_and_colour():
