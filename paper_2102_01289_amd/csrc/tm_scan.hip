@@ -951,7 +951,8 @@ __device__ __forceinline__ void stage3_tile(const ScanK &k, const int tile, int 
                             // staged so that each store covers 64 consecutive outputs
                             float *sv = reinterpret_cast<float *>(sh_adj + wave_id() * (kWave * VEC));
 #pragma unroll
-                            for (int i = 0; i < VEC; ++i) sv[lane * VEC + i] = adj_grad(k, cur.v[i], c1[i], c2[i]);
+                            for (int i = 0; i < VEC; ++i)
+                                sv[lane * VEC + i] = adj_grad(k, cur.v[i], c1[i], c2[i]);
                             wave_lds_sync();
 #pragma unroll
                             for (int i = 0; i < VEC; ++i)
