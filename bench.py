@@ -49,8 +49,8 @@ def _parse():
     ap.add_argument("--kernel-only", choices=["query", "tables", "backward"], default=None,
                     help="launch only that stage in the timed loop (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="leave out the batch and stress-set blocks of the default line "
-                         "(profiling runs)")
+                    help="leave out the batch, stress-set and log-variance blocks of the "
+                         "default line (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed loop, copy 1 GiB device-to-device once (a plain copy "
                          "kernel of known size, for calibrating HBM counters) and report its "
@@ -427,6 +427,41 @@ def bench_scan(args):
               f"{res['lookback']:.1f} us", file=sys.stderr, flush=True)
     print(json.dumps({"metric": "integral histogram build, three-stage vs single-pass look-back",
                       "unit": "us", "n_bins": n, "steps": args.steps, "rows": rows}), flush=True)
+
+
+def log_variance_extra(args, rgb, g, H, W):
+    """The log-domain variance variant's forward+backward step on the headline image, for
+    the default line: same parameters, steps timed as the headline's."""
+    import torch
+
+    import paper_2102_01289_amd as tm
+
+    p = tm.make_params(args.n_bins, args.n_scales, eps=args.eps, H=H, W=W)
+    m = tm.ToneMapper(H, W, p, args.prec, device=rgb.device, variance="log")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        m.run_train(rgb)
+        m.backward_resid(g)
+
+    def fwd():
+        m.run(rgb)
+
+    out = {}
+    for name, fn in (("fwd_bwd", step), ("fwd", fwd)):
+        for _ in range(args.warmup):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        out[name + "_ms"] = round(a.elapsed_time(b) / args.steps, 4)
+    mpx = H * W / 1e6
+    out["fwd_bwd_mp_s"] = round(mpx / (out["fwd_bwd_ms"] * 1e-3), 3)
+    out["fwd_mp_s"] = round(mpx / (out["fwd_ms"] * 1e-3), 3)
+    return out
 
 
 def bench_logvar(args):
@@ -839,7 +874,8 @@ def main():
             and not args.copy_probe):
         # the secondary workloads, so that every run of the default line records them
         for key, fn in (("batch", lambda: batch_extra(args)),
-                        ("stress", lambda: stress_line(args))):
+                        ("stress", lambda: stress_line(args)),
+                        ("log_variance", lambda: log_variance_extra(args, rgb, g, H, W))):
             try:
                 line[key] = fn()
             except Exception as e:   # a secondary block never loses the headline line
