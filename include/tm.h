@@ -552,9 +552,10 @@ tm_status tm_batch_set_concurrency(tm_batch *batch, int32_t streams, int32_t ima
  * log-domain variant (of l = ln max(i, FLT_MIN), as tm_prologue_log and
  * tm_integral_tables_log form it; the bins stay those of i).  Each image's output then equals
  * ToneMapper-style single-image calls of that variant bit for bit.  The device descriptor
- * table is updated by a copy enqueued on stream (order any forward on another stream after
- * it).  A graph captured before is released: call tm_batch_capture again before replaying.
- * Host call; not capturable itself. */
+ * table is updated by a copy on stream, and the call waits for the stream (so for the work
+ * queued on it before); order any forward on another stream after it.  A graph captured
+ * before is released: call tm_batch_capture again before replaying.  Host call; not
+ * capturable itself. */
 tm_status tm_batch_set_variance(tm_batch *batch, int32_t log_domain, void *stream);
 
 /* Record tm_batch_forward into a HIP graph (stream must not be the null stream; nothing is

@@ -375,9 +375,11 @@ tm_status tm_batch_set_variance(tm_batch *b, int32_t log_domain, void *stream) {
     if (!b || (log_domain != 0 && log_domain != 1)) return TM_ERR_ARG;
     b->log = log_domain != 0;
     for (ScanK &k : b->ck) k.log_src = log_domain;
-    // the scan descriptors on the device follow (the host vector outlives the copy)
+    // the scan descriptors on the device follow; the copy has completed when the call
+    // returns, so a later call may change the host table without racing it
     if (hipMemcpyAsync(b->d_ck, b->ck.data(), sizeof(ScanK) * b->count, hipMemcpyHostToDevice,
-                       (hipStream_t)stream) != hipSuccess)
+                       (hipStream_t)stream) != hipSuccess ||
+        hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
         return TM_ERR_HIP;
     // a graph captured before holds the other variant's prologue: it must be captured again
     if (b->exec) hipGraphExecDestroy(b->exec);

@@ -187,3 +187,13 @@ def test_batch_log_variance_equals_per_image(prec, t):
     back = [o.clone() for o in b.forward()]
     torch.cuda.synchronize()
     assert all(torch.equal(a, c) for a, c in zip(lin, back))
+    # switches and forwards queued back to back, no synchronisation in between: each
+    # forward runs with the variant set before it
+    got = []
+    for v in ("log", "linear", "log", "log", "linear"):
+        b.set_variance(v)
+        got.append((v, [o.clone() for o in b.forward()]))
+    torch.cuda.synchronize()
+    for v, o in got:
+        want = outs if v == "log" else lin
+        assert all(torch.equal(x, y) for x, y in zip(o, want)), v
