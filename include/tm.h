@@ -186,7 +186,8 @@ tm_status tm_prologue_noalloc(const float *rgb, int64_t ch_stride, int64_t ld_rg
  * its square (Eq. 5) for Eq. 10's window variance; the method is also defined with that
  * variance taken of the logarithmic image l the bins are cut from.  This call writes
  *   logv = ln(max(i, FLT_MIN))   (FP32, the device logf, within 2 ulp of the exact value)
- * (H x W, pitch ld_log; must not overlap lum) and, in the same pass, the statistics of l:
+ * (H x W, pitch ld_log; must not overlap lum; NULL: no plane, the statistics only) and, in
+ * the same pass, the statistics of l:
  * offsets[2] (device, nullable) = FP32-rounded means of l and l^2 (FP64 sums), the offsets a
  * TM_SAT_C32X2 integral image of l needs, and minmax[2] (device, nullable) = {min l, max l}.
  * The variant is then: tm_integral_image of logv with these offsets, the integral histogram

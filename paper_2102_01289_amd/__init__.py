@@ -202,12 +202,13 @@ def tm_image_stats(lum: torch.Tensor, n_bins: int, stream=None):
 
 
 def tm_log_luminance(lum: torch.Tensor, stream=None, out=None, offsets=None, minmax=None,
-                     ws=None):
+                     ws=None, write_plane: bool = True):
     """Log image l = ln(max(lum, FLT_MIN)) and its statistics: (l [H, W], offsets [2] =
-    FP32 means of l and l^2, minmax [2])."""
+    FP32 means of l and l^2, minmax [2]); l is None when write_plane is False (the
+    statistics only)."""
     H, W, ld = _img(lum, "lum")
     dev = lum.device
-    if out is None:
+    if out is None and write_plane:
         out = torch.empty((H, W), dtype=torch.float32, device=dev)
     if offsets is None:
         offsets = torch.empty(2, dtype=torch.float32, device=dev)
@@ -215,7 +216,7 @@ def tm_log_luminance(lum: torch.Tensor, stream=None, out=None, offsets=None, min
         minmax = torch.empty(2, dtype=torch.float32, device=dev)
     if ws is None:
         ws = _ws(_lib().tm_image_stats_workspace_bytes(H, W), dev)
-    _, _, ldo = _img(out, "out")
+    ldo = _img(out, "out")[2] if out is not None else 0
     _ck("tm_log_luminance", _lib().tm_log_luminance(
         _vp(lum), ld, H, W, _vp(out), ldo, _vp(offsets), _vp(minmax), _vp(ws), ws.numel(),
         _stream(stream)))

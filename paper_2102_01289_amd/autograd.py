@@ -31,12 +31,12 @@ __all__ = ["TonemapFn", "tonemap_luminance"]
 
 
 def _log_tables(lum, prec, edges, n_bins):
-    """The log-domain variant's tables: integral image of l = ln(max(lum, FLT_MIN)) with its
-    offsets, integral histogram of lum.  (l, loff, sat, hist)."""
-    l, loff, _ = tm_log_luminance(lum)
+    """The log-domain variant's tables: integral image of l = ln(max(lum, FLT_MIN)) (formed
+    on load) with l's offsets, integral histogram of lum.  (loff, sat, hist)."""
+    _, loff, _ = tm_log_luminance(lum, write_plane=False)   # the offsets; no plane needed
     sat, hist = tm_integral_tables_log(lum, prec, loff, edges, n_bins,
                                        "cumulative" if n_bins > 1 else None)
-    return l, loff, sat, hist
+    return loff, sat, hist
 
 
 class TonemapFn(torch.autograd.Function):
@@ -51,7 +51,7 @@ class TonemapFn(torch.autograd.Function):
         edges, offsets, _ = tm_image_stats(lum, n_bins)
         log = variance == "log"
         if log:
-            _, offsets, sat, hist = _log_tables(lum, prec, edges, n_bins)
+            offsets, sat, hist = _log_tables(lum, prec, edges, n_bins)
         else:
             sat, hist = tm_integral_tables(lum, prec, offsets, edges, n_bins, "cumulative")
         if recompute:

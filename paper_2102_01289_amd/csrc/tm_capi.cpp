@@ -250,9 +250,9 @@ tm_status tm_log_luminance(const float *lum, int64_t ld_lum, int32_t H, int32_t 
                            int64_t ld_log, float *offsets, float *minmax, void *ws,
                            size_t ws_bytes, void *stream) {
     TM_TRY(check_image(H, W));
-    if (!lum || !logv) return TM_ERR_ARG;
+    if (!lum) return TM_ERR_ARG;
     TM_TRY(check_plane(H, W, ld_lum));
-    TM_TRY(check_plane(H, W, ld_log));
+    if (logv) TM_TRY(check_plane(H, W, ld_log));
     TM_TRY(check_ws(ws, ws_bytes, tm_image_stats_workspace_bytes(H, W)));
     return from_hip(launch_log_stats(lum, ld_lum, logv, ld_log, H, W, offsets, minmax,
                                      static_cast<StatsPartial *>(ws), (hipStream_t)stream));

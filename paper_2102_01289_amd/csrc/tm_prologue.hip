@@ -139,12 +139,14 @@ __device__ void stats_part(const StatsK &k, int part, int nparts) {
             }
             if (LOG) {
                 for (int i = 0; i < 4; ++i) v[i] = logf(fmaxf(v[i], FLT_MIN));
-                float *o = k.lum_out + (int64_t)y * k.ld_out + x;
-                if (full && k.vec_out) {
-                    *reinterpret_cast<float4 *>(o) = make_float4(v[0], v[1], v[2], v[3]);
-                } else {
-                    for (int i = 0; i < 4; ++i)
-                        if (x + i < W) o[i] = v[i];
+                if (k.lum_out) {   // the plane is optional: the statistics are always formed
+                    float *o = k.lum_out + (int64_t)y * k.ld_out + x;
+                    if (full && k.vec_out) {
+                        *reinterpret_cast<float4 *>(o) = make_float4(v[0], v[1], v[2], v[3]);
+                    } else {
+                        for (int i = 0; i < 4; ++i)
+                            if (x + i < W) o[i] = v[i];
+                    }
                 }
             }
         }

@@ -188,7 +188,7 @@ def test_log_and_exposure_entry_argument_checks():
     P = ctypes.c_void_p
     fake, null = P(1 << 20), P(0)
     # log-luminance: null output, pitch too small, workspace missing
-    assert lib.tm_log_luminance(fake, 10, 10, 10, null, 10, null, null, fake, 1 << 20, null) == -1
+    assert lib.tm_log_luminance(null, 10, 10, 10, fake, 10, null, null, fake, 1 << 20, null) == -1
     assert lib.tm_log_luminance(fake, 10, 10, 10, fake, 9, null, null, fake, 1 << 20, null) == -2
     assert lib.tm_log_luminance(fake, 10, 10, 10, fake, 10, null, null, null, 0, null) == -4
     # exposure stacks: P out of range, overlapping channel/exposure strides

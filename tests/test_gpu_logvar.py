@@ -46,6 +46,10 @@ def test_log_luminance_plane_and_offsets(H, W):
     want = np.float32([got.mean(), (got * got).mean()])
     assert np.allclose(off.cpu().numpy(), want, rtol=2e-7, atol=1e-7)
     assert mm.cpu().numpy().tolist() == [float(got.min()), float(got.max())]
+    # without the plane: the same statistics, bit for bit
+    none, off2, mm2 = tm.tm_log_luminance(to_dev(lum), write_plane=False)
+    torch.cuda.synchronize()
+    assert none is None and torch.equal(off2, off) and torch.equal(mm2, mm)
 
 
 def _check_log_forward(rgb, n, rx, ry, eps, prec, ld=(0.0, 1.0)):
