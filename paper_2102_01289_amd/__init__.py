@@ -821,11 +821,13 @@ class ToneMapper:
 
 
 def tonemap(rgb: torch.Tensor, n_bins: int = 5, n_scales: int = 5, eps: float = 0.1,
-            prec: str = "c32x2", ld_min: float = 0.0, ld_max: float = 1.0) -> torch.Tensor:
-    """Tone-mapped luminance of one planar RGB image with the paper's parameter set."""
+            prec: str = "c32x2", ld_min: float = 0.0, ld_max: float = 1.0,
+            variance: str = "linear") -> torch.Tensor:
+    """Tone-mapped luminance of one planar RGB image with the paper's parameter set
+    (variance "linear", or "log" for the log-domain variance variant)."""
     _, H, W = rgb.shape
     p = make_params(n_bins, n_scales, eps=eps, ld_min=ld_min, ld_max=ld_max, H=H, W=W)
-    return ToneMapper(H, W, p, prec, device=rgb.device).run(rgb).clone()
+    return ToneMapper(H, W, p, prec, device=rgb.device, variance=variance).run(rgb).clone()
 
 
 # ------------------------------------------------------------------------ batches

@@ -323,6 +323,16 @@ def test_log_prologue_with_pitched_planes(pad_lum, pad_log):
     assert torch.equal(e2, edges) and torch.equal(o2, loff) and torch.equal(m2, mm)
 
 
+def test_tonemap_convenience_takes_the_variance():
+    rgb = to_dev(rgb_case(40, 70, 5, -3.0, 5.0, seed=3))
+    p = tm.make_params(5, 5, eps=0.1, H=40, W=70)
+    want = tm.ToneMapper(40, 70, p, "c32x2", variance="log").run(rgb).clone()
+    got = tm.tonemap(rgb, variance="log")
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    assert not torch.equal(got, tm.tonemap(rgb))
+
+
 def test_log_chain_rule_kernel():
     # grad_i = grad_l / i (one correctly rounded FP32 division) above the floor, 0 below;
     # in place too
