@@ -525,12 +525,22 @@ def tm_tonemap_forward_rgb(v, sat: Table, hist: Table | None, edges, params, rgb
 
 def tonemap_rgb(rgb: torch.Tensor, n_bins: int = 5, n_scales: int = 5, eps: float = 0.1,
                 prec: str = "c32x2", saturation: float = 0.6, ld_min: float = 0.0,
-                ld_max: float = 1.0, rgb_out=None, stream=None) -> torch.Tensor:
+                ld_max: float = 1.0, rgb_out=None, stream=None,
+                variance: str = "linear") -> torch.Tensor:
     """The whole path RGB -> RGB on one planar image (tm_tonemap_rgb): Eq. 11 luminance and
-    bin edges, integral tables, fused query with colour restoration (Eq. 12)."""
+    bin edges, integral tables, fused query with colour restoration (Eq. 12).  variance="log":
+    the log-domain variance variant, through ToneMapper's log prologue, tables and query."""
     _check_rgb(rgb)
     _, H, W = rgb.shape
     p = make_params(n_bins, n_scales, eps=eps, ld_min=ld_min, ld_max=ld_max, H=H, W=W)
+    if variance != "linear":
+        m = ToneMapper(H, W, p, prec, device=rgb.device, variance=variance)
+        out = m.run_rgb(rgb, saturation, stream)
+        if rgb_out is None:
+            return out
+        _check_rgb(rgb_out, H, W)
+        rgb_out.copy_(out)
+        return rgb_out
     if rgb_out is None:
         rgb_out = torch.empty((3, H, W), dtype=torch.float32, device=rgb.device)
     _check_rgb(rgb_out, H, W)

@@ -331,6 +331,11 @@ def test_tonemap_convenience_takes_the_variance():
     torch.cuda.synchronize()
     assert torch.equal(got, want)
     assert not torch.equal(got, tm.tonemap(rgb))
+    rgb_log = tm.tonemap_rgb(rgb, variance="log")
+    want_rgb = tm.ToneMapper(40, 70, p, "c32x2", variance="log").run_rgb(rgb)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb_log, want_rgb)
+    assert not torch.equal(rgb_log, tm.tonemap_rgb(rgb))
 
 
 def test_log_chain_rule_kernel():
